@@ -1,0 +1,212 @@
+/*
+ * gr.h -- C ABI of a frontier-driven single-source shortest path (SSSP)
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the paper's parallel native-graph SSSP (Osama, Porumbescu,
+ * Owens, "Essentials of Parallel Graph Analytics", Section IV-D, Listing 4):
+ * starting from dist = INF, dist[src] = 0 and the frontier {src}, repeat
+ *   advance  -- relax every out-edge (u -> v, w) of the active frontier:
+ *               new = dist[u] (+) w; old = atomic-min(dist[v], new);
+ *               v joins the next frontier iff new < old (Listing 3/4),
+ *   filter   -- deduplicate and compact the next frontier,
+ *   converge -- stop when the frontier is empty (Section III, item 4),
+ * over a graph stored as a CSR matrix (Section IV-A, Listing 1), with a
+ * transposed (CSC) copy for pull traversal (Section III-C).
+ *
+ * The result is unique and independent of schedule: for every vertex v,
+ *   dist[v] = min over paths src = v0 -> ... -> vk = v of the left fold
+ *             ((0 (+) w1) (+) w2) ... (+) wk,
+ * dist[src] = 0, and INF when no path exists (or when every fold reaches INF).
+ * (+) is uint32 addition saturating at GR_DIST_INF_U32, or IEEE-754 binary32
+ * addition rounded to nearest-even.  Distances are therefore bit-exact for
+ * both weight types whatever the traversal order.
+ *
+ * Conventions shared by every call
+ *  - Every call returns gr_status; argument errors are detected on the host
+ *    before anything is enqueued, and the text of the last error of the
+ *    calling thread is available from gr_last_error().
+ *  - "stream" is a hipStream_t (NULL = the null stream), passed as void* so
+ *    that this header needs no HIP headers.
+ *  - Graph ids, vertex ids, offsets and edge counts are int32: n < 2^31 and
+ *    m < 2^31 (the paper's csr_t uses int).
+ *  - Distances are 32-bit: uint32 values, or binary32 bit patterns.  INF is
+ *    GR_DIST_INF_U32, or FLT_MAX (GR_DIST_INF_F32_BITS), the initial value of
+ *    Listing 4.
+ */
+#ifndef GR_H_
+#define GR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GR_OK = 0,
+    GR_ERR_INVALID_ARG = 1,   /* malformed CSR, bad weight, bad pointer/size/flag */
+    GR_ERR_SOURCE_RANGE = 2,  /* a source id outside [0, n) */
+    GR_ERR_OUT_OF_MEMORY = 3, /* device or pinned host allocation failed */
+    GR_ERR_NO_CAPACITY = 4,   /* a query can never fit the server's memory budget */
+    GR_ERR_NOT_READY = 5,     /* a served query has not completed yet */
+    GR_ERR_ITER_LIMIT = 6,    /* the iteration cap was reached (a bug for w >= 0) */
+    GR_ERR_HIP = 7,           /* a HIP runtime call failed; see gr_last_error() */
+    GR_ERR_UNKNOWN_TICKET = 8 /* poll of a ticket the server never issued */
+} gr_status;
+
+typedef enum { GR_W_U32 = 0, GR_W_F32 = 1 } gr_weight_type;
+
+#define GR_DIST_INF_U32 0xFFFFFFFFu
+#define GR_DIST_INF_F32_BITS 0x7F7FFFFFu
+
+/* gr_graph_create_csr flags */
+#define GR_INPUT_DEVICE 0x1u /* the three arrays are device pointers */
+#define GR_NO_PULL 0x2u      /* never build the transposed copy: push traversal only */
+
+typedef struct gr_graph gr_graph;
+typedef struct gr_server gr_server;
+
+/*
+ * Builds a device-resident graph from a CSR matrix (Section IV-A, Listing 1:
+ * row_offsets, column_indices, values; rows = cols = n).
+ *   n            number of vertices, 1 <= n < 2^31
+ *   m            number of arcs, 0 <= m < 2^31
+ *   row_offsets  int32[n+1], row_offsets[0] = 0, non-decreasing, [n] = m
+ *   col_indices  int32[m], each in [0, n); arc u -> col_indices[e] for
+ *                e in [row_offsets[u], row_offsets[u+1])
+ *   weights      m values of type wt: uint32 (any value), or binary32 that
+ *                must be finite and >= 0 (-0.0 is stored as +0.0)
+ *   flags        GR_INPUT_DEVICE, GR_NO_PULL
+ *   stream       stream for the upload and preprocessing
+ * Self-loops and parallel arcs are accepted.  The arrays are copied; the
+ * caller keeps ownership.  Host arrays are validated on the host; device
+ * arrays (GR_INPUT_DEVICE) are validated by a device pass.  Unless
+ * GR_NO_PULL is given, a transposed copy (CSC) is built for pull traversal,
+ * and dropped again when the arcs and weights turn out to be symmetric (the
+ * CSR then serves both directions).  Returns GR_ERR_INVALID_ARG for a
+ * malformed matrix.  The call returns after the graph is ready.
+ */
+gr_status gr_graph_create_csr(gr_graph **out, int32_t n, int32_t m, const int32_t *row_offsets,
+                              const int32_t *col_indices, const void *weights, gr_weight_type wt,
+                              uint32_t flags, void *stream);
+
+/* Frees the graph's device memory.  No query on it may still be running. */
+gr_status gr_graph_destroy(gr_graph *g);
+
+/* Any output pointer may be NULL.  has_csc: 1 when a separate transposed copy
+ * is stored, 0 when the CSR serves pull too (symmetric) or pull is off. */
+gr_status gr_graph_info(const gr_graph *g, int32_t *n, int32_t *m, int32_t *wt, size_t *dev_bytes,
+                        int32_t *has_csc, int32_t *pull_enabled);
+
+/*
+ * Single-source shortest paths from src (Section IV-D, Listing 4).
+ *   dist_out  device memory for n 32-bit values of the graph's weight type;
+ *             it is used as the working distance array, so it must not alias
+ *             anything else in use.  Contents on return: the unique result.
+ * Work is ordered on `stream`.  Depending on the loop schedule the call may
+ * wait for the stream while it runs (host-driven loop) or return after
+ * enqueueing (device-driven loop); the result is complete once the stream
+ * has been synchronised.  Concurrent calls on the same graph are allowed on
+ * different streams.  GR_ERR_SOURCE_RANGE if src is outside [0, n).
+ */
+gr_status gr_sssp(const gr_graph *g, int32_t src, void *dist_out, void *stream);
+
+/* Loop schedule of gr_sssp_ex (Section III-A: execution policies). */
+typedef enum {
+    GR_LOOP_AUTO = 0,       /* the library's choice (tuned per graph) */
+    GR_LOOP_HOST = 1,       /* one launch per operator, host reads the frontier size */
+    GR_LOOP_PERSISTENT = 2  /* one cooperative launch, device-side grid barrier */
+} gr_loop_mode;
+
+/* Traversal direction policy (Section III-C: push vs pull). */
+typedef enum {
+    GR_DIR_AUTO = 0,      /* switch on frontier work (alpha rule) */
+    GR_DIR_PUSH = 1,      /* push every iteration */
+    GR_DIR_PULL = 2,      /* pull every iteration (needs pull enabled) */
+    GR_DIR_ALTERNATE = 3  /* push and pull alternately (a test of switching) */
+} gr_direction;
+
+typedef struct {
+    int32_t loop;       /* gr_loop_mode */
+    int32_t direction;  /* gr_direction */
+    int32_t alpha_x16;  /* pull when frontier out-edges * alpha_x16 >= 16 * m; 0 = default */
+    int32_t max_iters;  /* iteration cap; 0 = n + 1 (never reached for w >= 0) */
+    int32_t reserved[4];
+} gr_sssp_opts;
+
+typedef struct {
+    int32_t iterations;      /* advance/filter rounds executed */
+    int32_t pull_iterations; /* of which pull */
+    int64_t edges_pushed;    /* out-edges expanded by push (relaxations) */
+    int64_t arcs_pulled;     /* in-arcs scanned by pull */
+    int64_t frontier_sum;    /* sum of frontier sizes over the rounds */
+    int32_t frontier_max;
+    int32_t loop;            /* the gr_loop_mode that ran */
+} gr_sssp_stats;
+
+/* gr_sssp with an explicit schedule; opts and stats may be NULL.  stats are
+ * filled when the call returns for the host-driven loop, and after the stream
+ * has been synchronised for the device-driven loop. */
+gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, void *stream, const gr_sssp_opts *opts,
+                     gr_sssp_stats *stats);
+
+/*
+ * k independent SSSP queries on one graph in one batched launch.
+ *   srcs      host int32[k], each in [0, n); duplicates allowed
+ *   k         1 <= k <= 64
+ *   dist_out  device memory, k x n row-major: row i holds the result of srcs[i]
+ * Row i is bit-identical to gr_sssp(g, srcs[i], ...).  Ordered on `stream`;
+ * complete after stream synchronisation.
+ */
+gr_status gr_sssp_batch(const gr_graph *g, const int32_t *srcs, int32_t k, void *dist_out, void *stream);
+
+/* ---- serving ----------------------------------------------------------- */
+
+typedef struct {
+    int32_t max_batch;      /* queries per batched launch, 1..64 (0 = 64) */
+    int32_t num_streams;    /* concurrent batches on the device, 1..8 (0 = 2) */
+    int32_t max_wait_us;    /* how long a partial batch may wait for company (0 = 200) */
+    int32_t reserved[5];
+} gr_server_config;
+
+typedef struct {
+    int32_t status;      /* GR_OK, or the query's error */
+    int32_t graph_id;
+    int32_t src;
+    int32_t batch_size;  /* queries that shared its launch */
+    int64_t t_submit_ns; /* CLOCK_MONOTONIC times */
+    int64_t t_start_ns;
+    int64_t t_done_ns;
+} gr_query_result;
+
+/* A query server: resident graphs, admission by device-memory footprint,
+ * batching of queries that arrive while others run.  hbm_budget_bytes bounds
+ * the device workspace of queries in flight.  cfg may be NULL. */
+gr_status gr_server_create(gr_server **out, size_t hbm_budget_bytes, const gr_server_config *cfg);
+/* Registers a graph (not copied; it must outlive the server). */
+gr_status gr_server_add_graph(gr_server *s, const gr_graph *g, int32_t *graph_id);
+/* Queues one query; never blocks on the GPU.  dist_out: device memory for n
+ * values, written when the ticket completes.  GR_ERR_NO_CAPACITY when the
+ * query's footprint exceeds the whole budget. */
+gr_status gr_serve_submit(gr_server *s, int32_t graph_id, int32_t src, void *dist_out, uint64_t *ticket);
+/* GR_OK and *out filled once the query has completed (the ticket is then
+ * retired), GR_ERR_NOT_READY before, GR_ERR_UNKNOWN_TICKET for a ticket never
+ * issued or already retired. */
+gr_status gr_serve_poll(gr_server *s, uint64_t ticket, gr_query_result *out);
+/* Waits for every queued and running query, then frees the server. */
+gr_status gr_server_destroy(gr_server *s);
+
+/* ---- diagnostics ------------------------------------------------------- */
+
+const char *gr_status_string(gr_status s);
+/* Text of the calling thread's last error ("" if none). */
+const char *gr_last_error(void);
+/* Library version string. */
+const char *gr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GR_H_ */

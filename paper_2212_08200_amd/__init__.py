@@ -1,0 +1,312 @@
+"""Python binding of the gr C ABI (``include/gr.h``): frontier-driven SSSP on MI355X.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libgr.so``.  Importing succeeds without the library (so that CPU-only
+tooling can inspect the package), but every call raises ``GrLibraryMissing``
+until ``paper_2212_08200_amd.build.build()`` has produced it -- there is no
+CPU fallback.
+
+The functions carry the C names (``gr_graph_create_csr``, ``gr_sssp``,
+``gr_sssp_ex``, ``gr_sssp_batch``, ``gr_server_create``, ``gr_server_add_graph``,
+``gr_serve_submit``, ``gr_serve_poll``, ``gr_server_destroy``, ...).  Device
+buffers may be given as torch tensors (their ``data_ptr()``) or raw integer
+addresses; streams as ``torch.cuda.Stream``, raw ``hipStream_t`` integers, or
+``None`` for torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgr.so")
+
+GR_OK = 0
+GR_ERR_INVALID_ARG = 1
+GR_ERR_SOURCE_RANGE = 2
+GR_ERR_OUT_OF_MEMORY = 3
+GR_ERR_NO_CAPACITY = 4
+GR_ERR_NOT_READY = 5
+GR_ERR_ITER_LIMIT = 6
+GR_ERR_HIP = 7
+GR_ERR_UNKNOWN_TICKET = 8
+
+GR_W_U32 = 0
+GR_W_F32 = 1
+GR_DIST_INF_U32 = 0xFFFFFFFF
+GR_DIST_INF_F32_BITS = 0x7F7FFFFF
+
+GR_INPUT_DEVICE = 0x1
+GR_NO_PULL = 0x2
+
+GR_LOOP_AUTO = 0
+GR_LOOP_HOST = 1
+GR_LOOP_PERSISTENT = 2
+
+GR_DIR_AUTO = 0
+GR_DIR_PUSH = 1
+GR_DIR_PULL = 2
+GR_DIR_ALTERNATE = 3
+
+EXPORTED = [
+    "gr_graph_create_csr", "gr_graph_destroy", "gr_graph_info", "gr_sssp", "gr_sssp_ex", "gr_sssp_batch",
+    "gr_server_create", "gr_server_add_graph", "gr_serve_submit", "gr_serve_poll", "gr_server_destroy",
+    "gr_status_string", "gr_last_error", "gr_version",
+]
+
+
+class GrLibraryMissing(RuntimeError):
+    pass
+
+
+class GrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_status_name(status), message))
+        self.status = status
+        self.message = message
+
+
+class gr_sssp_opts(ctypes.Structure):
+    _fields_ = [("loop", ctypes.c_int32), ("direction", ctypes.c_int32), ("alpha_x16", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class gr_sssp_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("pull_iterations", ctypes.c_int32),
+                ("edges_pushed", ctypes.c_int64), ("arcs_pulled", ctypes.c_int64),
+                ("frontier_sum", ctypes.c_int64), ("frontier_max", ctypes.c_int32), ("loop", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class gr_server_config(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("num_streams", ctypes.c_int32), ("max_wait_us", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class gr_query_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("graph_id", ctypes.c_int32), ("src", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32), ("t_submit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """The loaded ``libgr.so`` (raises ``GrLibraryMissing`` if it was never built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise GrLibraryMissing("libgr.so is not built (run paper_2212_08200_amd.build.build())")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+            P = ctypes.POINTER
+            sigs = {
+                "gr_graph_create_csr": [P(vp), i32, i32, vp, vp, vp, ctypes.c_int, u32, vp],
+                "gr_graph_destroy": [vp],
+                "gr_graph_info": [vp, P(i32), P(i32), P(i32), P(ctypes.c_size_t), P(i32), P(i32)],
+                "gr_sssp": [vp, i32, vp, vp],
+                "gr_sssp_ex": [vp, i32, vp, vp, P(gr_sssp_opts), P(gr_sssp_stats)],
+                "gr_sssp_batch": [vp, vp, i32, vp, vp],
+                "gr_server_create": [P(vp), ctypes.c_size_t, P(gr_server_config)],
+                "gr_server_add_graph": [vp, vp, P(i32)],
+                "gr_serve_submit": [vp, i32, i32, vp, P(ctypes.c_uint64)],
+                "gr_serve_poll": [vp, ctypes.c_uint64, P(gr_query_result)],
+                "gr_server_destroy": [vp],
+            }
+            for name, args in sigs.items():
+                if hasattr(L, name):
+                    f = getattr(L, name)
+                    f.argtypes = args
+                    f.restype = ctypes.c_int
+            L.gr_status_string.argtypes = [ctypes.c_int]
+            L.gr_status_string.restype = ctypes.c_char_p
+            L.gr_last_error.restype = ctypes.c_char_p
+            L.gr_version.restype = ctypes.c_char_p
+            _lib = L
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().gr_status_string(s).decode()
+    except GrLibraryMissing:
+        return "GR_STATUS_%d" % s
+
+
+def _check(status: int, allow=(GR_OK,)) -> int:
+    if status not in allow:
+        raise GrError(status, lib().gr_last_error().decode())
+    return status
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return int(x.ctypes.data)
+    raise TypeError("cannot take the address of %r" % type(x))
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return int(torch.cuda.current_stream().cuda_stream) or None
+        except ImportError:
+            pass
+        return None
+    if isinstance(s, int):
+        return s or None
+    return int(s.cuda_stream) or None
+
+
+# ---- graph ------------------------------------------------------------------
+
+def gr_graph_create_csr(n, m, row_offsets, col_indices, weights, wt, flags=0, stream=None) -> int:
+    """Returns a graph handle (int).  Host arrays are numpy arrays (int32, int32,
+    uint32/float32); device arrays need ``flags |= GR_INPUT_DEVICE``."""
+    keep = []
+    if not (flags & GR_INPUT_DEVICE):
+        ro = np.ascontiguousarray(row_offsets, dtype=np.int32)
+        col = np.ascontiguousarray(col_indices, dtype=np.int32)
+        w = np.ascontiguousarray(weights)
+        if w.dtype == np.float32:
+            w = w.view(np.uint32)
+        w = np.ascontiguousarray(w, dtype=np.uint32)
+        keep = [ro, col, w]
+        a_ro, a_col, a_w = ro.ctypes.data, (col.ctypes.data if col.size else None), (w.ctypes.data if w.size else None)
+    else:
+        a_ro, a_col, a_w = _ptr(row_offsets), _ptr(col_indices), _ptr(weights)
+    h = ctypes.c_void_p()
+    _check(lib().gr_graph_create_csr(ctypes.byref(h), int(n), int(m), a_ro, a_col, a_w, int(wt), int(flags),
+                                     _stream(stream)))
+    del keep
+    return h.value
+
+
+def gr_graph_destroy(g: int) -> None:
+    _check(lib().gr_graph_destroy(g))
+
+
+def gr_graph_info(g: int) -> dict:
+    n, m, wt, hc, pe = (ctypes.c_int32() for _ in range(5))
+    db = ctypes.c_size_t()
+    _check(lib().gr_graph_info(g, ctypes.byref(n), ctypes.byref(m), ctypes.byref(wt), ctypes.byref(db),
+                               ctypes.byref(hc), ctypes.byref(pe)))
+    return dict(n=n.value, m=m.value, wt=wt.value, dev_bytes=db.value, has_csc=bool(hc.value),
+                pull_enabled=bool(pe.value))
+
+
+# ---- queries ----------------------------------------------------------------
+
+def gr_sssp(g: int, src: int, dist_out, stream=None) -> None:
+    _check(lib().gr_sssp(g, int(src), _ptr(dist_out), _stream(stream)))
+
+
+def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
+               max_iters=0) -> dict:
+    o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters)
+    st = gr_sssp_stats()
+    _check(lib().gr_sssp_ex(g, int(src), _ptr(dist_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def gr_sssp_batch(g: int, srcs, dist_out, stream=None) -> None:
+    s = np.ascontiguousarray(srcs, dtype=np.int32)
+    _check(lib().gr_sssp_batch(g, s.ctypes.data if s.size else None, int(s.size), _ptr(dist_out), _stream(stream)))
+
+
+# ---- serving ----------------------------------------------------------------
+
+def gr_server_create(hbm_budget_bytes: int, max_batch=0, num_streams=0, max_wait_us=0) -> int:
+    cfg = gr_server_config(max_batch=max_batch, num_streams=num_streams, max_wait_us=max_wait_us)
+    h = ctypes.c_void_p()
+    _check(lib().gr_server_create(ctypes.byref(h), int(hbm_budget_bytes), ctypes.byref(cfg)))
+    return h.value
+
+
+def gr_server_add_graph(server: int, g: int) -> int:
+    gid = ctypes.c_int32()
+    _check(lib().gr_server_add_graph(server, g, ctypes.byref(gid)))
+    return gid.value
+
+
+def gr_serve_submit(server: int, graph_id: int, src: int, dist_out) -> int:
+    t = ctypes.c_uint64()
+    _check(lib().gr_serve_submit(server, int(graph_id), int(src), _ptr(dist_out), ctypes.byref(t)))
+    return t.value
+
+
+def gr_serve_poll(server: int, ticket: int):
+    """Returns the result dict once done, or None while the query is pending."""
+    r = gr_query_result()
+    s = _check(lib().gr_serve_poll(server, int(ticket), ctypes.byref(r)), allow=(GR_OK, GR_ERR_NOT_READY))
+    return r.as_dict() if s == GR_OK else None
+
+
+def gr_server_destroy(server: int) -> None:
+    _check(lib().gr_server_destroy(server))
+
+
+def gr_status_string(s: int) -> str:
+    return lib().gr_status_string(int(s)).decode()
+
+
+def gr_last_error() -> str:
+    return lib().gr_last_error().decode()
+
+
+def gr_version() -> str:
+    return lib().gr_version().decode()
+
+
+# ---- convenience --------------------------------------------------------------
+
+class Graph:
+    """Owning wrapper around a graph handle."""
+
+    def __init__(self, n, row_offsets, col_indices, weights, wt, flags=0, stream=None):
+        m = int(np.asarray(col_indices).shape[0]) if not (flags & GR_INPUT_DEVICE) else int(col_indices.numel())
+        self.handle = gr_graph_create_csr(n, m, row_offsets, col_indices, weights, wt, flags, stream)
+        self.n, self.m, self.wt = int(n), m, int(wt)
+
+    @classmethod
+    def from_csr(cls, csr, flags=0, stream=None):
+        """From any object with n, ro, col, w (uint32 bits) and wtype attributes."""
+        return cls(csr.n, csr.ro, csr.col, csr.w, csr.wtype, flags, stream)
+
+    def info(self):
+        return gr_graph_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            gr_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,192 @@
+"""GPU parity: distances from the HIP path through the C ABI equal the CPU
+oracle bit for bit (tolerance 0, for uint32 and binary32 weights alike --
+the shortest-path vector is unique, see ``include/gr.h``), for every traversal
+schedule, on the benchmark configurations and on edge cases.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+gr = pytest.importorskip("paper_2212_08200_amd")
+
+DIRS = {"push": 1, "auto": 0, "pull": 2, "alternate": 3}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run(G, src, direction=0, loop=0, n=None):
+    dist = torch.full((n or G.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+    st = gr.gr_sssp_ex(G.handle, int(src), dist, direction=direction, loop=loop)
+    torch.cuda.synchronize()
+    return dist.cpu().numpy().view(np.uint32), st
+
+
+def assert_same(got, want, tag):
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        v = int(bad[0])
+        raise AssertionError("%s: %d mismatches, first vertex %d got 0x%08x want 0x%08x" % (
+            tag, len(bad), v, int(got[v]), int(want[v])))
+
+
+def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate")):
+    G = gr.Graph.from_csr(g)
+    info = G.info()
+    try:
+        for s in srcs:
+            want = oracle.dijkstra(g, int(s))
+            for d in dirs:
+                if d in ("pull", "alternate") and not info["pull_enabled"]:
+                    continue
+                say("case %s src=%d dir=%s n=%d m=%d" % (tag, s, d, g.n, g.m))
+                got, st = run(G, s, DIRS[d])
+                assert_same(got, want, "%s src %d dir %s" % (tag, s, d))
+    finally:
+        G.close()
+
+
+# ------------------------------------------------------------------ small cases
+
+def test_grid64_config():
+    g, srcs = gg.workload("grid64")
+    check_all_dirs(g, [int(srcs[0]), 4095, 2080], "grid64")
+
+
+@pytest.mark.parametrize("wtype", [gg.W_U32, gg.W_F32])
+def test_rmat12_both_types(wtype):
+    g = gg.rmat(12, 16, gseed=61, pseed=62, wseed=63, wtype=wtype)
+    srcs = gg.pick_sources(g, 64, 3)
+    check_all_dirs(g, srcs, "rmat12_w%d" % wtype)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_uniform_directed_with_zero_weights(seed):
+    g = gg.uniform(5000, 30000, gseed=seed, wseed=seed + 10, wtype=gg.W_U32, wlo=0, whi=3)
+    check_all_dirs(g, [0, 17, 4999], "uniform%d" % seed)
+
+
+def test_uniform_directed_f32():
+    g = gg.uniform(3000, 20000, gseed=5, wseed=6, wtype=gg.W_F32)
+    check_all_dirs(g, [0, 1234], "uniform_f32")
+
+
+def test_road_like_small():
+    g = gg.grid(200, wseed=71, wtype=gg.W_U32, wlo=1, whi=1000, shortcuts=40, sseed=72)
+    check_all_dirs(g, [0, 199 * 200 + 199], "road200")
+
+
+def test_edge_cases():
+    cases = [
+        ("single_vertex", gg.from_arcs(1, []), 0),
+        ("isolated_source", gg.from_arcs(4, [(1, 2, 3), (2, 3, 4)]), 0),
+        ("two_components", gg.from_arcs(6, [(0, 1, 2), (1, 2, 2), (3, 4, 1), (4, 5, 1)]), 0),
+        ("self_loops_parallel_zero", gg.from_arcs(4, [(0, 0, 0), (0, 1, 9), (0, 1, 4), (1, 1, 3), (1, 2, 0),
+                                                       (2, 0, 0), (2, 3, 0), (3, 2, 5)]), 3),
+        ("u32_saturation", gg.from_arcs(4, [(0, 1, 0xFFFFFFFF - 5), (1, 2, 3), (2, 3, 7)]), 0),
+        ("f32_rounding", gg.from_arcs(4, [(0, 1, 1.0), (1, 2, 2.0 ** -24), (2, 3, 2.0 ** -24), (0, 3, 1.0 + 2.0 ** -23)],
+                                      wtype=gg.W_F32), 0),
+        ("f32_overflow", gg.from_arcs(3, [(0, 1, 3.0e38), (1, 2, 3.0e38)], wtype=gg.W_F32), 0),
+        ("f32_negzero", gg.from_arcs(3, [(0, 1, -0.0), (1, 2, 0.5)], wtype=gg.W_F32), 0),
+        ("star_hub", gg.from_arcs(70001, [(0, i, i % 97 + 1) for i in range(1, 70001)]), 0),
+    ]
+    for name, g, s in cases:
+        check_all_dirs(g, [s], name)
+
+
+def test_ragged_group_boundaries():
+    # n just above multiples of the 4096-vertex bitmap group and the 256-vertex pull block
+    for n in (4097, 8191, 257):
+        g = gg.uniform(n, 6 * n, gseed=n, wseed=n + 1, wtype=gg.W_U32, wlo=1, whi=9)
+        check_all_dirs(g, [0, n - 1], "ragged%d" % n)
+
+
+def test_repeat_determinism():
+    g = gg.rmat(13, 16, gseed=81, pseed=82, wseed=83, wtype=gg.W_F32)
+    s = int(gg.pick_sources(g, 84, 1)[0])
+    want = oracle.dijkstra(g, s)
+    G = gr.Graph.from_csr(g)
+    try:
+        for i in range(10):
+            got, _ = run(G, s, DIRS["auto"])
+            assert_same(got, want, "repeat %d" % i)
+    finally:
+        G.close()
+
+
+def test_device_input_graph():
+    g = gg.rmat(11, 16, gseed=91, pseed=92, wseed=93, wtype=gg.W_U32)
+    ro = torch.from_numpy(g.ro.copy()).cuda()
+    col = torch.from_numpy(g.col.copy()).cuda()
+    w = torch.from_numpy(g.w.view(np.int32).copy()).cuda()
+    h = gr.gr_graph_create_csr(g.n, g.m, ro, col, w, g.wtype, gr.GR_INPUT_DEVICE)
+    try:
+        s = int(gg.pick_sources(g, 94, 1)[0])
+        dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        gr.gr_sssp(h, s, dist)
+        torch.cuda.synchronize()
+        assert_same(dist.cpu().numpy().view(np.uint32), oracle.dijkstra(g, s), "device input")
+    finally:
+        gr.gr_graph_destroy(h)
+    bad = torch.from_numpy(np.array([0, 1, 5], np.int32)).cuda()
+    with pytest.raises(gr.GrError) as ei:
+        gr.gr_graph_create_csr(2, 2, bad, col[:2], w[:2], 0, gr.GR_INPUT_DEVICE)
+    assert ei.value.status == gr.GR_ERR_INVALID_ARG
+
+
+def test_errors_on_gpu():
+    g = gg.grid(8, wseed=1)
+    G = gr.Graph.from_csr(g)
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    try:
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp(G.handle, g.n, dist)
+        assert ei.value.status == gr.GR_ERR_SOURCE_RANGE
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_ex(G.handle, 0, dist, max_iters=3)
+        assert ei.value.status == gr.GR_ERR_ITER_LIMIT
+    finally:
+        G.close()
+    Gp = gr.Graph.from_csr(g, flags=gr.GR_NO_PULL)
+    try:
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_ex(Gp.handle, 0, dist, direction=gr.GR_DIR_PULL)
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
+    finally:
+        Gp.close()
+
+
+def test_symmetry_detection():
+    sym = gg.rmat(10, 8, gseed=1, pseed=2, wseed=3)
+    G = gr.Graph.from_csr(sym)
+    assert G.info()["has_csc"] is False and G.info()["pull_enabled"]
+    G.close()
+    asym = gg.grid(16, wseed=4)  # one weight per directed arc: not symmetric
+    G = gr.Graph.from_csr(asym)
+    assert G.info()["has_csc"] is True
+    G.close()
+
+
+# ------------------------------------------------------------- benchmark configs
+
+def test_rmat20_config_f32():
+    g, srcs = gg.workload("rmat20")
+    check_all_dirs(g, srcs, "rmat20", dirs=("auto", "push", "pull"))
+
+
+def test_road2048_config():
+    g, srcs = gg.workload("road2048")
+    check_all_dirs(g, srcs, "road2048", dirs=("auto",))
+
+
+def test_rmat22_config_sampled_sources():
+    g, srcs = gg.workload("rmat22")
+    check_all_dirs(g, srcs[:2], "rmat22", dirs=("auto", "push"))
