@@ -61,8 +61,11 @@ typedef enum { GR_W_U32 = 0, GR_W_F32 = 1 } gr_weight_type;
 #define GR_DIST_INF_F32_BITS 0x7F7FFFFFu
 
 /* gr_graph_create_csr flags */
-#define GR_INPUT_DEVICE 0x1u /* the three arrays are device pointers */
-#define GR_NO_PULL 0x2u      /* never build the transposed copy: push traversal only */
+#define GR_INPUT_DEVICE 0x1u     /* the three arrays are device pointers */
+#define GR_NO_PULL 0x2u          /* never build the transposed copy: push traversal only */
+#define GR_NO_PARTITION 0x4u     /* never build the partitioned push layout */
+#define GR_FORCE_PARTITION 0x8u  /* always build it (default: only for large graphs whose
+                                    arcs mostly join distant vertex ids) */
 
 typedef struct gr_graph gr_graph;
 typedef struct gr_server gr_server;
@@ -77,7 +80,7 @@ typedef struct gr_server gr_server;
  *                e in [row_offsets[u], row_offsets[u+1])
  *   weights      m values of type wt: uint32 (any value), or binary32 that
  *                must be finite and >= 0 (-0.0 is stored as +0.0)
- *   flags        GR_INPUT_DEVICE, GR_NO_PULL
+ *   flags        GR_INPUT_DEVICE, GR_NO_PULL, GR_NO_PARTITION, GR_FORCE_PARTITION
  *   stream       stream for the upload and preprocessing
  * Self-loops and parallel arcs are accepted.  The arrays are copied; the
  * caller keeps ownership.  Host arrays are validated on the host; device
@@ -85,7 +88,11 @@ typedef struct gr_server gr_server;
  * GR_NO_PULL is given, a transposed copy (CSC) is built for pull traversal,
  * and dropped again when the arcs and weights turn out to be symmetric (the
  * CSR then serves both directions).  Returns GR_ERR_INVALID_ARG for a
- * malformed matrix.  The call returns after the graph is ready.
+ * malformed matrix.  A second, partitioned copy of the arcs may be built for
+ * push traversal: arcs grouped by destination into 8 vertex ranges, so that
+ * the blocks working on one range touch one eighth of the distance array
+ * (see GR_NO_PARTITION / GR_FORCE_PARTITION).  The call returns after the
+ * graph is ready.
  */
 gr_status gr_graph_create_csr(gr_graph **out, int32_t n, int32_t m, const int32_t *row_offsets,
                               const int32_t *col_indices, const void *weights, gr_weight_type wt,
@@ -95,9 +102,10 @@ gr_status gr_graph_create_csr(gr_graph **out, int32_t n, int32_t m, const int32_
 gr_status gr_graph_destroy(gr_graph *g);
 
 /* Any output pointer may be NULL.  has_csc: 1 when a separate transposed copy
- * is stored, 0 when the CSR serves pull too (symmetric) or pull is off. */
+ * is stored, 0 when the CSR serves pull too (symmetric) or pull is off.
+ * partitions: 8 when the partitioned push layout exists, else 1. */
 gr_status gr_graph_info(const gr_graph *g, int32_t *n, int32_t *m, int32_t *wt, size_t *dev_bytes,
-                        int32_t *has_csc, int32_t *pull_enabled);
+                        int32_t *has_csc, int32_t *pull_enabled, int32_t *partitions);
 
 /*
  * Single-source shortest paths from src (Section IV-D, Listing 4).
@@ -127,22 +135,37 @@ typedef enum {
     GR_DIR_ALTERNATE = 3  /* push and pull alternately (a test of switching) */
 } gr_direction;
 
+/* Arc layout used by push (see gr_graph_create_csr). */
+typedef enum {
+    GR_LAYOUT_AUTO = 0,        /* partitioned when the graph has it */
+    GR_LAYOUT_PLAIN = 1,       /* the CSR as given */
+    GR_LAYOUT_PARTITIONED = 2  /* needs the partitioned layout */
+} gr_layout;
+
 typedef struct {
     int32_t loop;       /* gr_loop_mode */
     int32_t direction;  /* gr_direction */
     int32_t alpha_x16;  /* pull when frontier out-edges * alpha_x16 >= 16 * m; 0 = default */
     int32_t max_iters;  /* iteration cap; 0 = n + 1 (never reached for w >= 0) */
-    int32_t reserved[4];
+    int32_t layout;     /* gr_layout */
+    int32_t timing;     /* 1: time every operator launch with HIP events (stats *_us fields) */
+    int32_t reserved[2];
 } gr_sssp_opts;
 
 typedef struct {
-    int32_t iterations;      /* advance/filter rounds executed */
-    int32_t pull_iterations; /* of which pull */
-    int64_t edges_pushed;    /* out-edges expanded by push (relaxations) */
-    int64_t arcs_pulled;     /* in-arcs scanned by pull */
-    int64_t frontier_sum;    /* sum of frontier sizes over the rounds */
+    int32_t iterations;        /* advance/filter rounds executed */
+    int32_t pull_iterations;   /* of which pull */
+    int64_t edges_pushed;      /* out-edges expanded by push (relaxations) */
+    int64_t arcs_pulled;       /* in-arcs scanned by pull */
+    int64_t frontier_sum;      /* sum of frontier sizes over the rounds */
+    int64_t push_frontier_sum; /* of which in push rounds */
     int32_t frontier_max;
-    int32_t loop;            /* the gr_loop_mode that ran */
+    int32_t loop;              /* the gr_loop_mode that ran */
+    int32_t push_launches;
+    int32_t layout;            /* the gr_layout that ran */
+    double push_us;            /* with opts.timing: summed push / pull / filter launch times */
+    double pull_us;
+    double filter_us;
 } gr_sssp_stats;
 
 /* gr_sssp with an explicit schedule; opts and stats may be NULL.  stats are

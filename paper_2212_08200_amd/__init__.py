@@ -41,6 +41,12 @@ GR_DIST_INF_F32_BITS = 0x7F7FFFFF
 
 GR_INPUT_DEVICE = 0x1
 GR_NO_PULL = 0x2
+GR_NO_PARTITION = 0x4
+GR_FORCE_PARTITION = 0x8
+
+GR_LAYOUT_AUTO = 0
+GR_LAYOUT_PLAIN = 1
+GR_LAYOUT_PARTITIONED = 2
 
 GR_LOOP_AUTO = 0
 GR_LOOP_HOST = 1
@@ -71,13 +77,17 @@ class GrError(RuntimeError):
 
 class gr_sssp_opts(ctypes.Structure):
     _fields_ = [("loop", ctypes.c_int32), ("direction", ctypes.c_int32), ("alpha_x16", ctypes.c_int32),
-                ("max_iters", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("max_iters", ctypes.c_int32), ("layout", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class gr_sssp_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("pull_iterations", ctypes.c_int32),
                 ("edges_pushed", ctypes.c_int64), ("arcs_pulled", ctypes.c_int64),
-                ("frontier_sum", ctypes.c_int64), ("frontier_max", ctypes.c_int32), ("loop", ctypes.c_int32)]
+                ("frontier_sum", ctypes.c_int64), ("push_frontier_sum", ctypes.c_int64),
+                ("frontier_max", ctypes.c_int32), ("loop", ctypes.c_int32), ("push_launches", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("push_us", ctypes.c_double), ("pull_us", ctypes.c_double),
+                ("filter_us", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -114,7 +124,7 @@ def lib():
             sigs = {
                 "gr_graph_create_csr": [P(vp), i32, i32, vp, vp, vp, ctypes.c_int, u32, vp],
                 "gr_graph_destroy": [vp],
-                "gr_graph_info": [vp, P(i32), P(i32), P(i32), P(ctypes.c_size_t), P(i32), P(i32)],
+                "gr_graph_info": [vp, P(i32), P(i32), P(i32), P(ctypes.c_size_t), P(i32), P(i32), P(i32)],
                 "gr_sssp": [vp, i32, vp, vp],
                 "gr_sssp_ex": [vp, i32, vp, vp, P(gr_sssp_opts), P(gr_sssp_stats)],
                 "gr_sssp_batch": [vp, vp, i32, vp, vp],
@@ -205,12 +215,12 @@ def gr_graph_destroy(g: int) -> None:
 
 
 def gr_graph_info(g: int) -> dict:
-    n, m, wt, hc, pe = (ctypes.c_int32() for _ in range(5))
+    n, m, wt, hc, pe, pa = (ctypes.c_int32() for _ in range(6))
     db = ctypes.c_size_t()
     _check(lib().gr_graph_info(g, ctypes.byref(n), ctypes.byref(m), ctypes.byref(wt), ctypes.byref(db),
-                               ctypes.byref(hc), ctypes.byref(pe)))
+                               ctypes.byref(hc), ctypes.byref(pe), ctypes.byref(pa)))
     return dict(n=n.value, m=m.value, wt=wt.value, dev_bytes=db.value, has_csc=bool(hc.value),
-                pull_enabled=bool(pe.value))
+                pull_enabled=bool(pe.value), partitions=pa.value)
 
 
 # ---- queries ----------------------------------------------------------------
@@ -220,8 +230,9 @@ def gr_sssp(g: int, src: int, dist_out, stream=None) -> None:
 
 
 def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
-               max_iters=0) -> dict:
-    o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters)
+               max_iters=0, layout=GR_LAYOUT_AUTO, timing=0) -> dict:
+    o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
+                     timing=timing)
     st = gr_sssp_stats()
     _check(lib().gr_sssp_ex(g, int(src), _ptr(dist_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()

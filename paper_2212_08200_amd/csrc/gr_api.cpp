@@ -6,21 +6,22 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <thread>
+#include <unordered_map>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "gr_internal.h"
-
-namespace gr {
-hipError_t launch_canon_negzero(uint2 *adj, int32_t m, hipStream_t st);
-size_t scan_tmp_ints(int64_t len);
-}  // namespace gr
+#include "gr_sched.h"
 
 using namespace gr;
 
@@ -115,18 +116,31 @@ static unsigned long long *pinned_slot() {
 // ---------------------------------------------------------------------------
 // graph
 
+// Partitioned push layout is built by default when the graph is large enough
+// for the distance array to outgrow one XCD's L2 and most arcs join distant
+// vertex ids (so that the plain layout would scatter dist accesses).
+static constexpr int32_t kPartitionMinN = 1 << 17;
+// An arc is "near" when |u - v| < n / 64: true for nearly all arcs of grids and
+// meshes, and for about 3% of the arcs of a graph with random vertex ids.
+static inline int32_t locality_span(int32_t n) { return std::max(n / 64, 64); }
+
 struct gr_graph {
     int device = 0;
-    DevGraph dg{};
+    DevGraph plain{};  // np = 1: push over the CSR as given
+    DevGraph part{};   // np = 8: partitioned push layout (when built)
+    bool has_part = false;
     int32_t *d_ro = nullptr;
     uint2 *d_adj = nullptr;
     int32_t *d_ro_in = nullptr;  // == d_ro when symmetric
     uint2 *d_adj_in = nullptr;   // == d_adj when symmetric
+    int32_t *d_pro = nullptr;
+    uint2 *d_padj = nullptr;
     bool pull = false;
     bool csc_separate = false;
     size_t dev_bytes = 0;
     std::vector<int32_t> h_ro;
     int32_t max_degree = 0;
+    double locality = 1.0;  // fraction of arcs with |u - v| < locality_span(n)
 };
 
 static gr_status validate_host(int32_t n, int32_t m, const int32_t *ro, const int32_t *col, const uint32_t *w,
@@ -156,113 +170,160 @@ static void graph_free(gr_graph *g) {
     if (g->d_adj_in && g->d_adj_in != g->d_adj) (void)hipFree(g->d_adj_in);
     if (g->d_ro) (void)hipFree(g->d_ro);
     if (g->d_adj) (void)hipFree(g->d_adj);
+    if (g->d_pro) (void)hipFree(g->d_pro);
+    if (g->d_padj) (void)hipFree(g->d_padj);
     delete g;
+}
+
+// Device scratch freed on every exit path of graph_build.
+struct Scratch {
+    std::vector<void *> ptrs;
+    ~Scratch() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    hipError_t alloc(T **p, size_t bytes) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+        if (e == hipSuccess) ptrs.push_back(q);
+        *p = static_cast<T *>(q);
+        return e;
+    }
+};
+
+#define BUILD_TRY(call, what)                      \
+    do {                                           \
+        hipError_t _e = (call);                    \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+static gr_status build_partition(gr_graph *g, int32_t n, int32_t m, hipStream_t st, Scratch &sc) {
+    const int np = kMaxParts;
+    int32_t psize = (int32_t)((n + np - 1) / np);
+    if (n >= 64 * np) psize = (psize + 63) & ~63;  // partitions start on bitmap words
+    const int64_t len = (int64_t)np * (n + 1) + 1;
+    int32_t *cnt = nullptr, *pm = nullptr, *tmp = nullptr;
+    unsigned long long *caps = nullptr;
+    BUILD_TRY(hipMalloc(&g->d_pro, sizeof(int32_t) * (size_t)len), "hipMalloc(partition offsets)");
+    BUILD_TRY(hipMalloc(&g->d_padj, sizeof(uint2) * (size_t)std::max(m, 1)), "hipMalloc(partition arcs)");
+    BUILD_TRY(sc.alloc(&cnt, sizeof(int32_t) * (size_t)len), "hipMalloc(partition counts)");
+    BUILD_TRY(sc.alloc(&pm, sizeof(int32_t) * (size_t)len), "hipMalloc(partition offsets)");
+    BUILD_TRY(sc.alloc(&tmp, sizeof(int32_t) * scan_tmp_ints(len)), "hipMalloc(scan)");
+    BUILD_TRY(sc.alloc(&caps, sizeof(unsigned long long) * kMaxParts), "hipMalloc(caps)");
+    BUILD_TRY(hipMemsetAsync(caps, 0, sizeof(unsigned long long) * kMaxParts, st), "memset caps");
+    BUILD_TRY(launch_partition_build(n, m, g->d_ro, g->d_adj, np, psize, g->d_pro, g->d_padj, cnt, pm, tmp, caps, st),
+              "partition build");
+    unsigned long long hc[kMaxParts];
+    BUILD_TRY(hipMemcpyAsync(hc, caps, sizeof hc, hipMemcpyDeviceToHost, st), "copy caps");
+    BUILD_TRY(hipStreamSynchronize(st), "partition build");
+    DevGraph &d = g->part;
+    d = g->plain;
+    d.np = np;
+    d.psize = psize;
+    d.pro = g->d_pro;
+    d.padj = g->d_padj;
+    for (int k = 0; k < kMaxParts; ++k) d.cap[k] = (int32_t)hc[k];
+    g->has_part = true;
+    g->dev_bytes += sizeof(int32_t) * (size_t)len + sizeof(uint2) * (size_t)std::max(m, 1);
+    return GR_OK;
 }
 
 static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *ro, const int32_t *col,
                              const void *weights, gr_weight_type wt, uint32_t flags, hipStream_t st) {
     const bool dev_in = flags & GR_INPUT_DEVICE;
-    HIP_TRY(hipGetDevice(&g->device));
-    HIP_TRY(hipMalloc(&g->d_ro, sizeof(int32_t) * ((size_t)n + 1)));
-    HIP_TRY(hipMalloc(&g->d_adj, sizeof(uint2) * (size_t)std::max(m, 1)));
+    Scratch sc;
+    BUILD_TRY(hipGetDevice(&g->device), "hipGetDevice");
+    BUILD_TRY(hipMalloc(&g->d_ro, sizeof(int32_t) * ((size_t)n + 1)), "hipMalloc(row_offsets)");
+    BUILD_TRY(hipMalloc(&g->d_adj, sizeof(uint2) * (size_t)std::max(m, 1)), "hipMalloc(arcs)");
     g->dev_bytes = sizeof(int32_t) * ((size_t)n + 1) + sizeof(uint2) * (size_t)std::max(m, 1);
     int32_t *tcol = nullptr;
     uint32_t *tw = nullptr;
     unsigned int *flag = nullptr;
-    auto cleanup = [&]() {
-        if (tcol) (void)hipFree(tcol);
-        if (tw) (void)hipFree(tw);
-        if (flag) (void)hipFree(flag);
-    };
-    hipError_t e;
+    unsigned long long *near = nullptr;
     const hipMemcpyKind kind = dev_in ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    if ((e = hipMalloc(&flag, 64)) != hipSuccess) { cleanup(); return hip_fail(e, "hipMalloc(flag)"); }
-    if ((e = hipMalloc(&tcol, sizeof(int32_t) * (size_t)std::max(m, 1))) != hipSuccess ||
-        (e = hipMalloc(&tw, sizeof(uint32_t) * (size_t)std::max(m, 1))) != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "hipMalloc(staging)");
+    BUILD_TRY(sc.alloc(&flag, 64), "hipMalloc(flag)");
+    BUILD_TRY(sc.alloc(&near, 64), "hipMalloc(flag)");
+    BUILD_TRY(sc.alloc(&tcol, sizeof(int32_t) * (size_t)std::max(m, 1)), "hipMalloc(staging)");
+    BUILD_TRY(sc.alloc(&tw, sizeof(uint32_t) * (size_t)std::max(m, 1)), "hipMalloc(staging)");
+    BUILD_TRY(hipMemcpyAsync(g->d_ro, ro, sizeof(int32_t) * ((size_t)n + 1), kind, st), "upload row_offsets");
+    if (m > 0) {
+        BUILD_TRY(hipMemcpyAsync(tcol, col, sizeof(int32_t) * (size_t)m, kind, st), "upload col_indices");
+        BUILD_TRY(hipMemcpyAsync(tw, weights, sizeof(uint32_t) * (size_t)m, kind, st), "upload weights");
     }
-    if ((e = hipMemcpyAsync(g->d_ro, ro, sizeof(int32_t) * ((size_t)n + 1), kind, st)) != hipSuccess ||
-        (m > 0 && (e = hipMemcpyAsync(tcol, col, sizeof(int32_t) * (size_t)m, kind, st)) != hipSuccess) ||
-        (m > 0 && (e = hipMemcpyAsync(tw, weights, sizeof(uint32_t) * (size_t)m, kind, st)) != hipSuccess) ||
-        (e = hipMemsetAsync(flag, 0, 64, st)) != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "upload");
-    }
+    BUILD_TRY(hipMemsetAsync(flag, 0, 64, st), "memset");
+    BUILD_TRY(hipMemsetAsync(near, 0, 64, st), "memset");
     if (dev_in) {
         unsigned int err = 0;
-        if ((e = launch_validate(n, m, g->d_ro, tcol, tw, (int)wt, flag, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(&err, flag, sizeof err, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-            (e = hipStreamSynchronize(st)) != hipSuccess) {
-            cleanup();
-            return hip_fail(e, "validate");
-        }
-        if (err) {
-            cleanup();
+        BUILD_TRY(launch_validate(n, m, g->d_ro, tcol, tw, (int)wt, flag, st), "validate");
+        BUILD_TRY(hipMemcpyAsync(&err, flag, sizeof err, hipMemcpyDeviceToHost, st), "validate");
+        BUILD_TRY(hipStreamSynchronize(st), "validate");
+        if (err)
             return fail(GR_ERR_INVALID_ARG, "device CSR is malformed (%s%s%s)", (err & 1) ? "row_offsets " : "",
                         (err & 2) ? "col_indices " : "", (err & 4) ? "weights" : "");
-        }
         g->h_ro.resize((size_t)n + 1);
-        if ((e = hipMemcpy(g->h_ro.data(), g->d_ro, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost)) !=
-            hipSuccess) {
-            cleanup();
-            return hip_fail(e, "copy row_offsets");
-        }
+        BUILD_TRY(hipMemcpy(g->h_ro.data(), g->d_ro, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost),
+                  "copy row_offsets");
     } else {
         g->h_ro.assign(ro, ro + (size_t)n + 1);
     }
-    if ((e = launch_pack_arcs(tcol, tw, m, g->d_adj, st)) != hipSuccess ||
-        (wt == GR_W_F32 && (e = launch_canon_negzero(g->d_adj, m, st)) != hipSuccess)) {
-        cleanup();
-        return hip_fail(e, "pack arcs");
+    BUILD_TRY(launch_pack_arcs(tcol, tw, m, g->d_adj, st), "pack arcs");
+    if (wt == GR_W_F32) BUILD_TRY(launch_canon_negzero(g->d_adj, m, st), "canonicalise -0");
+    int32_t nonempty = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t d = g->h_ro[v + 1] - g->h_ro[v];
+        g->max_degree = std::max(g->max_degree, d);
+        nonempty += d > 0;
     }
-    for (int32_t v = 0; v < n; ++v) g->max_degree = std::max(g->max_degree, g->h_ro[v + 1] - g->h_ro[v]);
+    BUILD_TRY(launch_locality(n, g->d_ro, g->d_adj, locality_span(n), near, st), "locality");
+    unsigned long long hnear = 0;
+    BUILD_TRY(hipMemcpyAsync(&hnear, near, sizeof hnear, hipMemcpyDeviceToHost, st), "locality");
 
     g->d_ro_in = g->d_ro;
     g->d_adj_in = g->d_adj;
     if (!(flags & GR_NO_PULL)) {
         unsigned int not_sym = 0;
-        if ((e = hipMemsetAsync(flag, 0, 64, st)) != hipSuccess ||
-            (e = launch_symmetry_check(n, g->d_ro, g->d_adj, flag, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(&not_sym, flag, sizeof not_sym, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-            (e = hipStreamSynchronize(st)) != hipSuccess) {
-            cleanup();
-            return hip_fail(e, "symmetry check");
-        }
+        BUILD_TRY(hipMemsetAsync(flag, 0, 64, st), "memset");
+        BUILD_TRY(launch_symmetry_check(n, g->d_ro, g->d_adj, flag, st), "symmetry check");
+        BUILD_TRY(hipMemcpyAsync(&not_sym, flag, sizeof not_sym, hipMemcpyDeviceToHost, st), "symmetry check");
+        BUILD_TRY(hipStreamSynchronize(st), "symmetry check");
         if (not_sym) {
             int32_t *scratch = nullptr;
-            const size_t sc = (2 * (size_t)n + 1) + scan_tmp_ints((int64_t)n + 1);
-            if ((e = hipMalloc(&g->d_ro_in, sizeof(int32_t) * ((size_t)n + 1))) != hipSuccess ||
-                (e = hipMalloc(&g->d_adj_in, sizeof(uint2) * (size_t)std::max(m, 1))) != hipSuccess ||
-                (e = hipMalloc(&scratch, sizeof(int32_t) * sc)) != hipSuccess) {
-                if (scratch) (void)hipFree(scratch);
-                cleanup();
-                return hip_fail(e, "hipMalloc(csc)");
-            }
-            e = launch_csc_build(n, m, g->d_ro, g->d_adj, g->d_ro_in, g->d_adj_in, scratch, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            (void)hipFree(scratch);
-            if (e != hipSuccess) {
-                cleanup();
-                return hip_fail(e, "csc build");
-            }
+            const size_t nsc = (2 * (size_t)n + 1) + scan_tmp_ints((int64_t)n + 1);
+            g->d_ro_in = nullptr;
+            g->d_adj_in = nullptr;
+            BUILD_TRY(hipMalloc(&g->d_ro_in, sizeof(int32_t) * ((size_t)n + 1)), "hipMalloc(csc)");
+            BUILD_TRY(hipMalloc(&g->d_adj_in, sizeof(uint2) * (size_t)std::max(m, 1)), "hipMalloc(csc)");
+            BUILD_TRY(sc.alloc(&scratch, sizeof(int32_t) * nsc), "hipMalloc(csc scratch)");
+            BUILD_TRY(launch_csc_build(n, m, g->d_ro, g->d_adj, g->d_ro_in, g->d_adj_in, scratch, st), "csc build");
             g->csc_separate = true;
             g->dev_bytes += sizeof(int32_t) * ((size_t)n + 1) + sizeof(uint2) * (size_t)std::max(m, 1);
         }
         g->pull = true;
     }
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "graph upload");
+    BUILD_TRY(hipStreamSynchronize(st), "graph upload");
+    g->locality = m > 0 ? (double)hnear / (double)m : 1.0;
+
+    DevGraph &d = g->plain;
+    d.n = n;
+    d.m = m;
+    d.wt = (int32_t)wt;
+    d.ro = g->d_ro;
+    d.adj = g->d_adj;
+    d.ro_in = g->d_ro_in;
+    d.adj_in = g->d_adj_in;
+    d.np = 1;
+    d.psize = n;
+    d.pro = g->d_ro;
+    d.padj = g->d_adj;
+    for (int k = 0; k < kMaxParts; ++k) d.cap[k] = 0;
+    d.cap[0] = nonempty;
+
+    const bool want_part = !(flags & GR_NO_PARTITION) &&
+                           ((flags & GR_FORCE_PARTITION) || (n >= kPartitionMinN && g->locality < 0.5));
+    if (want_part) {
+        gr_status s = build_partition(g, n, m, st, sc);
+        if (s != GR_OK) return s;
     }
-    cleanup();
-    g->dg.n = n;
-    g->dg.m = m;
-    g->dg.wt = (int32_t)wt;
-    g->dg.ro = g->d_ro;
-    g->dg.adj = g->d_adj;
-    g->dg.ro_in = g->d_ro_in;
-    g->dg.adj_in = g->d_adj_in;
     return GR_OK;
 }
 
@@ -274,7 +335,10 @@ extern "C" gr_status gr_graph_create_csr(gr_graph **out, int32_t n, int32_t m, c
     if (n < 1) return fail(GR_ERR_INVALID_ARG, "n = %d, expected >= 1", n);
     if (m < 0 || m == INT32_MAX) return fail(GR_ERR_INVALID_ARG, "m = %d outside [0, 2^31 - 1)", m);
     if (wt != GR_W_U32 && wt != GR_W_F32) return fail(GR_ERR_INVALID_ARG, "unknown weight type %d", (int)wt);
-    if (flags & ~(GR_INPUT_DEVICE | GR_NO_PULL)) return fail(GR_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const uint32_t known = GR_INPUT_DEVICE | GR_NO_PULL | GR_NO_PARTITION | GR_FORCE_PARTITION;
+    if (flags & ~known) return fail(GR_ERR_INVALID_ARG, "unknown flags 0x%x", flags & ~known);
+    if ((flags & GR_NO_PARTITION) && (flags & GR_FORCE_PARTITION))
+        return fail(GR_ERR_INVALID_ARG, "GR_NO_PARTITION and GR_FORCE_PARTITION are exclusive");
     if (!row_offsets || (m > 0 && (!col_indices || !weights)))
         return fail(GR_ERR_INVALID_ARG, "NULL array for n = %d, m = %d", n, m);
     if (!(flags & GR_INPUT_DEVICE)) {
@@ -300,14 +364,15 @@ extern "C" gr_status gr_graph_destroy(gr_graph *g) {
 }
 
 extern "C" gr_status gr_graph_info(const gr_graph *g, int32_t *n, int32_t *m, int32_t *wt, size_t *dev_bytes,
-                                   int32_t *has_csc, int32_t *pull_enabled) {
+                                   int32_t *has_csc, int32_t *pull_enabled, int32_t *partitions) {
     if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
-    if (n) *n = g->dg.n;
-    if (m) *m = g->dg.m;
-    if (wt) *wt = g->dg.wt;
+    if (n) *n = g->plain.n;
+    if (m) *m = g->plain.m;
+    if (wt) *wt = g->plain.wt;
     if (dev_bytes) *dev_bytes = g->dev_bytes;
     if (has_csc) *has_csc = g->csc_separate ? 1 : 0;
     if (pull_enabled) *pull_enabled = g->pull ? 1 : 0;
+    if (partitions) *partitions = g->has_part ? kMaxParts : 1;
     return GR_OK;
 }
 
@@ -321,30 +386,47 @@ struct RunCfg {
     int direction;
     int32_t alpha_x16;
     int64_t max_iters;
+    bool timing;
+    int layout;
+    const DevGraph *dg;
 };
 
 static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc) {
     rc->loop = o ? o->loop : GR_LOOP_AUTO;
     rc->direction = o ? o->direction : GR_DIR_AUTO;
     rc->alpha_x16 = (o && o->alpha_x16 > 0) ? o->alpha_x16 : kDefaultAlphaX16;
-    rc->max_iters = (o && o->max_iters > 0) ? o->max_iters : (int64_t)g->dg.n + 1;
+    rc->max_iters = (o && o->max_iters > 0) ? o->max_iters : (int64_t)g->plain.n + 1;
+    const int layout = o ? o->layout : GR_LAYOUT_AUTO;
     if (rc->loop < GR_LOOP_AUTO || rc->loop > GR_LOOP_PERSISTENT)
         return fail(GR_ERR_INVALID_ARG, "unknown loop mode %d", rc->loop);
     if (rc->direction < GR_DIR_AUTO || rc->direction > GR_DIR_ALTERNATE)
         return fail(GR_ERR_INVALID_ARG, "unknown direction %d", rc->direction);
     if ((rc->direction == GR_DIR_PULL || rc->direction == GR_DIR_ALTERNATE) && !g->pull)
         return fail(GR_ERR_INVALID_ARG, "pull traversal requested but the graph was built with GR_NO_PULL");
+    if (layout < GR_LAYOUT_AUTO || layout > GR_LAYOUT_PARTITIONED)
+        return fail(GR_ERR_INVALID_ARG, "unknown layout %d", layout);
+    if (layout == GR_LAYOUT_PARTITIONED && !g->has_part)
+        return fail(GR_ERR_INVALID_ARG, "partitioned layout requested but the graph has none");
+    rc->dg = (layout == GR_LAYOUT_PLAIN || !g->has_part) ? &g->plain : &g->part;
+    rc->layout = rc->dg->np > 1 ? GR_LAYOUT_PARTITIONED : GR_LAYOUT_PLAIN;
+    rc->timing = o && o->timing;
     return GR_OK;
 }
 
-static bool choose_pull(const gr_graph *g, const RunCfg &rc, int64_t iter, int32_t F, int32_t E) {
-    (void)F;
+static bool choose_pull(const gr_graph *g, const RunCfg &rc, int64_t iter, int64_t E) {
     if (!g->pull) return false;
     switch (rc.direction) {
         case GR_DIR_PUSH: return false;
         case GR_DIR_PULL: return true;
         case GR_DIR_ALTERNATE: return (iter & 1) != 0;
-        default: return (int64_t)E * rc.alpha_x16 >= (int64_t)16 * g->dg.m;
+        default: return E * rc.alpha_x16 >= (int64_t)16 * g->plain.m;
+    }
+}
+
+static void read_counts(const unsigned long long *h, FrontierCounts *c) {
+    for (int k = 0; k < kMaxParts; ++k) {
+        c->F[k] = (int32_t)(h[k] & 0xFFFFFFFFull);
+        c->E[k] = (int32_t)(h[k] >> 32);
     }
 }
 
@@ -355,46 +437,81 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
     if (s != GR_OK) return s;
     unsigned long long *hp = pinned_slot();
     if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
-    const int64_t n = g->dg.n;
+    const DevGraph &dg = *rc.dg;
     void *ws = nullptr;
-    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(n), st));
+    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
     Frontier f;
-    frontier_carve(f, ws, n);
+    frontier_carve(f, ws, dg);
     gr_sssp_stats local{};
     local.loop = GR_LOOP_HOST;
+    local.layout = rc.layout;
     gr_status status = GR_OK;
-    hipError_t e = launch_init(g->dg, dist, src, f, st);
-    const int32_t dsrc = g->h_ro[src + 1] - g->h_ro[src];
-    int32_t F = dsrc > 0 ? 1 : 0, E = dsrc;
-    int parity = 0;
+    // Optional per-launch timing: events around the advance and the filter.
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (rc.timing)
+        for (auto &x : ev)
+            if (hipEventCreate(&x) != hipSuccess) x = nullptr;
+    const bool timed = rc.timing && ev[0] && ev[1] && ev[2];
+    hipError_t e = launch_init(dg, dist, src, f, st);
+    // Frontier 0 = {src}: its counts are known on the host.
+    FrontierCounts c{};
+    {
+        const int64_t stride = (int64_t)dg.n + 1;
+        if (dg.np == 1) {
+            const int32_t d = g->h_ro[src + 1] - g->h_ro[src];
+            c.F[0] = d > 0 ? 1 : 0;
+            c.E[0] = d;
+        } else {
+            e = e == hipSuccess ? hipMemcpyAsync(hp, f.ctl, sizeof(unsigned long long) * kMaxParts,
+                                                 hipMemcpyDeviceToHost, st)
+                                : e;
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            read_counts(hp, &c);
+        }
+        (void)stride;
+    }
     int64_t iter = 0;
-    while (e == hipSuccess && F > 0) {
+    while (e == hipSuccess && c.Fsum() > 0) {
         if (iter >= rc.max_iters) {
             status = fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)rc.max_iters);
             break;
         }
-        const bool pull = choose_pull(g, rc, iter, F, E);
-        local.frontier_sum += F;
-        local.frontier_max = std::max(local.frontier_max, F);
+        const int64_t E = c.Esum();
+        const bool pull = choose_pull(g, rc, iter, E);
+        local.frontier_sum += c.Fsum();
+        local.frontier_max = std::max<int64_t>(local.frontier_max, c.Fsum());
+        if (timed) (void)hipEventRecord(ev[0], st);
         if (pull) {
-            e = launch_pull(g->dg, dist, f, parity, st);
+            e = launch_pull(dg, dist, f, iter, st);
             local.pull_iterations++;
-            local.arcs_pulled += g->dg.m;
+            local.arcs_pulled += dg.m;
         } else {
-            e = launch_push(g->dg, dist, f, parity, F, E, di.num_cu, st);
+            e = launch_push(dg, dist, f, iter, c, di.num_cu, st);
             local.edges_pushed += E;
+            local.push_frontier_sum += c.Fsum();
+            local.push_launches++;
         }
-        if (e == hipSuccess) e = launch_filter(g->dg, f, parity, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(hp, f.ctl + (parity ^ 1), 8, hipMemcpyDeviceToHost, st);
+        if (timed) (void)hipEventRecord(ev[1], st);
+        if (e == hipSuccess) e = launch_filter(dg, f, iter, nullptr, st);
+        if (timed) (void)hipEventRecord(ev[2], st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hp, counters_after(f, iter), sizeof(unsigned long long) * kMaxParts,
+                               hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) break;
-        const unsigned long long c = *hp;
-        F = (int32_t)(c & 0xFFFFFFFFull);
-        E = (int32_t)(c >> 32);
-        parity ^= 1;
+        if (timed) {
+            float a = 0.f, b = 0.f;
+            (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+            (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+            (pull ? local.pull_us : local.push_us) += 1e3 * a;
+            local.filter_us += 1e3 * b;
+        }
+        read_counts(hp, &c);
         ++iter;
     }
     local.iterations = (int32_t)iter;
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
     hipError_t e2 = hipFreeAsync(ws, st);
     if (e != hipSuccess) return hip_fail(e, "sssp host loop");
     if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
@@ -406,7 +523,7 @@ extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, 
                                 const gr_sssp_opts *opts, gr_sssp_stats *stats) {
     if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
     if (!dist_out) return fail(GR_ERR_INVALID_ARG, "dist_out is NULL");
-    if (src < 0 || src >= g->dg.n) return fail(GR_ERR_SOURCE_RANGE, "src = %d outside [0, %d)", src, g->dg.n);
+    if (src < 0 || src >= g->plain.n) return fail(GR_ERR_SOURCE_RANGE, "src = %d outside [0, %d)", src, g->plain.n);
     RunCfg rc;
     gr_status s = check_opts(g, opts, &rc);
     if (s != GR_OK) return s;
@@ -415,4 +532,250 @@ extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, 
 
 extern "C" gr_status gr_sssp(const gr_graph *g, int32_t src, void *dist_out, void *stream) {
     return gr_sssp_ex(g, src, dist_out, stream, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// batched multi-source queries
+
+struct BatchStats {
+    int32_t iterations = 0;
+    int64_t edges = 0;  // arc expansions (each serves every source active at its tail)
+};
+
+// Runs k <= kBatchLanes queries of graph g on stream st; row s of the result
+// goes to out_rows[s] (device pointers).  The host waits for the stream once
+// per iteration to read the frontier size.
+static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, uint32_t *const *out_rows,
+                           hipStream_t st, int64_t max_iters, BatchStats *bs) {
+    DeviceInfo di;
+    gr_status s = device_info(g->device, &di);
+    if (s != GR_OK) return s;
+    unsigned long long *hp = pinned_slot();
+    if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
+    const DevGraph &dg = g->plain;
+    void *ws = nullptr;
+    HIP_TRY(hipMallocAsync(&ws, batch_bytes(dg), st));
+    BatchWs w;
+    batch_carve(w, ws, dg);
+    // Staging copies are read by the stream before this function returns.
+    std::vector<uint32_t *> rows(out_rows, out_rows + k);
+    std::vector<int32_t> sv(srcs, srcs + k);
+    hipError_t e = hipMemcpyAsync(w.out_ptrs, rows.data(), sizeof(uint32_t *) * k, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(w.srcs, sv.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_batch_init(dg, w, k, st);
+    // The filter of "iteration -1" turns the source flags into frontier 0.
+    if (e == hipSuccess) e = launch_filter(dg, w.f, -1, nullptr, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp, counters_after(w.f, -1), sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    int64_t iter = 0;
+    gr_status status = GR_OK;
+    while (e == hipSuccess) {
+        const int32_t F = (int32_t)(hp[0] & 0xFFFFFFFFull), E = (int32_t)(hp[0] >> 32);
+        if (F == 0) break;
+        if (iter >= max_iters) {
+            status = fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)max_iters);
+            break;
+        }
+        e = launch_batch_push(dg, w, iter, F, E, di.num_cu, st);
+        if (e == hipSuccess) e = launch_filter(dg, w.f, iter, w.mask[iter & 1], st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hp, counters_after(w.f, iter), sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (bs) bs->edges += E;
+        ++iter;
+    }
+    if (e == hipSuccess && status == GR_OK) e = launch_batch_output(dg, w, k, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipError_t e2 = hipFreeAsync(ws, st);
+    if (bs) bs->iterations = (int32_t)iter;
+    if (e != hipSuccess) return hip_fail(e, "batched sssp");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    return status;
+}
+
+extern "C" gr_status gr_sssp_batch(const gr_graph *g, const int32_t *srcs, int32_t k, void *dist_out,
+                                   void *stream) {
+    if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
+    if (!srcs || !dist_out) return fail(GR_ERR_INVALID_ARG, "NULL srcs or dist_out");
+    if (k < 1 || k > kBatchLanes) return fail(GR_ERR_INVALID_ARG, "k = %d outside [1, %d]", k, kBatchLanes);
+    for (int32_t i = 0; i < k; ++i)
+        if (srcs[i] < 0 || srcs[i] >= g->plain.n)
+            return fail(GR_ERR_SOURCE_RANGE, "srcs[%d] = %d outside [0, %d)", i, srcs[i], g->plain.n);
+    std::vector<uint32_t *> rows((size_t)k);
+    for (int32_t i = 0; i < k; ++i) rows[i] = static_cast<uint32_t *>(dist_out) + (size_t)i * g->plain.n;
+    return run_batch(g, srcs, k, rows.data(), static_cast<hipStream_t>(stream), (int64_t)g->plain.n + 1, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// query server
+
+static int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+enum TicketState { kQueued = 0, kRunning = 1, kDone = 2 };
+
+struct Ticket {
+    TicketState state = kQueued;
+    gr_query_result res{};
+};
+
+struct gr_server {
+    int device = 0;
+    size_t budget = 0;
+    gr_server_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<const gr_graph *> graphs;
+    std::unique_ptr<BatchPolicy> policy;
+    std::unordered_map<uint64_t, Ticket> tickets;
+    uint64_t next_ticket = 1;
+    size_t in_flight = 0;
+    bool stopping = false;
+    std::vector<hipStream_t> streams;
+    std::vector<std::thread> workers;
+};
+
+static size_t batch_footprint(const gr_graph *g) { return batch_bytes(g->plain); }
+
+// One worker per stream: takes the next batch the policy admits, runs it,
+// publishes the results.  Batches on different streams overlap on the device.
+static void server_worker(gr_server *s, int slot) {
+    (void)hipSetDevice(s->device);
+    hipStream_t st = s->streams[slot];
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        SchedBatch b;
+        int64_t wake = 0;
+        const BatchPolicy::Decision d = s->policy->next(now_ns(), s->in_flight, s->stopping, &b, &wake);
+        if (d != BatchPolicy::kLaunch) {
+            if (s->stopping && s->policy->pending() == 0) return;
+            if (d == BatchPolicy::kWaitUntil)
+                s->cv.wait_for(lk, std::chrono::nanoseconds(std::max<int64_t>(wake - now_ns(), 1000)));
+            else
+                s->cv.wait(lk);
+            continue;
+        }
+        s->in_flight += b.bytes;
+        const int64_t t_start = now_ns();
+        const gr_graph *g = s->graphs[b.graph];
+        const int32_t k = (int32_t)b.queries.size();
+        std::vector<int32_t> srcs(k);
+        std::vector<uint32_t *> rows(k);
+        for (int32_t i = 0; i < k; ++i) {
+            srcs[i] = b.queries[i].src;
+            rows[i] = static_cast<uint32_t *>(b.queries[i].dst);
+            Ticket &t = s->tickets[b.queries[i].ticket];
+            t.state = kRunning;
+            t.res.t_start_ns = t_start;
+            t.res.batch_size = k;
+        }
+        lk.unlock();
+        const gr_status rc = run_batch(g, srcs.data(), k, rows.data(), st, (int64_t)g->plain.n + 1, nullptr);
+        const int64_t t_done = now_ns();
+        lk.lock();
+        s->in_flight -= b.bytes;
+        for (const SchedQuery &q : b.queries) {
+            Ticket &t = s->tickets[q.ticket];
+            t.state = kDone;
+            t.res.status = rc;
+            t.res.t_done_ns = t_done;
+        }
+        s->cv.notify_all();
+    }
+}
+
+extern "C" gr_status gr_server_create(gr_server **out, size_t hbm_budget_bytes, const gr_server_config *cfg) {
+    if (!out) return fail(GR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    gr_server_config c{};
+    if (cfg) c = *cfg;
+    if (c.max_batch == 0) c.max_batch = kBatchLanes;
+    if (c.num_streams == 0) c.num_streams = 2;
+    if (c.max_wait_us == 0) c.max_wait_us = 200;
+    if (c.max_batch < 1 || c.max_batch > kBatchLanes)
+        return fail(GR_ERR_INVALID_ARG, "max_batch = %d outside [1, %d]", c.max_batch, kBatchLanes);
+    if (c.num_streams < 1 || c.num_streams > 8)
+        return fail(GR_ERR_INVALID_ARG, "num_streams = %d outside [1, 8]", c.num_streams);
+    if (c.max_wait_us < 0) return fail(GR_ERR_INVALID_ARG, "max_wait_us = %d is negative", c.max_wait_us);
+    if (hbm_budget_bytes == 0) return fail(GR_ERR_INVALID_ARG, "zero memory budget");
+    std::unique_ptr<gr_server> s(new (std::nothrow) gr_server());
+    if (!s) return fail(GR_ERR_OUT_OF_MEMORY, "host allocation");
+    HIP_TRY(hipGetDevice(&s->device));
+    s->budget = hbm_budget_bytes;
+    s->cfg = c;
+    gr_server *raw = s.get();
+    s->policy.reset(new BatchPolicy(c.max_batch, (int64_t)c.max_wait_us * 1000, hbm_budget_bytes,
+                                    [raw](int32_t gid) { return batch_footprint(raw->graphs[gid]); }));
+    for (int i = 0; i < c.num_streams; ++i) {
+        hipStream_t st;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+            return hip_fail(e, "hipStreamCreate");
+        }
+        s->streams.push_back(st);
+    }
+    for (int i = 0; i < c.num_streams; ++i) s->workers.emplace_back(server_worker, raw, i);
+    *out = s.release();
+    return GR_OK;
+}
+
+extern "C" gr_status gr_server_add_graph(gr_server *s, const gr_graph *g, int32_t *graph_id) {
+    if (!s || !g || !graph_id) return fail(GR_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->graphs.push_back(g);
+    *graph_id = (int32_t)s->graphs.size() - 1;
+    return GR_OK;
+}
+
+extern "C" gr_status gr_serve_submit(gr_server *s, int32_t graph_id, int32_t src, void *dist_out,
+                                     uint64_t *ticket) {
+    if (!s || !dist_out || !ticket) return fail(GR_ERR_INVALID_ARG, "NULL argument");
+    const int64_t t = now_ns();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (graph_id < 0 || graph_id >= (int32_t)s->graphs.size())
+        return fail(GR_ERR_INVALID_ARG, "unknown graph id %d", graph_id);
+    const gr_graph *g = s->graphs[graph_id];
+    if (src < 0 || src >= g->plain.n) return fail(GR_ERR_SOURCE_RANGE, "src = %d outside [0, %d)", src, g->plain.n);
+    const size_t need = batch_footprint(g);
+    if (need > s->budget)
+        return fail(GR_ERR_NO_CAPACITY, "a query on graph %d needs %zu bytes, budget is %zu", graph_id, need,
+                    s->budget);
+    const uint64_t id = s->next_ticket++;
+    Ticket &tk = s->tickets[id];
+    tk.res.status = GR_ERR_NOT_READY;
+    tk.res.graph_id = graph_id;
+    tk.res.src = src;
+    tk.res.t_submit_ns = t;
+    s->policy->push(SchedQuery{id, graph_id, src, dist_out, t});
+    s->cv.notify_all();
+    *ticket = id;
+    return GR_OK;
+}
+
+extern "C" gr_status gr_serve_poll(gr_server *s, uint64_t ticket, gr_query_result *out) {
+    if (!s) return fail(GR_ERR_INVALID_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return fail(GR_ERR_UNKNOWN_TICKET, "ticket %llu unknown", (unsigned long long)ticket);
+    if (it->second.state != kDone) return GR_ERR_NOT_READY;
+    if (out) *out = it->second.res;
+    s->tickets.erase(it);
+    return GR_OK;
+}
+
+extern "C" gr_status gr_server_destroy(gr_server *s) {
+    if (!s) return fail(GR_ERR_INVALID_ARG, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv.notify_all();
+    for (std::thread &t : s->workers) t.join();
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    delete s;
+    return GR_OK;
 }

@@ -10,18 +10,26 @@ namespace gr {
 constexpr uint32_t kInfU32 = 0xFFFFFFFFu;
 constexpr uint32_t kInfF32 = 0x7F7FFFFFu;  // FLT_MAX bits
 
-// Frontier bitmaps are grouped in blocks of 4096 vertices (64 words of 64
-// bits); a summary bitmap holds one bit per group so that the filter skips
-// empty groups without reading them.
+// The filter works on groups of 4096 vertices.
 constexpr int kGroupShift = 12;
 constexpr int kGroupVerts = 1 << kGroupShift;
-constexpr int kGroupWords = kGroupVerts / 64;
+
+// Push layouts: the arcs are split by destination into kMaxParts contiguous
+// vertex ranges ("partitions"), stored partition-major.  Push blocks are
+// assigned to partitions round-robin, matching the round-robin placement of
+// workgroups on the 8 XCDs, so each XCD's L2 only holds its slice of the
+// distance array.  A one-partition layout is the plain CSR.
+constexpr int kMaxParts = 8;
 
 inline int64_t groups_for(int64_t n) { return (n + kGroupVerts - 1) / kGroupVerts; }
 
-// Device view of a graph: CSR for push, CSC (or the same CSR when the graph
-// is symmetric) for pull.  Arcs are interleaved (destination, weight bits) so
-// that one 8-byte load fetches both.
+// Device view of a graph.
+//   ro/adj        CSR, arcs interleaved as (destination, weight bits)
+//   ro_in/adj_in  transposed copy for pull (== ro/adj when symmetric)
+//   pro/padj      push layout with np partitions: arcs of u into partition k
+//                 are padj[pro[u*np+k] .. pro[(u+1)*np+k]) (arcs stored
+//                 partition-major, offsets vertex-major); for np == 1 these
+//                 alias ro/adj
 struct DevGraph {
     int32_t n;
     int32_t m;
@@ -30,35 +38,41 @@ struct DevGraph {
     const uint2 *adj;
     const int32_t *ro_in;
     const uint2 *adj_in;
+    int32_t np;     // 1 or kMaxParts
+    int32_t psize;  // vertices per partition (multiple of kGroupVerts)
+    const int32_t *pro;
+    const uint2 *padj;
+    int32_t cap[kMaxParts];  // max frontier entries per partition
 };
 
 // Per-query frontier workspace (device memory).
-//   bits[p], sum[p]   frontier bitmap and its group summary, parity p
-//   q[p], s[p]        sparse frontier (vertex ids) and the exclusive prefix
-//                     sum of their out-degrees, parity p
-//   ctl[0..1]         packed counters per parity: low 32 bits = frontier
-//                     size F, high 32 bits = sum of out-degrees E
-//   ctl[2]            filter blocks-done counter
-//   ctl[3..]          device-loop state (barrier, iteration, stats)
+//   flags[2]         frontier as one byte per vertex (current / next, by
+//                    iteration parity), padded to whole groups
+//   qse[k], qs[k]    sparse frontier of partition k: (first arc, u) and the
+//                    exclusive prefix sum of the arc counts
+//   ctl              3 slots x kMaxParts packed counters (low 32 bits = F_k,
+//                    high 32 bits = E_k), rotated over three iterations so that
+//                    a slot is cleared one iteration after its last use; then
+//                    the device-driven loop state
 struct Frontier {
-    uint64_t *bits[2];
-    uint64_t *sum[2];
-    int32_t *q[2];
-    int32_t *s[2];
+    uint8_t *flags[2];
+    uint2 *qse[kMaxParts];
+    int32_t *qs[kMaxParts];
     unsigned long long *ctl;
-    int64_t nwords;   // words per bitmap (multiple of kGroupWords)
-    int64_t nsumw;    // words per summary bitmap
+    int64_t nflag;  // bytes per flag array (multiple of kGroupVerts)
     int32_t ngroups;
+    int32_t np;
 };
 
-constexpr int kCtlWords = 64;
+constexpr int kCtlSlots = 3;
+constexpr int kCtlWords = 64;  // 3 x 8 counters, then LoopState
 
-// Device-driven loop state, at ctl + 8.
+// Device-driven loop state, at ctl + 32.
 struct LoopState {
-    unsigned long long bar_count;   // grid barrier arrivals
-    unsigned long long bar_gen;     // grid barrier generation
-    unsigned long long iter;        // iterations done
-    unsigned long long status;      // 0 running, 1 done, 2 iteration cap
+    unsigned long long bar_count;  // grid barrier arrivals
+    unsigned long long bar_gen;    // grid barrier generation
+    unsigned long long iter;       // iterations done
+    unsigned long long status;     // 0 running, 1 done, 2 iteration cap
     unsigned long long edges_pushed;
     unsigned long long arcs_pulled;
     unsigned long long frontier_sum;
@@ -66,15 +80,26 @@ struct LoopState {
     unsigned long long pull_iters;
 };
 
-size_t frontier_bytes(int64_t n);
-void frontier_carve(Frontier &f, void *base, int64_t n);
+size_t frontier_bytes(const DevGraph &g);
+void frontier_carve(Frontier &f, void *base, const DevGraph &g);
+
+// Totals of one frontier as read back from the counters.
+struct FrontierCounts {
+    int32_t F[kMaxParts];
+    int32_t E[kMaxParts];
+    int64_t Fsum() const;
+    int64_t Esum() const;
+};
 
 // ---- launch wrappers (gr_kernels.hip) -------------------------------------
 hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Frontier &f, hipStream_t st);
-hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int parity, int32_t F, int32_t E,
+hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, const FrontierCounts &c,
                        int num_cu, hipStream_t st);
-hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int parity, hipStream_t st);
-hipError_t launch_filter(const DevGraph &g, const Frontier &f, int parity, hipStream_t st);
+hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st);
+// zmask: optional per-vertex 64-bit masks (batched queries) cleared by the filter.
+hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uint64_t *zmask, hipStream_t st);
+// Device address of the counter slot filled by the filter of iteration `iter`.
+unsigned long long *counters_after(const Frontier &f, int64_t iter);
 
 // Device-driven loop (cooperative launch).
 struct PersistentCfg {
@@ -89,32 +114,38 @@ int persistent_max_blocks_per_cu();
 
 // Graph build helpers.
 hipError_t launch_pack_arcs(const int32_t *col, const uint32_t *w, int32_t m, uint2 *adj, hipStream_t st);
+hipError_t launch_canon_negzero(uint2 *adj, int32_t m, hipStream_t st);
 hipError_t launch_validate(int32_t n, int32_t m, const int32_t *ro, const int32_t *col, const uint32_t *w, int wt,
                            unsigned int *err, hipStream_t st);
+size_t scan_tmp_ints(int64_t len);
 hipError_t launch_csc_build(int32_t n, int32_t m, const int32_t *ro, const uint2 *adj, int32_t *ro_in,
-                            uint2 *adj_in, int32_t *scratch_cnt, hipStream_t st);
+                            uint2 *adj_in, int32_t *scratch, hipStream_t st);
 hipError_t launch_symmetry_check(int32_t n, const int32_t *ro, const uint2 *adj, unsigned int *not_sym,
                                  hipStream_t st);
+// Partitioned push layout: pro needs (n+1)*np ints; cnt and pm np*(n+1)+1
+// ints each, tmp scan_tmp_ints(np*(n+1)+1).
+hipError_t launch_partition_build(int32_t n, int32_t m, const int32_t *ro, const uint2 *adj, int32_t np,
+                                  int32_t psize, int32_t *pro, uint2 *padj, int32_t *cnt, int32_t *pm, int32_t *tmp,
+                                  unsigned long long *caps, hipStream_t st);
+// Fraction numerator for the locality test: arcs with |u - v| < span.
+hipError_t launch_locality(int32_t n, const int32_t *ro, const uint2 *adj, int32_t span, unsigned long long *near,
+                           hipStream_t st);
 
-// Batched multi-source.
+// Batched multi-source (gr_batch.hip): up to kBatchLanes sources, one per
+// wave lane, distances vertex-major D[v * kBatchLanes + s].
+constexpr int kBatchLanes = 64;
 struct BatchWs {
-    uint32_t *dist;     // n x 64 vertex-major (lane = source slot)
-    uint64_t *mask[2];  // per-vertex active-source masks, parity
-    uint64_t *bits[2];  // any-source frontier bitmap
-    uint64_t *sum[2];
-    int32_t *q[2];
-    int32_t *s[2];
-    unsigned long long *ctl;
-    int64_t nwords, nsumw;
-    int32_t ngroups;
+    uint32_t *D;
+    uint64_t *mask[2];   // per-vertex active-source masks, by iteration parity
+    Frontier f;          // shared frontier (flags, one-partition queue, counters)
+    uint32_t **out_ptrs; // device array: output row pointer of each slot
+    int32_t *srcs;       // device array: source of each slot
 };
-size_t batch_bytes(int64_t n);
-void batch_carve(BatchWs &b, void *base, int64_t n);
-hipError_t launch_batch_init(const DevGraph &g, const BatchWs &b, const int32_t *srcs_dev, int32_t k,
+size_t batch_bytes(const DevGraph &g);
+void batch_carve(BatchWs &w, void *base, const DevGraph &g);
+hipError_t launch_batch_init(const DevGraph &g, const BatchWs &w, int32_t k, hipStream_t st);
+hipError_t launch_batch_push(const DevGraph &g, const BatchWs &w, int64_t iter, int32_t F, int32_t E, int num_cu,
                              hipStream_t st);
-hipError_t launch_batch_push(const DevGraph &g, const BatchWs &b, int parity, int32_t F, int32_t E, int num_cu,
-                             hipStream_t st);
-hipError_t launch_batch_filter(const DevGraph &g, const BatchWs &b, int parity, hipStream_t st);
-hipError_t launch_batch_output(const DevGraph &g, const BatchWs &b, int32_t k, uint32_t *dist_out, hipStream_t st);
+hipError_t launch_batch_output(const DevGraph &g, const BatchWs &w, int32_t k, hipStream_t st);
 
 }  // namespace gr

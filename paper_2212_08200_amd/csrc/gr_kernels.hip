@@ -1,192 +1,193 @@
 // HIP kernels for frontier-driven SSSP on gfx950 (MI355X).
 //
 // Operators (Osama et al., Section IV-C) on a CSR graph (Section IV-A) and a
-// frontier kept both as a dense bitmap and a sparse queue (Section IV-B):
+// frontier kept both as a dense bitmap and as sparse queues (Section IV-B):
 //   k_init    dist = INF, dist[src] = 0, frontier = {src} (Listing 4 set-up)
-//   k_push    advance, push direction (Listing 3 / Listing 4 condition):
-//             every out-edge of the sparse frontier is relaxed with an
-//             atomic min; the destination joins the next bitmap iff the new
-//             value is strictly smaller than the old one.  Edges are spread
-//             evenly over blocks by a load-balanced search over the prefix
-//             sum of frontier out-degrees, so one hub's edges are shared by
-//             many blocks and every lane reads consecutive edges.
+//   k_push    advance, push direction (Listing 3, with Listing 4's condition):
+//             every out-edge of the sparse frontier is relaxed with an atomic
+//             min, and the destination joins the next bitmap iff the new value
+//             is strictly smaller than the old one.  Edges are spread evenly
+//             over blocks by a load-balanced search over the prefix sum of
+//             frontier out-degrees, so a hub's edges are shared by many blocks
+//             and consecutive lanes read consecutive arcs.
 //   k_pull    advance, pull direction over the transposed graph
-//             (Section III-C): each vertex takes the min over its in-arcs
-//             from active vertices; one owner per vertex, no global atomics.
-//   k_filter  deduplicated, compacted next frontier from the bitmap: vertex
-//             ids (sorted within a block), their out-degree prefix sums and
-//             the totals (F, E) that the convergence test reads.
+//             (Section III-C): each vertex takes the min over its in-arcs from
+//             active vertices; one owner per vertex, no global atomics on dist.
+//   k_filter  deduplicated, compacted next frontier from the flags, written
+//             as per-partition queues of (first arc, u) plus the prefix sum of
+//             arc counts, and the totals the convergence test reads.
+//
+// Partitioned push layout: arcs are grouped by destination range into up to
+// eight partitions; block b of the push works on partition b % 8.  Workgroups
+// are placed on the eight XCDs round-robin, so each XCD's L2 only sees one
+// eighth of the distance array (2 MB at 4M vertices), which then stays
+// resident and the per-edge pre-read of dist[v] hits in L2.
 //
 // Distances are 32-bit patterns; binary32 values are non-negative, so their
 // bit patterns order like the values and one uint32 atomic min serves both
 // weight types.
-#include "gr_internal.h"
+#include "gr_device.h"
 
 #include <hip/hip_runtime.h>
 
 namespace gr {
 
-constexpr int kBlk = 256;  // threads per block (4 wave64)
 
-// ---------------------------------------------------------------------------
-// (+): uint32 add saturating at INF, or binary32 add (round to nearest even)
-// clamped at FLT_MAX.  A clamped value equals INF and never wins a min.
-template <int WT>
-__device__ __forceinline__ uint32_t plus(uint32_t d, uint32_t w) {
-    if constexpr (WT == 0) {
-        uint32_t s = d + w;
-        return s < d ? kInfU32 : s;
-    } else {
-        float s = __uint_as_float(d) + __uint_as_float(w);
-        uint32_t b = __float_as_uint(s);
-        return b > kInfF32 ? kInfF32 : b;
-    }
-}
+// The next frontier is a byte per vertex, set by plain stores: every writer
+// stores the same value, so concurrent marks need no atomics (distinct bytes
+// are distinct memory locations, so marks of neighbouring vertices by other
+// blocks are never lost).
+__device__ __forceinline__ void mark(uint8_t *flags, uint32_t v) { flags[v] = 1; }
 
-// Arcs are streamed once per advance: non-temporal loads keep them from
-// evicting the distance array and bitmaps from the caches.
-__device__ __forceinline__ uint2 load_arc(const uint2 *p) {
-    const unsigned long long x = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
-    return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
-}
-
-// Marks v in a frontier bitmap and its group summary.  The plain read first
-// skips the atomic when the bit is already visible as set; bits are only set
-// during an advance, so a stale read can only miss a set bit, never invent one.
-__device__ __forceinline__ void mark(uint64_t *bits, uint64_t *sum, uint32_t v) {
-    const uint64_t bit = 1ull << (v & 63);
-    uint64_t *w = bits + (v >> 6);
-    if (*reinterpret_cast<volatile uint64_t *>(w) & bit) return;
-    uint64_t old = atomicOr(reinterpret_cast<unsigned long long *>(w), (unsigned long long)bit);
-    if (old == 0) {
-        const uint32_t g = v >> kGroupShift;
-        atomicOr(reinterpret_cast<unsigned long long *>(sum + (g >> 6)), 1ull << (g & 63));
-    }
-}
-
-// Relaxation of one edge (Listing 4): new = du (+) w, atomic min, strict <.
-// The plain pre-read of dist[v] may be stale (older, hence larger or equal),
-// so skipping when new >= pre-read never drops a needed update.
-template <int WT>
-__device__ __forceinline__ void relax(uint32_t *dist, uint64_t *nbits, uint64_t *nsum, uint32_t du, uint2 a) {
-    const uint32_t v = a.x;
-    const uint32_t nd = plus<WT>(du, a.y);
-    const uint32_t cur = __builtin_nontemporal_load(dist + v);
-    if (nd < cur) {
-        const uint32_t old = atomicMin(dist + v, nd);
-        if (nd < old) mark(nbits, nsum, v);
-    }
+// Relaxation of one edge (Listing 4) is split in two so that a thread can
+// issue the loads of several edges before any of their atomics:
+//   new = du (+) w; old = plain read of dist[v]; then, if new < old, an atomic
+//   min and a mark of v for the next frontier.
+// The old value is taken from the plain read instead of from the atomic's
+// return, so the atomic needs no reply.  The read may be stale, i.e. older and
+// hence larger or equal: if new >= read, no update is needed; if new < read,
+// then either the atomic lowers dist[v] or dist[v] was already lowered since
+// the read was cached, during this advance -- either way v improved in this
+// round, so the marked set is exactly the set of improved vertices.
+__device__ __forceinline__ void relax_commit(uint32_t *dist, uint8_t *nflags, uint32_t v, uint32_t nd) {
+    __hip_atomic_fetch_min(dist + v, nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mark(nflags, v);
 }
 
 // ---------------------------------------------------------------------------
-// init
-__global__ __launch_bounds__(kBlk) void k_init(uint32_t *__restrict__ dist, int32_t n, uint32_t inf, int32_t src,
-                                               const int32_t *__restrict__ ro, uint64_t *b0, uint64_t *b1,
-                                               int64_t nwords, uint64_t *s0, uint64_t *s1, int64_t nsumw,
-                                               int32_t *q0, int32_t *s0q, unsigned long long *ctl) {
+// init: dist, bitmaps, summaries, counters and the one-vertex frontier.
+
+struct InitArgs {
+    uint32_t *dist;
+    int32_t n;
+    int32_t np;
+    uint32_t inf;
+    int32_t src;
+    const int32_t *pro;
+    uint8_t *flags0, *flags1;
+    int64_t nflag;  // bytes per flag array (multiple of 16)
+    uint2 *qse[kMaxParts];
+    int32_t *qs[kMaxParts];
+    unsigned long long *ctl;
+};
+
+__global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = tid; v < n; v += stride) dist[v] = (v == src) ? 0u : inf;
-    const int64_t sw = src >> 6;
-    for (int64_t w = tid; w < nwords; w += stride) {
-        b0[w] = (w == sw) ? (1ull << (src & 63)) : 0ull;
-        b1[w] = 0ull;
+    const int32_t src = a.src;
+    for (int64_t v = tid; v < a.n; v += stride) a.dist[v] = (v == src) ? 0u : a.inf;
+    const int64_t sw = src >> 4;
+    for (int64_t w = tid; w < a.nflag / 16; w += stride) {
+        uint4 z = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4 *>(a.flags1)[w] = z;
+        if (w == sw) reinterpret_cast<uint32_t *>(&z)[(src >> 2) & 3] = 1u << ((src & 3) * 8);
+        reinterpret_cast<uint4 *>(a.flags0)[w] = z;
     }
-    const int64_t sg = src >> kGroupShift;
-    for (int64_t w = tid; w < nsumw; w += stride) {
-        s0[w] = (w == (sg >> 6)) ? (1ull << (sg & 63)) : 0ull;
-        s1[w] = 0ull;
-    }
-    if (tid == 0) {
-        const int32_t deg = ro[src + 1] - ro[src];
-        q0[0] = src;
-        s0q[0] = 0;
-        ctl[0] = deg > 0 ? (1ull | ((unsigned long long)deg << 32)) : 0ull;
-        for (int i = 1; i < kCtlWords; ++i) ctl[i] = 0ull;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < kCtlWords) a.ctl[threadIdx.x] = 0ull;
+        __syncthreads();
+        if (threadIdx.x < a.np) {
+            const int k = threadIdx.x;
+            const int32_t st = a.pro[(int64_t)src * a.np + k];
+            const int32_t d = a.pro[(int64_t)(src + 1) * a.np + k] - st;
+            if (d > 0) {
+                a.qse[k][0] = make_uint2((uint32_t)st, (uint32_t)src);
+                a.qs[k][0] = 0;
+                a.ctl[k] = 1ull | ((unsigned long long)d << 32);
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // push advance with load-balanced search.
 //
-// The sparse frontier q[0..F) has exclusive out-degree prefix sums s[0..F)
-// (strictly increasing: the filter drops vertices without out-edges) and
-// E = total.  Block b relaxes edge ranks [b*per_block, min(E, (b+1)*per_block)).
-// It finds the frontier entry holding its first rank with a 256-way search,
-// then walks windows of up to kWin consecutive entries staged in LDS; each
-// lane maps its rank to an entry by binary search in LDS and reads the arc at
-// ro[u] + (rank - s[entry]).  Consecutive lanes read consecutive arcs.
-constexpr int kWin = 256;
+// Partition k's frontier has F entries (first arc, du) with exclusive arc
+// count prefix sums s[0..F) (strictly increasing: the filter drops entries
+// without arcs) and E arcs in total.  Block j of partition k relaxes arc ranks
+// [j*per, min(E, (j+1)*per)).  It finds the entry holding its first rank with
+// a 256-way search, then walks windows of up to kWin consecutive entries
+// staged in LDS; each lane maps its rank to an entry by binary search in LDS.
 constexpr int kPushItems = 4;
 
-__device__ __forceinline__ int32_t find_entry(const int32_t *__restrict__ s, int32_t F, int32_t rank) {
-    // Largest i in [0, F) with s[i] <= rank (s[0] = 0 <= rank); block-wide.
-    int32_t lo = 0, hi = F;  // s[lo] <= rank < s[hi] (s[F] = E)
-    while (hi - lo > 1) {
-        const int64_t span = hi - lo;
-        const int32_t p = lo + (int32_t)((span * threadIdx.x) / kBlk);
-        const int ok = s[p] <= rank;
-        const int c = __syncthreads_count(ok);  // samples are monotone: a prefix is <= rank
-        const int32_t nlo = lo + (int32_t)((span * (c - 1)) / kBlk);
-        const int32_t nhi = (c < kBlk) ? lo + (int32_t)((span * c) / kBlk) : hi;
-        lo = nlo;
-        hi = nhi;
-    }
-    return lo;
-}
+struct PushArgs {
+    const uint2 *padj;
+    uint32_t *dist;
+    const uint2 *qse[kMaxParts];
+    const int32_t *qs[kMaxParts];
+    int32_t F[kMaxParts];
+    int32_t E[kMaxParts];
+    int32_t per[kMaxParts];
+    uint8_t *nflags;
+};
 
-template <int WT>
-__global__ __launch_bounds__(kBlk) void k_push(const int32_t *__restrict__ ro, const uint2 *__restrict__ adj,
-                                               uint32_t *__restrict__ dist, const int32_t *__restrict__ q,
-                                               const int32_t *__restrict__ s, int32_t F, int32_t E,
-                                               int32_t per_block, uint64_t *__restrict__ nbits,
-                                               uint64_t *__restrict__ nsum) {
+template <int WT, int NP>
+__global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
     __shared__ int32_t sS[kWin + 1];
-    __shared__ int32_t sRow[kWin];
+    __shared__ uint32_t sRow[kWin];
     __shared__ uint32_t sDu[kWin];
 
-    const int64_t beg64 = (int64_t)blockIdx.x * per_block;
-    if (beg64 >= E) return;
+    const int k = (NP == 1) ? 0 : (int)(blockIdx.x % NP);
+    const int64_t j = (NP == 1) ? blockIdx.x : blockIdx.x / NP;
+    const int32_t F = a.F[k], E = a.E[k], per = a.per[k];
+    const int64_t beg64 = j * per;
+    if (F <= 0 || beg64 >= E) return;
     const int32_t beg = (int32_t)beg64;
-    const int32_t end = (int32_t)min<int64_t>(beg64 + per_block, E);
+    const int32_t end = (int32_t)min<int64_t>(beg64 + per, E);
+    const int32_t *__restrict__ s = a.qs[k];
+    const uint2 *__restrict__ qse = a.qse[k];
 
     int32_t i0 = find_entry(s, F, beg);
     int32_t e = beg;
     while (e < end) {
         const int32_t cnt = min(kWin, F - i0);
+        // dist[u] is read now rather than when the filter ran: a value lowered
+        // since then (earlier in this advance) saves relaxations.
         for (int t = threadIdx.x; t < cnt; t += kBlk) {
-            const int32_t u = q[i0 + t];
+            const uint2 q = qse[i0 + t];
             sS[t] = s[i0 + t];
-            sRow[t] = ro[u];
-            sDu[t] = __builtin_nontemporal_load(dist + u);
+            sRow[t] = q.x;
+            sDu[t] = a.dist[q.y];
         }
-        if (threadIdx.x == 0) sS[cnt] = (i0 + cnt < F) ? s[i0 + cnt] : E;
+        // sS[cnt] bounds the window's ranks; entries past it are padded with
+        // INT32_MAX so that the search below needs no bounds test.
+        for (int t = cnt + threadIdx.x; t <= kWin; t += kBlk)
+            sS[t] = (t == cnt) ? ((i0 + cnt < F) ? s[i0 + cnt] : E) : INT32_MAX;
         __syncthreads();
         const int32_t wend = min(end, sS[cnt]);
         for (int32_t x0 = e + threadIdx.x; x0 < wend; x0 += kBlk * kPushItems) {
-            int32_t j[kPushItems];
-            uint2 a[kPushItems];
+            // Ranks past the window end are clamped to its last rank, so every
+            // item does the same unconditional LDS reads and loads (keeping them
+            // batched); only the commit is predicated.
+            int32_t xr[kPushItems], pos[kPushItems];
 #pragma unroll
-            for (int k = 0; k < kPushItems; ++k) {
-                const int32_t x = x0 + k * kBlk;
-                int lo = 0, hi = cnt - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (sS[mid] <= x) lo = mid;
-                    else hi = mid - 1;
+            for (int it = 0; it < kPushItems; ++it) {
+                xr[it] = min(x0 + it * kBlk, wend - 1);
+                pos[it] = 0;
+            }
+            // entry of each rank: largest j with sS[j] <= rank, by branch-free
+            // binary lifting (sS is strictly increasing, then padded)
+#pragma unroll
+            for (int b = kWin / 2; b >= 1; b >>= 1) {
+#pragma unroll
+                for (int it = 0; it < kPushItems; ++it) {
+                    const int32_t p = pos[it] + b;
+                    pos[it] = (sS[p] <= xr[it]) ? p : pos[it];
                 }
-                j[k] = lo;
+            }
+            uint2 arc[kPushItems];
+#pragma unroll
+            for (int it = 0; it < kPushItems; ++it)
+                arc[it] = load_arc(a.padj + sRow[pos[it]] + (uint32_t)(xr[it] - sS[pos[it]]));
+            uint32_t nd[kPushItems], cur[kPushItems];
+#pragma unroll
+            for (int it = 0; it < kPushItems; ++it) {
+                nd[it] = plus<WT>(sDu[pos[it]], arc[it].y);
+                cur[it] = a.dist[arc[it].x];
             }
 #pragma unroll
-            for (int k = 0; k < kPushItems; ++k) {
-                const int32_t x = x0 + k * kBlk;
-                if (x < wend) a[k] = load_arc(adj + sRow[j[k]] + (x - sS[j[k]]));
-            }
-#pragma unroll
-            for (int k = 0; k < kPushItems; ++k) {
-                const int32_t x = x0 + k * kBlk;
-                if (x < wend) relax<WT>(dist, nbits, nsum, sDu[j[k]], a[k]);
-            }
+            for (int it = 0; it < kPushItems; ++it)
+                if (x0 + it * kBlk < wend && nd[it] < cur[it]) relax_commit(a.dist, a.nflags, arc[it].x, nd[it]);
         }
         i0 += cnt;
         e = wend;
@@ -197,161 +198,152 @@ __global__ __launch_bounds__(kBlk) void k_push(const int32_t *__restrict__ ro, c
 // ---------------------------------------------------------------------------
 // pull advance: block owns vertices [v0, v0 + kBlk); its in-arcs are the
 // contiguous CSC range [ro_in[v0], ro_in[v0 + kBlk]).  Lanes stride over that
-// range, map each arc to its owner by binary search in LDS, and fold
+// range, map each arc to its owner by binary search in LDS, and fold the
 // candidates dist[u] (+) w of active u into an LDS min per owner.  Then each
 // owner compares with dist[v], stores the improvement (it is the only writer
-// of dist[v] in this launch) and the wave writes its 64-bit bitmap word.
+// of dist[v] in this launch) and each wave writes its 64-bit bitmap word.
+constexpr int kPullItems = 4;
+
 template <int WT>
 __global__ __launch_bounds__(kBlk) void k_pull(int32_t n, const int32_t *__restrict__ ro_in,
                                                const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
-                                               const uint64_t *__restrict__ cbits, uint64_t *__restrict__ nbits,
-                                               uint64_t *__restrict__ nsum) {
+                                               const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags) {
     __shared__ int32_t sOff[kBlk + 1];
     __shared__ uint32_t sMin[kBlk];
     const int32_t v0 = blockIdx.x * kBlk;
     const int32_t nv = min(kBlk, n - v0);
-    for (int t = threadIdx.x; t <= nv; t += kBlk) sOff[t] = ro_in[v0 + t];
+    // sOff[0..nv] are the owners' arc offsets; entries past nv are padded with
+    // INT32_MAX so that the owner search needs no bounds test.
+    for (int t = threadIdx.x; t <= kBlk; t += kBlk) sOff[t] = (t <= nv) ? ro_in[v0 + t] : INT32_MAX;
     sMin[threadIdx.x] = kInfU32;
     __syncthreads();
     const int32_t a0 = sOff[0], a1 = sOff[nv];
-    for (int32_t x = a0 + threadIdx.x; x < a1; x += kBlk) {
-        const uint2 a = load_arc(adj_in + x);
-        const uint32_t u = a.x;
-        if ((cbits[u >> 6] >> (u & 63)) & 1ull) {
-            int lo = 0, hi = nv - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (sOff[mid] <= x) lo = mid;
-                else hi = mid - 1;
+    const uint32_t inf = WT == 0 ? kInfU32 : kInfF32;
+    for (int32_t x0 = a0 + threadIdx.x; x0 < a1; x0 += kBlk * kPullItems) {
+        // arcs past the range end are clamped to its last arc (loads stay
+        // unconditional and batched); only the fold is predicated
+        int32_t xr[kPullItems];
+        uint2 arc[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) {
+            xr[it] = min(x0 + it * kBlk, a1 - 1);
+            arc[it] = load_arc(adj_in + xr[it]);
+        }
+        uint8_t fl[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) fl[it] = cflags[arc[it].x];
+        uint32_t du[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) du[it] = dist[arc[it].x];
+        int32_t pos[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) pos[it] = 0;
+#pragma unroll
+        for (int b = kBlk / 2; b >= 1; b >>= 1) {
+#pragma unroll
+            for (int it = 0; it < kPullItems; ++it) {
+                const int32_t p = pos[it] + b;
+                pos[it] = (sOff[p] <= xr[it]) ? p : pos[it];
             }
-            const uint32_t du = __builtin_nontemporal_load(dist + u);
-            if (du != (WT == 0 ? kInfU32 : kInfF32)) atomicMin(&sMin[lo], plus<WT>(du, a.y));
+        }
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) {
+            const bool act = (x0 + it * kBlk < a1) && fl[it] && du[it] != inf;
+            if (act) atomicMin(&sMin[pos[it]], plus<WT>(du[it], arc[it].y));
         }
     }
     __syncthreads();
     const int32_t v = v0 + threadIdx.x;
-    bool improved = false;
     if (threadIdx.x < nv) {
         const uint32_t cand = sMin[threadIdx.x];
         const uint32_t cur = dist[v];
         if (cand < cur) {
             dist[v] = cand;
-            improved = true;
+            mark(nflags, (uint32_t)v);
         }
-    }
-    const uint64_t word = __ballot(improved);
-    if ((threadIdx.x & 63) == 0 && word) {
-        nbits[v >> 6] = word;  // block is 64-aligned: this wave owns the word
-        const uint32_t g = (uint32_t)v >> kGroupShift;
-        atomicOr(reinterpret_cast<unsigned long long *>(nsum + (g >> 6)), 1ull << (g & 63));
     }
 }
 
 // ---------------------------------------------------------------------------
-// filter: one block per 4096-vertex group; thread t owns vertices
-// [base + 16 t, base + 16 t + 16), so the block's output is in vertex order.
-// Reserves its slice of the next queue and of the degree prefix sum with one
-// 64-bit atomic add of (count | degree_sum << 32).  Also clears the current
-// frontier's bitmap (guided by its summary) so it can hold the frontier after
-// next, and the last block to finish clears the current summary and counter.
+// filter: one block per (group of 4096 vertices, partition k); block b works
+// on group b / np and partition b % np, so with 8 partitions the queue of
+// partition k is written on the XCD whose push blocks read it.  Thread t owns
+// vertices [base + 16 t, base + 16 t + 16), so each queue slice is in vertex
+// order.  A block reserves its slice of partition k's queue and of that
+// queue's arc prefix sum with one 64-bit atomic add of (count | arcs << 32).
+// It also clears its share of the current frontier's flags (so they can hold
+// the frontier after next); block 0 clears the counter slot that was last
+// used one iteration ago.
 constexpr int kVpt = kGroupVerts / kBlk;  // 16
 
-__device__ __forceinline__ void block_scan2(int32_t &a, int32_t &b, int32_t &tot_a, int32_t &tot_b) {
-    // exclusive scan of (a, b) over the block; returns totals.
-    __shared__ int32_t wa[kBlk / 64], wb[kBlk / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int32_t ia = a, ib = b;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t ta = __shfl_up(ia, o, 64), tb = __shfl_up(ib, o, 64);
-        if (lane >= o) {
-            ia += ta;
-            ib += tb;
-        }
-    }
-    if (lane == 63) {
-        wa[wid] = ia;
-        wb[wid] = ib;
-    }
-    __syncthreads();
-    int32_t pa = 0, pb = 0;
-    tot_a = 0;
-    tot_b = 0;
-#pragma unroll
-    for (int w = 0; w < kBlk / 64; ++w) {
-        if (w < wid) {
-            pa += wa[w];
-            pb += wb[w];
-        }
-        tot_a += wa[w];
-        tot_b += wb[w];
-    }
-    a = pa + ia - a;
-    b = pb + ib - b;
-    __syncthreads();
-}
+struct FilterArgs {
+    int32_t np;
+    const int32_t *pro;
+    uint64_t *zmask;  // when set (batched queries): per-vertex masks cleared by partition-0 blocks
+    const uint8_t *nflags;
+    uint8_t *cflags;
+    uint2 *qse[kMaxParts];
+    int32_t *qs[kMaxParts];
+    unsigned long long *ctl_next;
+    unsigned long long *ctl_zero;
+};
 
-__global__ __launch_bounds__(kBlk) void k_filter(int32_t n, const int32_t *__restrict__ ro,
-                                                 const uint64_t *__restrict__ nbits,
-                                                 const uint64_t *__restrict__ nsum, uint64_t *__restrict__ cbits,
-                                                 uint64_t *__restrict__ csum, int64_t nsumw,
-                                                 int32_t *__restrict__ q, int32_t *__restrict__ s,
-                                                 unsigned long long *__restrict__ ctl_next,
-                                                 unsigned long long *__restrict__ ctl_cur,
-                                                 unsigned long long *__restrict__ done) {
+__global__ __launch_bounds__(kBlk) void k_filter(FilterArgs a) {
     __shared__ unsigned long long sh_base;
-    const int32_t g = blockIdx.x;
-    const bool cur_has = (csum[g >> 6] >> (g & 63)) & 1ull;
-    const bool nxt_has = (nsum[g >> 6] >> (g & 63)) & 1ull;
-    if (cur_has && threadIdx.x < kGroupWords) cbits[(int64_t)g * kGroupWords + threadIdx.x] = 0ull;
-    if (nxt_has) {
-        const int64_t base = (int64_t)g * kGroupVerts + threadIdx.x * kVpt;
-        const uint64_t word = nbits[base >> 6];
-        const uint32_t mask16 = (uint32_t)(word >> (base & 63)) & 0xFFFFu;
-        uint32_t keep = 0;
-        int32_t cnt = 0, dsum = 0;
-        for (int k = 0; k < kVpt; ++k) {
-            if ((mask16 >> k) & 1u) {
-                const int64_t v = base + k;
-                const int32_t d = ro[v + 1] - ro[v];
-                if (d > 0) {
-                    keep |= 1u << k;
-                    ++cnt;
-                    dsum += d;
-                }
-            }
-        }
-        int32_t tc, td;
-        block_scan2(cnt, dsum, tc, td);
-        if (threadIdx.x == 0) {
-            sh_base = tc ? atomicAdd(ctl_next, (unsigned long long)tc | ((unsigned long long)td << 32)) : 0ull;
-        }
-        __syncthreads();
-        int32_t qpos = (int32_t)(sh_base & 0xFFFFFFFFull) + cnt;
-        int32_t spos = (int32_t)(sh_base >> 32) + dsum;
-        for (int k = 0; k < kVpt; ++k) {
-            if ((keep >> k) & 1u) {
-                const int64_t v = base + k;
-                q[qpos] = (int32_t)v;
-                s[qpos] = spos;
-                ++qpos;
-                spos += ro[v + 1] - ro[v];
+    const int np = a.np;
+    const int32_t g = blockIdx.x / np;
+    const int k = blockIdx.x % np;
+    if (blockIdx.x == 0 && threadIdx.x < kMaxParts) a.ctl_zero[threadIdx.x] = 0ull;
+    if (a.zmask && k == 0)
+        for (int t = threadIdx.x; t < kGroupVerts; t += kBlk) a.zmask[(int64_t)g * kGroupVerts + t] = 0ull;
+    {
+        // this block's share of the group's current flags: 4096 / np bytes
+        const int share16 = kGroupVerts / 16 / np;
+        if ((int)threadIdx.x < share16)
+            reinterpret_cast<uint4 *>(a.cflags)[(int64_t)g * (kGroupVerts / 16) + k * share16 + threadIdx.x] =
+                make_uint4(0u, 0u, 0u, 0u);
+    }
+    const int64_t base = (int64_t)g * kGroupVerts + threadIdx.x * kVpt;
+    const uint4 fw = reinterpret_cast<const uint4 *>(a.nflags)[base >> 4];
+    uint32_t mask16 = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        const uint32_t word = b < 4 ? fw.x : b < 8 ? fw.y : b < 12 ? fw.z : fw.w;
+        mask16 |= (((word >> ((b & 3) * 8)) & 0xFFu) != 0u ? 1u : 0u) << b;
+    }
+    if (!__syncthreads_or(mask16 != 0)) return;  // uniform per block
+
+    int32_t x[2] = {0, 0}, tot[2];
+    for (int b = 0; b < kVpt; ++b) {
+        if ((mask16 >> b) & 1u) {
+            const int64_t u = base + b;
+            const int32_t d = a.pro[(u + 1) * np + k] - a.pro[u * np + k];
+            if (d > 0) {
+                x[0] += 1;
+                x[1] += d;
             }
         }
     }
-    // Last block out clears the current summary and counter slot.
-    __shared__ bool last;
+    block_scan<2>(x, tot);
+    if (threadIdx.x == 0)
+        sh_base = tot[0] ? atomicAdd(a.ctl_next + k, (unsigned long long)tot[0] | ((unsigned long long)tot[1] << 32))
+                         : 0ull;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last = atomicAdd(done, 1ull) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last) {
-        for (int64_t w = threadIdx.x; w < nsumw; w += kBlk) csum[w] = 0ull;
-        if (threadIdx.x == 0) {
-            *ctl_cur = 0ull;
-            *done = 0ull;
+    int32_t pos = (int32_t)(sh_base & 0xFFFFFFFFull) + x[0];
+    int32_t spos = (int32_t)(sh_base >> 32) + x[1];
+    uint2 *__restrict__ qse = a.qse[k];
+    int32_t *__restrict__ qs = a.qs[k];
+    for (int b = 0; b < kVpt; ++b) {
+        if ((mask16 >> b) & 1u) {
+            const int64_t u = base + b;
+            const int32_t st = a.pro[u * np + k];
+            const int32_t d = a.pro[(u + 1) * np + k] - st;
+            if (d > 0) {
+                qse[pos] = make_uint2((uint32_t)st, (uint32_t)u);
+                qs[pos] = spos;
+                ++pos;
+                spos += d;
+            }
         }
     }
 }
@@ -382,7 +374,7 @@ __global__ void k_validate(int32_t n, int32_t m, const int32_t *__restrict__ ro,
         if (col[i] < 0 || col[i] >= n) e |= 2u;
         if (wt == 1) {
             const uint32_t b = w[i];
-            if ((b & 0x80000000u) && b != 0x80000000u) e |= 4u;  // negative (but -0 is allowed)
+            if ((b & 0x80000000u) && b != 0x80000000u) e |= 4u;  // negative (-0 is allowed)
             if ((b & 0x7F800000u) == 0x7F800000u) e |= 4u;       // inf / NaN
         }
     }
@@ -417,15 +409,15 @@ __global__ __launch_bounds__(kBlk) void k_scan_level(const int32_t *__restrict__
         v[k] = (base + k < len) ? in[base + k] : 0;
         t += v[k];
     }
-    int32_t dummy = 0, tot, td;
-    int32_t ex = t;
-    block_scan2(ex, dummy, tot, td);
+    int32_t x[1] = {t}, tot[1];
+    block_scan<1>(x, tot);
+    int32_t ex = x[0];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < len) out[base + k] = ex;
         ex += v[k];
     }
-    if (threadIdx.x == 0 && bsum) bsum[blockIdx.x] = tot;
+    if (threadIdx.x == 0 && bsum) bsum[blockIdx.x] = tot[0];
 }
 
 __global__ void k_scan_add(int32_t *__restrict__ out, int64_t len, const int32_t *__restrict__ boff) {
@@ -433,12 +425,18 @@ __global__ void k_scan_add(int32_t *__restrict__ out, int64_t len, const int32_t
     if (i < len) out[i] += boff[i / kScanChunk];
 }
 
-__global__ void k_scatter_in(int32_t n, const int32_t *__restrict__ ro, const uint2 *__restrict__ adj,
-                             const int32_t *__restrict__ ro_in, int32_t *__restrict__ fill,
-                             uint2 *__restrict__ adj_in) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
-        for (int32_t e = ro[u]; e < ro[u + 1]; ++e) {
+// One wave per row (grid-stride over rows).
+#define FOR_EACH_ROW_BY_WAVE(u, n)                                                   \
+    for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; u < (n); \
+         u += ((int64_t)gridDim.x * blockDim.x) / 64)
+
+__global__ __launch_bounds__(kBlk) void k_scatter_in(int32_t n, const int32_t *__restrict__ ro,
+                                                     const uint2 *__restrict__ adj,
+                                                     const int32_t *__restrict__ ro_in, int32_t *__restrict__ fill,
+                                                     uint2 *__restrict__ adj_in) {
+    const int lane = threadIdx.x & 63;
+    FOR_EACH_ROW_BY_WAVE(u, n) {
+        for (int32_t e = ro[u] + lane; e < ro[u + 1]; e += 64) {
             const uint2 a = adj[e];
             const int32_t p = atomicAdd(fill + a.x, 1);
             adj_in[ro_in[a.x] + p] = make_uint2((uint32_t)u, a.y);
@@ -448,17 +446,15 @@ __global__ void k_scatter_in(int32_t n, const int32_t *__restrict__ ro, const ui
 
 // Symmetric iff every row is strictly increasing and each arc u -> v of
 // weight w has a reverse arc v -> u of the same weight bits.
-__global__ void k_symmetry(int32_t n, const int32_t *__restrict__ ro, const uint2 *__restrict__ adj,
-                           unsigned int *not_sym) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__global__ __launch_bounds__(kBlk) void k_symmetry(int32_t n, const int32_t *__restrict__ ro,
+                                                   const uint2 *__restrict__ adj, unsigned int *not_sym) {
+    const int lane = threadIdx.x & 63;
     bool bad = false;
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n && !bad; u += stride) {
-        for (int32_t e = ro[u]; e < ro[u + 1] && !bad; ++e) {
+    FOR_EACH_ROW_BY_WAVE(u, n) {
+        const int32_t r1 = ro[u + 1];
+        for (int32_t e = ro[u] + lane; e < r1; e += 64) {
             const uint2 a = adj[e];
-            if (e + 1 < ro[u + 1] && adj[e + 1].x <= a.x) {
-                bad = true;
-                break;
-            }
+            if (e + 1 < r1 && adj[e + 1].x <= a.x) bad = true;
             int32_t lo = ro[a.x], hi = ro[a.x + 1];
             while (lo < hi) {
                 const int32_t mid = (lo + hi) >> 1;
@@ -468,7 +464,96 @@ __global__ void k_symmetry(int32_t n, const int32_t *__restrict__ ro, const uint
             if (lo >= ro[a.x + 1] || (int64_t)adj[lo].x != u || adj[lo].y != a.y) bad = true;
         }
     }
-    if (bad) atomicOr(not_sym, 1u);
+    if (__ballot(bad) && lane == 0) atomicOr(not_sym, 1u);
+}
+
+// Arcs with |u - v| < span (locality test for the push layout choice).
+__global__ __launch_bounds__(kBlk) void k_locality(int32_t n, const int32_t *__restrict__ ro,
+                                                   const uint2 *__restrict__ adj, int32_t span,
+                                                   unsigned long long *near) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long c = 0;
+    FOR_EACH_ROW_BY_WAVE(u, n) {
+        for (int32_t e = ro[u] + lane; e < ro[u + 1]; e += 64) {
+            const int64_t d = (int64_t)adj[e].x - u;
+            c += (d < span && d > -span) ? 1 : 0;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if (lane == 0 && c) atomicAdd(near, c);
+}
+
+// Partition layout: count the arcs of each row per destination partition.
+__global__ __launch_bounds__(kBlk) void k_part_count(int32_t n, const int32_t *__restrict__ ro,
+                                                     const uint2 *__restrict__ adj, int32_t np, int32_t psize,
+                                                     int32_t *__restrict__ cnt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)n + 1;
+    FOR_EACH_ROW_BY_WAVE(u, n) {
+        int32_t c[kMaxParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int32_t e0 = ro[u]; e0 < ro[u + 1]; e0 += 64) {
+            const int32_t e = e0 + lane;
+            const int p = (e < ro[u + 1]) ? (int)(adj[e].x / (uint32_t)psize) : -1;
+#pragma unroll
+            for (int k = 0; k < kMaxParts; ++k) c[k] += __popcll(__ballot(p == k));
+        }
+        if (lane < np) {
+            int32_t mine = 0;
+#pragma unroll
+            for (int k = 0; k < kMaxParts; ++k)
+                if (k == lane) mine = c[k];
+            cnt[lane * stride + u] = mine;
+        }
+    }
+}
+
+// Vertices with at least one arc into partition k (queue capacity).
+__global__ __launch_bounds__(kBlk) void k_part_caps(int32_t n, int32_t np, const int32_t *__restrict__ cnt,
+                                                    unsigned long long *caps) {
+    __shared__ unsigned int sc[kMaxParts];
+    if (threadIdx.x < kMaxParts) sc[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)n + 1;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+        for (int k = 0; k < np; ++k)
+            if (cnt[k * stride + u] > 0) atomicAdd(&sc[k], 1u);
+    __syncthreads();
+    if (threadIdx.x < np && sc[threadIdx.x]) atomicAdd(caps + threadIdx.x, (unsigned long long)sc[threadIdx.x]);
+}
+
+// Scatter arcs into the partition-major layout, keeping their order in the row.
+__global__ __launch_bounds__(kBlk) void k_part_scatter(int32_t n, const int32_t *__restrict__ ro,
+                                                       const uint2 *__restrict__ adj, int32_t psize,
+                                                       const int32_t *__restrict__ pro, uint2 *__restrict__ padj) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)n + 1;
+    const uint64_t lanemask_lt = (1ull << lane) - 1ull;
+    FOR_EACH_ROW_BY_WAVE(u, n) {
+        int32_t run[kMaxParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int32_t e0 = ro[u]; e0 < ro[u + 1]; e0 += 64) {
+            const int32_t e = e0 + lane;
+            const bool ok = e < ro[u + 1];
+            const uint2 a = ok ? adj[e] : make_uint2(0u, 0u);
+            const int p = ok ? (int)(a.x / (uint32_t)psize) : -1;
+#pragma unroll
+            for (int k = 0; k < kMaxParts; ++k) {
+                const uint64_t msk = __ballot(p == k);
+                if (p == k) padj[pro[k * stride + u] + run[k] + __popcll(msk & lanemask_lt)] = a;
+                run[k] += __popcll(msk);
+            }
+        }
+    }
+}
+
+// Partition-major offsets (k, u) -> vertex-major (u, k), so that the filter
+// reads one contiguous record per frontier vertex.
+__global__ void k_part_transpose(int32_t n, int32_t np, const int32_t *__restrict__ pm, int32_t *__restrict__ vm) {
+    const int64_t total = ((int64_t)n + 1) * np;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int64_t u = i / np, k = i % np;
+        vm[i] = pm[k * ((int64_t)n + 1) + u];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -481,47 +566,102 @@ static inline int grid_for(int64_t items, int per_block, int cap) {
     return (int)b;
 }
 
+static inline int slot_of(int64_t i) { return (int)(((i % kCtlSlots) + kCtlSlots) % kCtlSlots); }
+
+unsigned long long *counters_after(const Frontier &f, int64_t iter) { return f.ctl + slot_of(iter + 1) * kMaxParts; }
+
+int64_t FrontierCounts::Fsum() const {
+    int64_t s = 0;
+    for (int k = 0; k < kMaxParts; ++k) s += F[k];
+    return s;
+}
+
+int64_t FrontierCounts::Esum() const {
+    int64_t s = 0;
+    for (int k = 0; k < kMaxParts; ++k) s += E[k];
+    return s;
+}
+
 hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Frontier &f, hipStream_t st) {
-    const uint32_t inf = g.wt == 1 ? kInfF32 : kInfU32;
+    InitArgs a;
+    a.dist = dist;
+    a.n = g.n;
+    a.np = g.np;
+    a.inf = g.wt == 1 ? kInfF32 : kInfU32;
+    a.src = src;
+    a.pro = g.pro;
+    a.flags0 = f.flags[0];
+    a.flags1 = f.flags[1];
+    a.nflag = f.nflag;
+    for (int k = 0; k < kMaxParts; ++k) {
+        a.qse[k] = f.qse[k];
+        a.qs[k] = f.qs[k];
+    }
+    a.ctl = f.ctl;
     const int grid = grid_for(g.n, kBlk * 4, 8192);
-    hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlk), 0, st, dist, g.n, inf, src, g.ro, f.bits[0], f.bits[1],
-                       f.nwords, f.sum[0], f.sum[1], f.nsumw, f.q[0], f.s[0], f.ctl);
+    hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlk), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int parity, int32_t F, int32_t E,
+hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, const FrontierCounts &c,
                        int num_cu, hipStream_t st) {
-    if (F <= 0 || E <= 0) return hipSuccess;
-    int64_t per = ((int64_t)E + (int64_t)num_cu * 8 - 1) / ((int64_t)num_cu * 8);
-    if (per < 2048) per = 2048;
-    per = (per + 255) & ~int64_t(255);
-    const int grid = (int)(((int64_t)E + per - 1) / per);
-    const int p = parity & 1, np = p ^ 1;
-    if (g.wt == 1)
-        hipLaunchKernelGGL(k_push<1>, dim3(grid), dim3(kBlk), 0, st, g.ro, g.adj, dist, f.q[p], f.s[p], F, E,
-                           (int32_t)per, f.bits[np], f.sum[np]);
-    else
-        hipLaunchKernelGGL(k_push<0>, dim3(grid), dim3(kBlk), 0, st, g.ro, g.adj, dist, f.q[p], f.s[p], F, E,
-                           (int32_t)per, f.bits[np], f.sum[np]);
+    const int64_t E = c.Esum();
+    if (E <= 0) return hipSuccess;
+    int64_t target = (E + (int64_t)num_cu * 8 - 1) / ((int64_t)num_cu * 8);
+    if (target < 2048) target = 2048;
+    int64_t emax = 0;
+    for (int k = 0; k < g.np; ++k) emax = c.E[k] > emax ? c.E[k] : emax;
+    const int64_t B = (emax + target - 1) / target;
+    PushArgs a;
+    a.padj = g.padj;
+    a.dist = dist;
+    for (int k = 0; k < kMaxParts; ++k) {
+        a.qse[k] = f.qse[k];
+        a.qs[k] = f.qs[k];
+        a.F[k] = k < g.np ? c.F[k] : 0;
+        a.E[k] = k < g.np ? c.E[k] : 0;
+        a.per[k] = (int32_t)((a.E[k] + B - 1) / B);
+        if (a.per[k] < 1) a.per[k] = 1;
+    }
+    a.nflags = f.flags[(iter + 1) & 1];
+    const int grid = (int)(B * g.np);
+    if (g.np == 1) {
+        if (g.wt == 1) hipLaunchKernelGGL((k_push<1, 1>), dim3(grid), dim3(kBlk), 0, st, a);
+        else hipLaunchKernelGGL((k_push<0, 1>), dim3(grid), dim3(kBlk), 0, st, a);
+    } else {
+        if (g.wt == 1) hipLaunchKernelGGL((k_push<1, kMaxParts>), dim3(grid), dim3(kBlk), 0, st, a);
+        else hipLaunchKernelGGL((k_push<0, kMaxParts>), dim3(grid), dim3(kBlk), 0, st, a);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int parity, hipStream_t st) {
+hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st) {
     const int grid = (g.n + kBlk - 1) / kBlk;
-    const int p = parity & 1, np = p ^ 1;
+    const int p = (int)(iter & 1), np1 = p ^ 1;
     if (g.wt == 1)
-        hipLaunchKernelGGL(k_pull<1>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.bits[p],
-                           f.bits[np], f.sum[np]);
+        hipLaunchKernelGGL(k_pull<1>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
+                           f.flags[np1]);
     else
-        hipLaunchKernelGGL(k_pull<0>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.bits[p],
-                           f.bits[np], f.sum[np]);
+        hipLaunchKernelGGL(k_pull<0>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
+                           f.flags[np1]);
     return hipGetLastError();
 }
 
-hipError_t launch_filter(const DevGraph &g, const Frontier &f, int parity, hipStream_t st) {
-    const int p = parity & 1, np = p ^ 1;
-    hipLaunchKernelGGL(k_filter, dim3(f.ngroups), dim3(kBlk), 0, st, g.n, g.ro, f.bits[np], f.sum[np], f.bits[p],
-                       f.sum[p], f.nsumw, f.q[np], f.s[np], f.ctl + np, f.ctl + p, f.ctl + 2);
+hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uint64_t *zmask, hipStream_t st) {
+    FilterArgs a;
+    const int p = (int)(iter & 1);
+    a.np = g.np;
+    a.pro = g.pro;
+    a.zmask = zmask;
+    a.nflags = f.flags[p ^ 1];
+    a.cflags = f.flags[p];
+    for (int k = 0; k < kMaxParts; ++k) {
+        a.qse[k] = f.qse[k];
+        a.qs[k] = f.qs[k];
+    }
+    a.ctl_next = f.ctl + slot_of(iter + 1) * kMaxParts;
+    a.ctl_zero = f.ctl + slot_of(iter + 2) * kMaxParts;
+    hipLaunchKernelGGL(k_filter, dim3(f.ngroups * g.np), dim3(kBlk), 0, st, a);
     return hipGetLastError();
 }
 
@@ -539,7 +679,7 @@ hipError_t launch_validate(int32_t n, int32_t m, const int32_t *ro, const int32_
 }
 
 static hipError_t scan_exclusive(const int32_t *in, int64_t len, int32_t *out, int32_t *tmp, hipStream_t st) {
-    // out[0..len) = exclusive scan of in; tmp needs >= 2 * ceil(len / 1024) + 2048 ints.
+    // out[0..len) = exclusive scan of in; tmp holds scan_tmp_ints(len) ints.
     const int64_t nb = (len + kScanChunk - 1) / kScanChunk;
     hipLaunchKernelGGL(k_scan_level, dim3((unsigned)nb), dim3(kBlk), 0, st, in, len, out, tmp);
     if (nb > 1) {
@@ -548,35 +688,6 @@ static hipError_t scan_exclusive(const int32_t *in, int64_t len, int32_t *out, i
         hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((len + kBlk - 1) / kBlk)), dim3(kBlk), 0, st, out, len,
                            tmp + nb);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_csc_build(int32_t n, int32_t m, const int32_t *ro, const uint2 *adj, int32_t *ro_in,
-                            uint2 *adj_in, int32_t *scratch, hipStream_t st) {
-    // scratch: n + 1 ints (counts) + n ints (fill) + scan temporaries.
-    int32_t *cnt = scratch;
-    int32_t *fill = scratch + (n + 1);
-    int32_t *tmp = fill + n;
-    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)(2 * (int64_t)n + 1), st);
-    if (e != hipSuccess) return e;
-    if (m > 0) hipLaunchKernelGGL(k_count_in, dim3(grid_for(m, kBlk * 8, 16384)), dim3(kBlk), 0, st, adj, m, cnt);
-    e = scan_exclusive(cnt, (int64_t)n + 1, ro_in, tmp, st);
-    if (e != hipSuccess) return e;
-    if (m > 0)
-        hipLaunchKernelGGL(k_scatter_in, dim3(grid_for(n, kBlk, 16384)), dim3(kBlk), 0, st, n, ro, adj, ro_in, fill,
-                           adj_in);
-    return hipGetLastError();
-}
-
-hipError_t launch_symmetry_check(int32_t n, const int32_t *ro, const uint2 *adj, unsigned int *not_sym,
-                                 hipStream_t st) {
-    hipLaunchKernelGGL(k_symmetry, dim3(grid_for(n, kBlk, 16384)), dim3(kBlk), 0, st, n, ro, adj, not_sym);
-    return hipGetLastError();
-}
-
-hipError_t launch_canon_negzero(uint2 *adj, int32_t m, hipStream_t st) {
-    if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_canon_negzero, dim3(grid_for(m, kBlk * 8, 16384)), dim3(kBlk), 0, st, adj, m);
     return hipGetLastError();
 }
 
@@ -592,42 +703,100 @@ size_t scan_tmp_ints(int64_t len) {
     return t + 16;
 }
 
+static inline int row_grid(int32_t n) { return grid_for((int64_t)n, kBlk / 64, 16384); }
+
+hipError_t launch_csc_build(int32_t n, int32_t m, const int32_t *ro, const uint2 *adj, int32_t *ro_in,
+                            uint2 *adj_in, int32_t *scratch, hipStream_t st) {
+    // scratch: n + 1 ints (counts) + n ints (fill) + scan temporaries.
+    int32_t *cnt = scratch;
+    int32_t *fill = scratch + (n + 1);
+    int32_t *tmp = fill + n;
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)(2 * (int64_t)n + 1), st);
+    if (e != hipSuccess) return e;
+    if (m > 0) hipLaunchKernelGGL(k_count_in, dim3(grid_for(m, kBlk * 8, 16384)), dim3(kBlk), 0, st, adj, m, cnt);
+    e = scan_exclusive(cnt, (int64_t)n + 1, ro_in, tmp, st);
+    if (e != hipSuccess) return e;
+    if (m > 0)
+        hipLaunchKernelGGL(k_scatter_in, dim3(row_grid(n)), dim3(kBlk), 0, st, n, ro, adj, ro_in, fill, adj_in);
+    return hipGetLastError();
+}
+
+hipError_t launch_symmetry_check(int32_t n, const int32_t *ro, const uint2 *adj, unsigned int *not_sym,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_symmetry, dim3(row_grid(n)), dim3(kBlk), 0, st, n, ro, adj, not_sym);
+    return hipGetLastError();
+}
+
+hipError_t launch_locality(int32_t n, const int32_t *ro, const uint2 *adj, int32_t span, unsigned long long *near,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_locality, dim3(row_grid(n)), dim3(kBlk), 0, st, n, ro, adj, span, near);
+    return hipGetLastError();
+}
+
+hipError_t launch_partition_build(int32_t n, int32_t m, const int32_t *ro, const uint2 *adj, int32_t np,
+                                  int32_t psize, int32_t *pro, uint2 *padj, int32_t *cnt, int32_t *pm, int32_t *tmp,
+                                  unsigned long long *caps, hipStream_t st) {
+    // cnt, pm: np * (n + 1) + 1 ints.  In partition-major order the entries
+    // k*(n+1)+n and the last stay 0, so the exclusive scan gives
+    // pm[k*(n+1)+n] = pm[(k+1)*(n+1)] (end of partition k's arcs).  The result
+    // pro is vertex-major: pro[u*np + k], u in [0, n].
+    const int64_t len = (int64_t)np * (n + 1) + 1;
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)len, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_part_count, dim3(row_grid(n)), dim3(kBlk), 0, st, n, ro, adj, np, psize, cnt);
+    hipLaunchKernelGGL(k_part_caps, dim3(grid_for(n, kBlk * 16, 4096)), dim3(kBlk), 0, st, n, np, cnt, caps);
+    e = scan_exclusive(cnt, len, pm, tmp, st);
+    if (e != hipSuccess) return e;
+    if (m > 0)
+        hipLaunchKernelGGL(k_part_scatter, dim3(row_grid(n)), dim3(kBlk), 0, st, n, ro, adj, psize, pm, padj);
+    hipLaunchKernelGGL(k_part_transpose, dim3(grid_for(((int64_t)n + 1) * np, kBlk * 4, 16384)), dim3(kBlk), 0, st,
+                       n, np, pm, pro);
+    return hipGetLastError();
+}
+
+hipError_t launch_canon_negzero(uint2 *adj, int32_t m, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_canon_negzero, dim3(grid_for(m, kBlk * 8, 16384)), dim3(kBlk), 0, st, adj, m);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // frontier workspace layout
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-size_t frontier_bytes(int64_t n) {
-    const int64_t ng = groups_for(n);
-    const int64_t nw = ng * kGroupWords;
-    const int64_t ns = (ng + 63) / 64;
+size_t frontier_bytes(const DevGraph &g) {
+    const int64_t ng = groups_for(g.n);
     size_t b = 0;
-    b += 2 * align256(nw * 8);
-    b += 2 * align256(ns * 8);
-    b += 4 * align256((size_t)(n > 0 ? n : 1) * 4);
+    b += 2 * align256((size_t)ng * kGroupVerts);
+    for (int k = 0; k < g.np; ++k) {
+        const size_t c = (size_t)(g.cap[k] > 0 ? g.cap[k] : 1);
+        b += align256(c * 8) + align256(c * 4);
+    }
     b += align256(kCtlWords * 8);
     return b;
 }
 
-void frontier_carve(Frontier &f, void *base, int64_t n) {
-    const int64_t ng = groups_for(n);
+void frontier_carve(Frontier &f, void *base, const DevGraph &g) {
+    const int64_t ng = groups_for(g.n);
     f.ngroups = (int32_t)ng;
-    f.nwords = ng * kGroupWords;
-    f.nsumw = (ng + 63) / 64;
+    f.nflag = ng * kGroupVerts;
+    f.np = g.np;
     char *p = static_cast<char *>(base);
     for (int i = 0; i < 2; ++i) {
-        f.bits[i] = reinterpret_cast<uint64_t *>(p);
-        p += align256(f.nwords * 8);
+        f.flags[i] = reinterpret_cast<uint8_t *>(p);
+        p += align256((size_t)f.nflag);
     }
-    for (int i = 0; i < 2; ++i) {
-        f.sum[i] = reinterpret_cast<uint64_t *>(p);
-        p += align256(f.nsumw * 8);
+    for (int k = 0; k < kMaxParts; ++k) {
+        f.qse[k] = nullptr;
+        f.qs[k] = nullptr;
     }
-    for (int i = 0; i < 2; ++i) {
-        f.q[i] = reinterpret_cast<int32_t *>(p);
-        p += align256((size_t)(n > 0 ? n : 1) * 4);
-        f.s[i] = reinterpret_cast<int32_t *>(p);
-        p += align256((size_t)(n > 0 ? n : 1) * 4);
+    for (int k = 0; k < g.np; ++k) {
+        const size_t c = (size_t)(g.cap[k] > 0 ? g.cap[k] : 1);
+        f.qse[k] = reinterpret_cast<uint2 *>(p);
+        p += align256(c * 8);
+        f.qs[k] = reinterpret_cast<int32_t *>(p);
+        p += align256(c * 4);
     }
     f.ctl = reinterpret_cast<unsigned long long *>(p);
 }

@@ -23,9 +23,9 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run(G, src, direction=0, loop=0, n=None):
+def run(G, src, direction=0, loop=0, n=None, layout=0):
     dist = torch.full((n or G.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
-    st = gr.gr_sssp_ex(G.handle, int(src), dist, direction=direction, loop=loop)
+    st = gr.gr_sssp_ex(G.handle, int(src), dist, direction=direction, loop=loop, layout=layout)
     torch.cuda.synchronize()
     return dist.cpu().numpy().view(np.uint32), st
 
@@ -38,18 +38,23 @@ def assert_same(got, want, tag):
             tag, len(bad), v, int(got[v]), int(want[v])))
 
 
-def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate")):
-    G = gr.Graph.from_csr(g)
+def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate"), flags=gr.GR_FORCE_PARTITION):
+    """Every direction policy, with both push layouts (plain CSR and partitioned)."""
+    G = gr.Graph.from_csr(g, flags=flags)
     info = G.info()
+    layouts = [gr.GR_LAYOUT_PLAIN] + ([gr.GR_LAYOUT_PARTITIONED] if info["partitions"] > 1 else [])
     try:
         for s in srcs:
             want = oracle.dijkstra(g, int(s))
-            for d in dirs:
-                if d in ("pull", "alternate") and not info["pull_enabled"]:
-                    continue
-                say("case %s src=%d dir=%s n=%d m=%d" % (tag, s, d, g.n, g.m))
-                got, st = run(G, s, DIRS[d])
-                assert_same(got, want, "%s src %d dir %s" % (tag, s, d))
+            for lay in layouts:
+                for d in dirs:
+                    if d in ("pull", "alternate") and not info["pull_enabled"]:
+                        continue
+                    if d == "pull" and lay != layouts[0]:
+                        continue  # pull does not use the push layout
+                    say("case %s src=%d dir=%s layout=%d n=%d m=%d" % (tag, s, d, lay, g.n, g.m))
+                    got, st = run(G, s, DIRS[d], layout=lay)
+                    assert_same(got, want, "%s src %d dir %s layout %d" % (tag, s, d, lay))
     finally:
         G.close()
 
@@ -113,10 +118,10 @@ def test_repeat_determinism():
     g = gg.rmat(13, 16, gseed=81, pseed=82, wseed=83, wtype=gg.W_F32)
     s = int(gg.pick_sources(g, 84, 1)[0])
     want = oracle.dijkstra(g, s)
-    G = gr.Graph.from_csr(g)
+    G = gr.Graph.from_csr(g, flags=gr.GR_FORCE_PARTITION)
     try:
         for i in range(10):
-            got, _ = run(G, s, DIRS["auto"])
+            got, _ = run(G, s, DIRS["auto"], layout=gr.GR_LAYOUT_PARTITIONED if i % 2 else gr.GR_LAYOUT_PLAIN)
             assert_same(got, want, "repeat %d" % i)
     finally:
         G.close()
@@ -164,6 +169,24 @@ def test_errors_on_gpu():
         Gp.close()
 
 
+def test_partition_layout_default_choice():
+    # random ids (R-MAT) and large n: partitioned; grid: neighbours are close, plain only
+    g = gg.rmat(17, 8, gseed=5, pseed=6, wseed=7)
+    G = gr.Graph.from_csr(g)
+    assert G.info()["partitions"] == 8
+    G.close()
+    g = gg.grid(400, wseed=8)
+    G = gr.Graph.from_csr(g)
+    assert G.info()["partitions"] == 1
+    G.close()
+    G = gr.Graph.from_csr(gg.grid(8, wseed=1), flags=gr.GR_NO_PARTITION)
+    dist = torch.empty(64, dtype=torch.int32, device="cuda")
+    with pytest.raises(gr.GrError) as ei:
+        gr.gr_sssp_ex(G.handle, 0, dist, layout=gr.GR_LAYOUT_PARTITIONED)
+    assert ei.value.status == gr.GR_ERR_INVALID_ARG
+    G.close()
+
+
 def test_symmetry_detection():
     sym = gg.rmat(10, 8, gseed=1, pseed=2, wseed=3)
     G = gr.Graph.from_csr(sym)
@@ -179,14 +202,14 @@ def test_symmetry_detection():
 
 def test_rmat20_config_f32():
     g, srcs = gg.workload("rmat20")
-    check_all_dirs(g, srcs, "rmat20", dirs=("auto", "push", "pull"))
+    check_all_dirs(g, srcs, "rmat20", dirs=("auto", "push", "pull"), flags=0)
 
 
 def test_road2048_config():
     g, srcs = gg.workload("road2048")
-    check_all_dirs(g, srcs, "road2048", dirs=("auto",))
+    check_all_dirs(g, srcs, "road2048", dirs=("auto",), flags=0)
 
 
 def test_rmat22_config_sampled_sources():
     g, srcs = gg.workload("rmat22")
-    check_all_dirs(g, srcs[:2], "rmat22", dirs=("auto", "push"))
+    check_all_dirs(g, srcs[:2], "rmat22", dirs=("auto", "push"), flags=0)
