@@ -149,7 +149,10 @@ typedef struct {
     int32_t max_iters;  /* iteration cap; 0 = n + 1 (never reached for w >= 0) */
     int32_t layout;     /* gr_layout */
     int32_t timing;     /* 1: time every operator launch with HIP events (stats *_us fields) */
-    int32_t reserved[2];
+    int32_t filter;     /* 0 auto, 1 visit the 4096-vertex groups holding flags (small frontiers),
+                           2 stream the per-partition member lists (large frontiers) */
+    int32_t barrier_timeout_us; /* device-driven loop: bound on one grid-barrier wait;
+                                   0 = 20 s.  Exceeding it ends the query with GR_ERR_HIP. */
 } gr_sssp_opts;
 
 typedef struct {

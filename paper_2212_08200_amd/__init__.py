@@ -78,7 +78,7 @@ class GrError(RuntimeError):
 class gr_sssp_opts(ctypes.Structure):
     _fields_ = [("loop", ctypes.c_int32), ("direction", ctypes.c_int32), ("alpha_x16", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("layout", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("filter", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32)]
 
 
 class gr_sssp_stats(ctypes.Structure):
@@ -230,9 +230,9 @@ def gr_sssp(g: int, src: int, dist_out, stream=None) -> None:
 
 
 def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
-               max_iters=0, layout=GR_LAYOUT_AUTO, timing=0) -> dict:
+               max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, barrier_timeout_us=0) -> dict:
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
-                     timing=timing)
+                     timing=timing, filter=filter, barrier_timeout_us=barrier_timeout_us)
     st = gr_sssp_stats()
     _check(lib().gr_sssp_ex(g, int(src), _ptr(dist_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()

@@ -77,6 +77,7 @@ extern "C" const char *gr_version(void) { return "gr 0.1 (gfx950)"; }
 struct DeviceInfo {
     int num_cu = 0;
     bool coop = false;
+    int wall_khz = 0;  // rate of the device's constant-rate clock
 };
 
 static std::mutex g_dev_mu;
@@ -90,6 +91,9 @@ static gr_status device_info(int dev, DeviceInfo *out) {
         int cu = 0, coop = 0;
         HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
         HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+        d.wall_khz = khz;
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
             uint64_t thr = UINT64_MAX;  // keep freed workspaces cached in the pool
@@ -135,6 +139,8 @@ struct gr_graph {
     uint2 *d_adj_in = nullptr;   // == d_adj when symmetric
     int32_t *d_pro = nullptr;
     uint2 *d_padj = nullptr;
+    int32_t *d_mem_u[2] = {nullptr, nullptr};  // membership lists: plain, partitioned
+    uint2 *d_mem_sd[2] = {nullptr, nullptr};
     bool pull = false;
     bool csc_separate = false;
     size_t dev_bytes = 0;
@@ -172,6 +178,10 @@ static void graph_free(gr_graph *g) {
     if (g->d_adj) (void)hipFree(g->d_adj);
     if (g->d_pro) (void)hipFree(g->d_pro);
     if (g->d_padj) (void)hipFree(g->d_padj);
+    for (int i = 0; i < 2; ++i) {
+        if (g->d_mem_u[i]) (void)hipFree(g->d_mem_u[i]);
+        if (g->d_mem_sd[i]) (void)hipFree(g->d_mem_sd[i]);
+    }
     delete g;
 }
 
@@ -196,6 +206,36 @@ struct Scratch {
         hipError_t _e = (call);                    \
         if (_e != hipSuccess) return hip_fail(_e, what); \
     } while (0)
+
+// Membership lists of a push layout (which vertices have arcs into each partition).
+static gr_status build_members(gr_graph *g, DevGraph &d, int which, hipStream_t st, Scratch &sc) {
+    const int32_t n = d.n, np = d.np;
+    const int64_t len = (int64_t)np * (n + 1) + 1;
+    int64_t total = 0;
+    for (int k = 0; k < np; ++k) total += d.cap[k];
+    int32_t *cnt = nullptr, *pos = nullptr, *tmp = nullptr;
+    long long *off = nullptr;
+    BUILD_TRY(sc.alloc(&cnt, sizeof(int32_t) * (size_t)len), "hipMalloc(member counts)");
+    BUILD_TRY(sc.alloc(&pos, sizeof(int32_t) * (size_t)len), "hipMalloc(member offsets)");
+    BUILD_TRY(sc.alloc(&tmp, sizeof(int32_t) * scan_tmp_ints(len)), "hipMalloc(scan)");
+    BUILD_TRY(sc.alloc(&off, sizeof(long long) * (kMaxParts + 1)), "hipMalloc(member offsets)");
+    BUILD_TRY(hipMalloc(&g->d_mem_u[which], sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1)),
+              "hipMalloc(members)");
+    BUILD_TRY(hipMalloc(&g->d_mem_sd[which], sizeof(uint2) * (size_t)std::max<int64_t>(total, 1)),
+              "hipMalloc(members)");
+    BUILD_TRY(launch_members(n, np, d.pro, cnt, pos, tmp, g->d_mem_u[which], g->d_mem_sd[which], off, st),
+              "membership lists");
+    long long hoff[kMaxParts + 1] = {0};
+    BUILD_TRY(hipMemcpyAsync(hoff, off, sizeof(long long) * (np + 1), hipMemcpyDeviceToHost, st), "copy offsets");
+    BUILD_TRY(hipStreamSynchronize(st), "membership lists");
+    if (hoff[np] != total) return fail(GR_ERR_HIP, "membership lists hold %lld entries, expected %lld", hoff[np],
+                                       (long long)total);
+    d.mem_u = g->d_mem_u[which];
+    d.mem_sd = g->d_mem_sd[which];
+    for (int k = 0; k <= kMaxParts; ++k) d.mem_off[k] = k <= np ? hoff[k] : hoff[np];
+    g->dev_bytes += (size_t)total * 12;
+    return GR_OK;
+}
 
 static gr_status build_partition(gr_graph *g, int32_t n, int32_t m, hipStream_t st, Scratch &sc) {
     const int np = kMaxParts;
@@ -225,7 +265,7 @@ static gr_status build_partition(gr_graph *g, int32_t n, int32_t m, hipStream_t 
     for (int k = 0; k < kMaxParts; ++k) d.cap[k] = (int32_t)hc[k];
     g->has_part = true;
     g->dev_bytes += sizeof(int32_t) * (size_t)len + sizeof(uint2) * (size_t)std::max(m, 1);
-    return GR_OK;
+    return build_members(g, d, 1, st, sc);
 }
 
 static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *ro, const int32_t *col,
@@ -317,6 +357,10 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
     d.padj = g->d_adj;
     for (int k = 0; k < kMaxParts; ++k) d.cap[k] = 0;
     d.cap[0] = nonempty;
+    {
+        gr_status s = build_members(g, d, 0, st, sc);
+        if (s != GR_OK) return s;
+    }
 
     const bool want_part = !(flags & GR_NO_PARTITION) &&
                            ((flags & GR_FORCE_PARTITION) || (n >= kPartitionMinN && g->locality < 0.5));
@@ -379,7 +423,9 @@ extern "C" gr_status gr_graph_info(const gr_graph *g, int32_t *n, int32_t *m, in
 // ---------------------------------------------------------------------------
 // single-source loop drivers
 
-static constexpr int32_t kDefaultAlphaX16 = 32;  // pull when E >= m / 2
+// AUTO direction: pull when frontier out-edges * alpha_x16 >= 16 * m.  The
+// default never pulls: on the measured graphs push is faster every round.
+static constexpr int32_t kDefaultAlphaX16 = 0;
 
 struct RunCfg {
     int loop;
@@ -388,6 +434,8 @@ struct RunCfg {
     int64_t max_iters;
     bool timing;
     int layout;
+    int filter;
+    int64_t barrier_timeout_us;
     const DevGraph *dg;
 };
 
@@ -410,6 +458,9 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
     rc->dg = (layout == GR_LAYOUT_PLAIN || !g->has_part) ? &g->plain : &g->part;
     rc->layout = rc->dg->np > 1 ? GR_LAYOUT_PARTITIONED : GR_LAYOUT_PLAIN;
     rc->timing = o && o->timing;
+    rc->filter = o ? o->filter : 0;
+    rc->barrier_timeout_us = (o && o->barrier_timeout_us > 0) ? o->barrier_timeout_us : 20000000;
+    if (rc->filter < 0 || rc->filter > 2) return fail(GR_ERR_INVALID_ARG, "unknown filter mode %d", rc->filter);
     return GR_OK;
 }
 
@@ -419,7 +470,7 @@ static bool choose_pull(const gr_graph *g, const RunCfg &rc, int64_t iter, int64
         case GR_DIR_PUSH: return false;
         case GR_DIR_PULL: return true;
         case GR_DIR_ALTERNATE: return (iter & 1) != 0;
-        default: return E * rc.alpha_x16 >= (int64_t)16 * g->plain.m;
+        default: return rc.alpha_x16 > 0 && E * rc.alpha_x16 >= (int64_t)16 * g->plain.m;
     }
 }
 
@@ -492,7 +543,9 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
             local.push_launches++;
         }
         if (timed) (void)hipEventRecord(ev[1], st);
-        if (e == hipSuccess) e = launch_filter(dg, f, iter, nullptr, st);
+        // the streaming filter pays off once the next frontier is likely large
+        const bool dense = rc.filter == 2 || (rc.filter == 0 && c.Fsum() * kDenseRatio >= (int64_t)dg.n);
+        if (e == hipSuccess) e = launch_filter(dg, f, iter, nullptr, dense, st);
         if (timed) (void)hipEventRecord(ev[2], st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hp, counters_after(f, iter), sizeof(unsigned long long) * kMaxParts,
@@ -519,6 +572,66 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
     return status;
 }
 
+static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
+                                gr_sssp_stats *stats) {
+    DeviceInfo di;
+    gr_status s = device_info(g->device, &di);
+    if (s != GR_OK) return s;
+    if (!di.coop) return fail(GR_ERR_HIP, "device does not support cooperative launches");
+    const DevGraph &dg = *rc.dg;
+    PersistentCfg cfg;
+    cfg.grid = persistent_grid(dg, di.num_cu);
+    if (cfg.grid < kMaxParts) return fail(GR_ERR_HIP, "no co-resident grid for the device-driven loop");
+    cfg.max_iters = (int32_t)std::min<int64_t>(rc.max_iters, INT32_MAX);
+    cfg.alpha_x16 = rc.alpha_x16;
+    cfg.direction = rc.direction;
+    cfg.filter = rc.filter;
+    cfg.spin_ticks = (uint64_t)rc.barrier_timeout_us * (uint64_t)di.wall_khz / 1000ull;
+    unsigned long long *hp = pinned_slot();
+    if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
+    void *ws = nullptr;
+    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
+    Frontier f;
+    frontier_carve(f, ws, dg);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool timed = rc.timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
+    hipError_t e = launch_init(dg, dist, src, f, st);
+    if (e == hipSuccess && timed) e = hipEventRecord(ev[0], st);
+    if (e == hipSuccess) e = launch_persistent(dg, dist, f, cfg, st);
+    if (e == hipSuccess && timed) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp, f.ctl + kLoopStateWord, sizeof(LoopState), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    LoopState ls{};
+    if (e == hipSuccess) std::memcpy(&ls, hp, sizeof ls);
+    gr_sssp_stats local{};
+    local.loop = GR_LOOP_PERSISTENT;
+    local.layout = rc.layout;
+    local.iterations = (int32_t)ls.iter;
+    local.pull_iterations = (int32_t)ls.pull_iters;
+    local.edges_pushed = (int64_t)ls.edges_pushed;
+    local.arcs_pulled = (int64_t)ls.arcs_pulled;
+    local.frontier_sum = (int64_t)ls.frontier_sum;
+    local.frontier_max = (int32_t)ls.frontier_max;
+    local.push_launches = 1;
+    if (timed) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+        local.push_us = 1e3 * ms;  // the whole loop is one launch
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    hipError_t e2 = hipFreeAsync(ws, st);
+    if (e != hipSuccess) return hip_fail(e, "device-driven loop");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    if (stats) *stats = local;
+    if (ls.status == 2) return fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)rc.max_iters);
+    if (ls.status == 3) return fail(GR_ERR_HIP, "device-driven loop: a grid-barrier wait exceeded %lld us",
+                                    (long long)rc.barrier_timeout_us);
+    if (ls.status != 1) return fail(GR_ERR_HIP, "device-driven loop ended in state %llu", ls.status);
+    return GR_OK;
+}
+
 extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, void *stream,
                                 const gr_sssp_opts *opts, gr_sssp_stats *stats) {
     if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
@@ -527,6 +640,10 @@ extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, 
     RunCfg rc;
     gr_status s = check_opts(g, opts, &rc);
     if (s != GR_OK) return s;
+    int loop = rc.loop;
+    if (loop == GR_LOOP_AUTO) loop = GR_LOOP_HOST;
+    if (loop == GR_LOOP_PERSISTENT)
+        return run_persistent(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
     return run_host_loop(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
 }
 
@@ -564,7 +681,7 @@ static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, ui
     if (e == hipSuccess) e = hipMemcpyAsync(w.srcs, sv.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_batch_init(dg, w, k, st);
     // The filter of "iteration -1" turns the source flags into frontier 0.
-    if (e == hipSuccess) e = launch_filter(dg, w.f, -1, nullptr, st);
+    if (e == hipSuccess) e = launch_filter(dg, w.f, -1, nullptr, false, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(hp, counters_after(w.f, -1), sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -578,7 +695,7 @@ static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, ui
             break;
         }
         e = launch_batch_push(dg, w, iter, F, E, di.num_cu, st);
-        if (e == hipSuccess) e = launch_filter(dg, w.f, iter, w.mask[iter & 1], st);
+        if (e == hipSuccess) e = launch_filter(dg, w.f, iter, w.mask[iter & 1], (int64_t)F * kDenseRatio >= dg.n, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hp, counters_after(w.f, iter), sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -39,10 +39,16 @@ struct DevGraph {
     const int32_t *ro_in;
     const uint2 *adj_in;
     int32_t np;     // 1 or kMaxParts
-    int32_t psize;  // vertices per partition (multiple of kGroupVerts)
+    int32_t psize;  // vertices per partition
     const int32_t *pro;
     const uint2 *padj;
     int32_t cap[kMaxParts];  // max frontier entries per partition
+    // Members of partition k: the vertices u with arcs into it, in increasing
+    // order, as mem_u[i] = u and mem_sd[i] = (first arc, arc count), for
+    // i in [mem_off[k], mem_off[k+1]).  Used by the streaming filter.
+    const int32_t *mem_u;
+    const uint2 *mem_sd;
+    int64_t mem_off[kMaxParts + 1];
 };
 
 // Per-query frontier workspace (device memory).
@@ -65,14 +71,16 @@ struct Frontier {
 };
 
 constexpr int kCtlSlots = 3;
-constexpr int kCtlWords = 64;  // 3 x 8 counters, then LoopState
+constexpr int kCtlWords = 64;       // 3 x 8 counters, then LoopState
+constexpr int kLoopStateWord = 32;  // LoopState at ctl + 32
+constexpr int64_t kDenseRatio = 64;  // streaming filter when |frontier| >= n / 64
 
-// Device-driven loop state, at ctl + 32.
+// Device-driven loop state.
 struct LoopState {
     unsigned long long bar_count;  // grid barrier arrivals
     unsigned long long bar_gen;    // grid barrier generation
     unsigned long long iter;       // iterations done
-    unsigned long long status;     // 0 running, 1 done, 2 iteration cap
+    unsigned long long status;     // 0 running, 1 done, 2 iteration cap, 3 barrier wait timed out
     unsigned long long edges_pushed;
     unsigned long long arcs_pulled;
     unsigned long long frontier_sum;
@@ -97,7 +105,10 @@ hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int
                        int num_cu, hipStream_t st);
 hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st);
 // zmask: optional per-vertex 64-bit masks (batched queries) cleared by the filter.
-hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uint64_t *zmask, hipStream_t st);
+// dense: stream the membership lists (large frontiers) instead of visiting
+// the 4096-vertex groups that hold flags (small frontiers).
+hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uint64_t *zmask, bool dense,
+                         hipStream_t st);
 // Device address of the counter slot filled by the filter of iteration `iter`.
 unsigned long long *counters_after(const Frontier &f, int64_t iter);
 
@@ -105,12 +116,15 @@ unsigned long long *counters_after(const Frontier &f, int64_t iter);
 struct PersistentCfg {
     int32_t max_iters;
     int32_t alpha_x16;
-    int32_t direction;  // gr_direction
-    int32_t grid;       // blocks (co-resident)
+    int32_t direction;    // gr_direction
+    int32_t filter;       // 0 auto, 1 group, 2 streaming
+    int32_t grid;         // co-resident blocks, a multiple of kMaxParts
+    uint64_t spin_ticks;  // grid-barrier wait bound, in wall_clock64 ticks
 };
-hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, int32_t src, const Frontier &f,
-                             const PersistentCfg &cfg, hipStream_t st);
-int persistent_max_blocks_per_cu();
+// Largest co-resident grid for the graph's layout (0 if none).
+int persistent_grid(const DevGraph &g, int num_cu);
+hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg,
+                             hipStream_t st);
 
 // Graph build helpers.
 hipError_t launch_pack_arcs(const int32_t *col, const uint32_t *w, int32_t m, uint2 *adj, hipStream_t st);
@@ -127,6 +141,11 @@ hipError_t launch_symmetry_check(int32_t n, const int32_t *ro, const uint2 *adj,
 hipError_t launch_partition_build(int32_t n, int32_t m, const int32_t *ro, const uint2 *adj, int32_t np,
                                   int32_t psize, int32_t *pro, uint2 *padj, int32_t *cnt, int32_t *pm, int32_t *tmp,
                                   unsigned long long *caps, hipStream_t st);
+// Membership lists of a push layout (see DevGraph): cnt needs np*(n+1)+1 ints,
+// pos the same, tmp scan_tmp_ints(np*(n+1)+1); mem_u / mem_sd hold
+// sum(cap) entries; off receives np + 1 offsets (device, int64).
+hipError_t launch_members(int32_t n, int32_t np, const int32_t *pro, int32_t *cnt, int32_t *pos, int32_t *tmp,
+                          int32_t *mem_u, uint2 *mem_sd, long long *off, hipStream_t st);
 // Fraction numerator for the locality test: arcs with |u - v| < span.
 hipError_t launch_locality(int32_t n, const int32_t *ro, const uint2 *adj, int32_t span, unsigned long long *near,
                            hipStream_t st);

@@ -30,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace gr {
 
 
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
 // [j*per, min(E, (j+1)*per)).  It finds the entry holding its first rank with
 // a 256-way search, then walks windows of up to kWin consecutive entries
 // staged in LDS; each lane maps its rank to an entry by binary search in LDS.
-constexpr int kPushItems = 4;
+constexpr int kPushItems = 8;
 
 struct PushArgs {
     const uint2 *padj;
@@ -121,21 +123,21 @@ struct PushArgs {
     uint8_t *nflags;
 };
 
-template <int WT, int NP>
-__global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
+// Arc ranks [j*per, min(E, (j+1)*per)) of one partition's frontier
+// (F entries (first arc, u) with arc-count prefix sums s), by one block.
+template <int WT>
+__device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint32_t *__restrict__ dist,
+                                           const uint2 *__restrict__ qse, const int32_t *__restrict__ s,
+                                           int32_t F, int32_t E, int32_t per, int64_t j,
+                                           uint8_t *__restrict__ nflags) {
     __shared__ int32_t sS[kWin + 1];
     __shared__ uint32_t sRow[kWin];
     __shared__ uint32_t sDu[kWin];
 
-    const int k = (NP == 1) ? 0 : (int)(blockIdx.x % NP);
-    const int64_t j = (NP == 1) ? blockIdx.x : blockIdx.x / NP;
-    const int32_t F = a.F[k], E = a.E[k], per = a.per[k];
     const int64_t beg64 = j * per;
     if (F <= 0 || beg64 >= E) return;
     const int32_t beg = (int32_t)beg64;
     const int32_t end = (int32_t)min<int64_t>(beg64 + per, E);
-    const int32_t *__restrict__ s = a.qs[k];
-    const uint2 *__restrict__ qse = a.qse[k];
 
     int32_t i0 = find_entry(s, F, beg);
     int32_t e = beg;
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
             const uint2 q = qse[i0 + t];
             sS[t] = s[i0 + t];
             sRow[t] = q.x;
-            sDu[t] = a.dist[q.y];
+            sDu[t] = dist[q.y];
         }
         // sS[cnt] bounds the window's ranks; entries past it are padded with
         // INT32_MAX so that the search below needs no bounds test.
@@ -178,21 +180,28 @@ __global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
             uint2 arc[kPushItems];
 #pragma unroll
             for (int it = 0; it < kPushItems; ++it)
-                arc[it] = load_arc(a.padj + sRow[pos[it]] + (uint32_t)(xr[it] - sS[pos[it]]));
+                arc[it] = load_arc(padj + sRow[pos[it]] + (uint32_t)(xr[it] - sS[pos[it]]));
             uint32_t nd[kPushItems], cur[kPushItems];
 #pragma unroll
             for (int it = 0; it < kPushItems; ++it) {
                 nd[it] = plus<WT>(sDu[pos[it]], arc[it].y);
-                cur[it] = a.dist[arc[it].x];
+                cur[it] = dist[arc[it].x];
             }
 #pragma unroll
             for (int it = 0; it < kPushItems; ++it)
-                if (x0 + it * kBlk < wend && nd[it] < cur[it]) relax_commit(a.dist, a.nflags, arc[it].x, nd[it]);
+                if (x0 + it * kBlk < wend && nd[it] < cur[it]) relax_commit(dist, nflags, arc[it].x, nd[it]);
         }
         i0 += cnt;
         e = wend;
         __syncthreads();  // window reuse
     }
+}
+
+template <int WT, int NP>
+__global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
+    const int k = (NP == 1) ? 0 : (int)(blockIdx.x % NP);
+    const int64_t j = (NP == 1) ? blockIdx.x : blockIdx.x / NP;
+    push_range<WT>(a.padj, a.dist, a.qse[k], a.qs[k], a.F[k], a.E[k], a.per[k], j, a.nflags);
 }
 
 // ---------------------------------------------------------------------------
@@ -205,12 +214,13 @@ __global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
 constexpr int kPullItems = 4;
 
 template <int WT>
-__global__ __launch_bounds__(kBlk) void k_pull(int32_t n, const int32_t *__restrict__ ro_in,
-                                               const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
-                                               const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags) {
+__device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict__ ro_in,
+                                           const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
+                                           const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags,
+                                           int64_t vb) {
     __shared__ int32_t sOff[kBlk + 1];
     __shared__ uint32_t sMin[kBlk];
-    const int32_t v0 = blockIdx.x * kBlk;
+    const int32_t v0 = (int32_t)(vb * kBlk);
     const int32_t nv = min(kBlk, n - v0);
     // sOff[0..nv] are the owners' arc offsets; entries past nv are padded with
     // INT32_MAX so that the owner search needs no bounds test.
@@ -264,6 +274,13 @@ __global__ __launch_bounds__(kBlk) void k_pull(int32_t n, const int32_t *__restr
     }
 }
 
+template <int WT>
+__global__ __launch_bounds__(kBlk) void k_pull(int32_t n, const int32_t *__restrict__ ro_in,
+                                               const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
+                                               const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags) {
+    pull_block<WT>(n, ro_in, adj_in, dist, cflags, nflags, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // filter: one block per (group of 4096 vertices, partition k); block b works
 // on group b / np and partition b % np, so with 8 partitions the queue of
@@ -288,23 +305,27 @@ struct FilterArgs {
     unsigned long long *ctl_zero;
 };
 
-__global__ __launch_bounds__(kBlk) void k_filter(FilterArgs a) {
+// a: the iteration-independent arguments (kernel-argument resident); the
+// flags and counter slots of the iteration are passed separately.
+__device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t vb, const uint8_t *__restrict__ nflags,
+                                             uint8_t *__restrict__ cflags, unsigned long long *ctl_next,
+                                             unsigned long long *ctl_zero) {
     __shared__ unsigned long long sh_base;
     const int np = a.np;
-    const int32_t g = blockIdx.x / np;
-    const int k = blockIdx.x % np;
-    if (blockIdx.x == 0 && threadIdx.x < kMaxParts) a.ctl_zero[threadIdx.x] = 0ull;
+    const int32_t g = (int32_t)(vb / np);
+    const int k = (int)(vb % np);
+    if (vb == 0 && threadIdx.x < kMaxParts) ctl_zero[threadIdx.x] = 0ull;
     if (a.zmask && k == 0)
         for (int t = threadIdx.x; t < kGroupVerts; t += kBlk) a.zmask[(int64_t)g * kGroupVerts + t] = 0ull;
     {
         // this block's share of the group's current flags: 4096 / np bytes
         const int share16 = kGroupVerts / 16 / np;
         if ((int)threadIdx.x < share16)
-            reinterpret_cast<uint4 *>(a.cflags)[(int64_t)g * (kGroupVerts / 16) + k * share16 + threadIdx.x] =
+            reinterpret_cast<uint4 *>(cflags)[(int64_t)g * (kGroupVerts / 16) + k * share16 + threadIdx.x] =
                 make_uint4(0u, 0u, 0u, 0u);
     }
     const int64_t base = (int64_t)g * kGroupVerts + threadIdx.x * kVpt;
-    const uint4 fw = reinterpret_cast<const uint4 *>(a.nflags)[base >> 4];
+    const uint4 fw = reinterpret_cast<const uint4 *>(nflags)[base >> 4];
     uint32_t mask16 = 0;
 #pragma unroll
     for (int b = 0; b < 16; ++b) {
@@ -326,7 +347,7 @@ __global__ __launch_bounds__(kBlk) void k_filter(FilterArgs a) {
     }
     block_scan<2>(x, tot);
     if (threadIdx.x == 0)
-        sh_base = tot[0] ? atomicAdd(a.ctl_next + k, (unsigned long long)tot[0] | ((unsigned long long)tot[1] << 32))
+        sh_base = tot[0] ? atomicAdd(ctl_next + k, (unsigned long long)tot[0] | ((unsigned long long)tot[1] << 32))
                          : 0ull;
     __syncthreads();
     int32_t pos = (int32_t)(sh_base & 0xFFFFFFFFull) + x[0];
@@ -346,6 +367,250 @@ __global__ __launch_bounds__(kBlk) void k_filter(FilterArgs a) {
             }
         }
     }
+}
+
+__global__ __launch_bounds__(kBlk) void k_filter(FilterArgs a) {
+    filter_group(a, blockIdx.x, a.nflags, a.cflags, a.ctl_next, a.ctl_zero);
+}
+
+// Streaming filter for large frontiers: block b works on partition b % np and
+// on chunk b / np of that partition's membership list (kDenseChunk members,
+// in vertex order).  Each member whose frontier flag is set becomes an entry
+// (first arc, u); one atomic per block reserves the slice.  Every block also
+// clears its share of the current frontier's flags.
+constexpr int kDenseItems = 4;
+constexpr int kDenseChunk = kBlk * kDenseItems;
+
+struct DenseFilterArgs {
+    int32_t np;
+    int32_t chunks;  // chunks of the longest list
+    const int32_t *mem_u;
+    const uint2 *mem_sd;
+    long long off[kMaxParts + 1];
+    const uint8_t *nflags;
+    uint8_t *cflags;
+    int64_t clear16;  // uint4 words of flags each block clears
+    int64_t nflag16;
+    uint64_t *zmask;  // when set: per-vertex masks to clear (same share as the flags)
+    uint2 *qse[kMaxParts];
+    int32_t *qs[kMaxParts];
+    unsigned long long *ctl_next;
+    unsigned long long *ctl_zero;
+};
+
+__device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t vb, const uint8_t *__restrict__ nflags,
+                                             uint8_t *__restrict__ cflags, uint64_t *zmask,
+                                             unsigned long long *ctl_next, unsigned long long *ctl_zero) {
+    __shared__ unsigned long long sh_base;
+    const int np = a.np;
+    const int k = (int)(vb % np);
+    const int64_t j = vb / np;
+    if (vb == 0 && threadIdx.x < kMaxParts) ctl_zero[threadIdx.x] = 0ull;
+    {
+        const int64_t c0 = vb * a.clear16;
+        const int64_t c1 = min(c0 + a.clear16, a.nflag16);
+        for (int64_t w = c0 + threadIdx.x; w < c1; w += kBlk) {
+            reinterpret_cast<uint4 *>(cflags)[w] = make_uint4(0u, 0u, 0u, 0u);
+            if (zmask)
+                for (int q = 0; q < 16; ++q) zmask[w * 16 + q] = 0ull;
+        }
+    }
+    const int64_t lo = a.off[k] + j * kDenseChunk;
+    const int64_t hi = min((int64_t)a.off[k + 1], lo + kDenseChunk);
+    if (lo >= hi) return;  // uniform per block
+    // thread t takes members lo + t*kDenseItems ... (consecutive, vertex order)
+    const int64_t m0 = lo + (int64_t)threadIdx.x * kDenseItems;
+    int32_t u[kDenseItems];
+    uint2 sd[kDenseItems];
+    bool on[kDenseItems];
+#pragma unroll
+    for (int it = 0; it < kDenseItems; ++it) {
+        const int64_t m = min(m0 + it, hi - 1);
+        u[it] = a.mem_u[m];
+        sd[it] = a.mem_sd[m];
+    }
+    int32_t x[2] = {0, 0}, tot[2];
+#pragma unroll
+    for (int it = 0; it < kDenseItems; ++it) {
+        on[it] = (m0 + it < hi) && nflags[u[it]] != 0;
+        if (on[it]) {
+            x[0] += 1;
+            x[1] += (int32_t)sd[it].y;
+        }
+    }
+    block_scan<2>(x, tot);
+    if (threadIdx.x == 0)
+        sh_base = tot[0] ? atomicAdd(ctl_next + k, (unsigned long long)tot[0] | ((unsigned long long)tot[1] << 32))
+                         : 0ull;
+    __syncthreads();
+    int32_t pos = (int32_t)(sh_base & 0xFFFFFFFFull) + x[0];
+    int32_t spos = (int32_t)(sh_base >> 32) + x[1];
+#pragma unroll
+    for (int it = 0; it < kDenseItems; ++it) {
+        if (on[it]) {
+            a.qse[k][pos] = make_uint2(sd[it].x, (uint32_t)u[it]);
+            a.qs[k][pos] = spos;
+            ++pos;
+            spos += (int32_t)sd[it].y;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void k_filter_dense(DenseFilterArgs a) {
+    filter_dense(a, blockIdx.x, a.nflags, a.cflags, a.zmask, a.ctl_next, a.ctl_zero);
+}
+
+// ---------------------------------------------------------------------------
+// Device-driven loop: one cooperative launch runs every iteration (advance,
+// grid barrier, filter, grid barrier, convergence test) without returning to
+// the host.  All blocks are co-resident (cooperative launch), block b stays
+// on XCD b % 8 for the whole query, so its partition's distances stay in
+// that XCD's L2 across iterations.
+
+// Grid barrier: arrival counter + generation.  Thread 0 of each block
+// publishes the block's writes with an agent-scope fence, arrives, and waits
+// for the generation to move; the last arrival resets the counter and moves
+// it.  The wait is bounded: after spin_ticks of the constant-rate clock the
+// block marks the loop failed (status 3) and moves the generation itself, so
+// that every block leaves instead of waiting forever.  Returns false once the
+// loop has failed.
+__device__ __forceinline__ bool grid_sync(LoopState *ls, unsigned nblocks, uint64_t spin_ticks) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long g = __hip_atomic_load(&ls->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned long long arrived =
+            __hip_atomic_fetch_add(&ls->bar_count, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
+        if (arrived == nblocks) {
+            __hip_atomic_store(&ls->bar_count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ls->bar_gen, g + 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&ls->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > spin_ticks) {
+                    __hip_atomic_store(&ls->status, 3ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&ls->bar_gen, g + 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        ok = __hip_atomic_load(&ls->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 3ull;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+struct PersistArgs {
+    FilterArgs fg;        // iteration-independent filter arguments
+    DenseFilterArgs fd;
+    const uint2 *padj;
+    uint32_t *dist;
+    const int32_t *ro_in;
+    const uint2 *adj_in;
+    uint8_t *flags[2];
+    unsigned long long *ctl;
+    int32_t n, m, ngroups;
+    int32_t max_iters, alpha_x16, direction, filter;
+    uint64_t spin_ticks;
+};
+
+template <int WT, int NP>
+__global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
+    LoopState *ls = reinterpret_cast<LoopState *>(a.ctl + kLoopStateWord);
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int kb = (int)(b % NP);
+    const int64_t jb = b / NP, B = G / NP;
+    for (int64_t iter = 0;; ++iter) {
+        const unsigned long long *cur = a.ctl + ((iter % kCtlSlots) * kMaxParts);
+        int64_t Fs = 0, Es = 0;
+        int32_t Fk = 0, Ek = 0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const unsigned long long c = __hip_atomic_load(cur + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int32_t f = (int32_t)(c & 0xFFFFFFFFull), e = (int32_t)(c >> 32);
+            Fs += f;
+            Es += e;
+            if (k == kb) {
+                Fk = f;
+                Ek = e;
+            }
+        }
+        if (Fs == 0 || iter >= a.max_iters) {
+            if (b == 0 && threadIdx.x == 0) {
+                ls->status = Fs == 0 ? 1ull : 2ull;
+                ls->iter = (unsigned long long)iter;
+            }
+            break;
+        }
+        bool pull;
+        switch (a.direction) {
+            case 1: pull = false; break;
+            case 2: pull = true; break;
+            case 3: pull = (iter & 1) != 0; break;
+            default: pull = a.alpha_x16 > 0 && Es * a.alpha_x16 >= (int64_t)16 * a.m;
+        }
+        uint8_t *cf = a.flags[iter & 1];
+        uint8_t *nf = a.flags[(iter + 1) & 1];
+        if (pull) {
+            const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
+            for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
+        } else {
+            const int32_t per = (int32_t)max<int64_t>(1, ((int64_t)Ek + B - 1) / B);
+            push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], Fk, Ek, per, jb, nf);
+        }
+        if (!grid_sync(ls, (unsigned)G, a.spin_ticks)) break;
+        unsigned long long *cn = a.ctl + (((iter + 1) % kCtlSlots) * kMaxParts);
+        unsigned long long *cz = a.ctl + (((iter + 2) % kCtlSlots) * kMaxParts);
+        const bool dense = a.filter == 2 || (a.filter == 0 && Fs * kDenseRatio >= a.n);
+        if (dense) {
+            const int64_t nvb = (int64_t)a.fd.chunks * NP;
+            for (int64_t vb = b; vb < nvb; vb += G) filter_dense(a.fd, vb, nf, cf, nullptr, cn, cz);
+        } else {
+            const int64_t nvb = (int64_t)a.ngroups * NP;
+            for (int64_t vb = b; vb < nvb; vb += G) filter_group(a.fg, vb, nf, cf, cn, cz);
+        }
+        if (b == 0 && threadIdx.x == 0) {
+            ls->frontier_sum += (unsigned long long)Fs;
+            if ((unsigned long long)Fs > ls->frontier_max) ls->frontier_max = (unsigned long long)Fs;
+            if (pull) {
+                ls->arcs_pulled += (unsigned long long)a.m;
+                ls->pull_iters += 1ull;
+            } else {
+                ls->edges_pushed += (unsigned long long)Es;
+            }
+        }
+        if (!grid_sync(ls, (unsigned)G, a.spin_ticks)) break;
+    }
+}
+
+// Membership lists: flag[k*(n+1)+u] = 1 when u has arcs into partition k.
+__global__ void k_member_flags(int32_t n, int32_t np, const int32_t *__restrict__ pro, int32_t *__restrict__ cnt) {
+    const int64_t total = (int64_t)np * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int64_t k = i / n, u = i % n;
+        cnt[k * ((int64_t)n + 1) + u] = pro[(u + 1) * np + k] > pro[u * np + k] ? 1 : 0;
+    }
+}
+
+__global__ void k_member_scatter(int32_t n, int32_t np, const int32_t *__restrict__ pro,
+                                 const int32_t *__restrict__ cnt, const int32_t *__restrict__ pos,
+                                 int32_t *__restrict__ mem_u, uint2 *__restrict__ mem_sd, long long *off) {
+    const int64_t total = (int64_t)np * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int64_t k = i / n, u = i % n;
+        const int64_t c = k * ((int64_t)n + 1) + u;
+        if (cnt[c]) {
+            const int32_t st = pro[u * np + k];
+            mem_u[pos[c]] = (int32_t)u;
+            mem_sd[pos[c]] = make_uint2((uint32_t)st, (uint32_t)(pro[(u + 1) * np + k] - st));
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x <= np) off[threadIdx.x] = pos[(int64_t)threadIdx.x * ((int64_t)n + 1)];
 }
 
 // ---------------------------------------------------------------------------
@@ -566,6 +831,8 @@ static inline int grid_for(int64_t items, int per_block, int cap) {
     return (int)b;
 }
 
+static hipError_t scan_exclusive(const int32_t *in, int64_t len, int32_t *out, int32_t *tmp, hipStream_t st);
+
 static inline int slot_of(int64_t i) { return (int)(((i % kCtlSlots) + kCtlSlots) % kCtlSlots); }
 
 unsigned long long *counters_after(const Frontier &f, int64_t iter) { return f.ctl + slot_of(iter + 1) * kMaxParts; }
@@ -647,9 +914,34 @@ hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int
     return hipGetLastError();
 }
 
-hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uint64_t *zmask, hipStream_t st) {
-    FilterArgs a;
+hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uint64_t *zmask, bool dense,
+                         hipStream_t st) {
     const int p = (int)(iter & 1);
+    if (dense) {
+        DenseFilterArgs a;
+        a.np = g.np;
+        int64_t maxlen = 0;
+        for (int k = 0; k < g.np; ++k) maxlen = std::max<int64_t>(maxlen, g.mem_off[k + 1] - g.mem_off[k]);
+        a.chunks = (int32_t)std::max<int64_t>(1, (maxlen + kDenseChunk - 1) / kDenseChunk);
+        const int64_t blocks = (int64_t)a.chunks * g.np;
+        a.mem_u = g.mem_u;
+        a.mem_sd = g.mem_sd;
+        for (int k = 0; k <= kMaxParts; ++k) a.off[k] = k <= g.np ? g.mem_off[k] : g.mem_off[g.np];
+        a.nflags = f.flags[p ^ 1];
+        a.cflags = f.flags[p];
+        a.nflag16 = f.nflag / 16;
+        a.clear16 = (a.nflag16 + blocks - 1) / blocks;
+        a.zmask = zmask;
+        for (int k = 0; k < kMaxParts; ++k) {
+            a.qse[k] = f.qse[k];
+            a.qs[k] = f.qs[k];
+        }
+        a.ctl_next = f.ctl + slot_of(iter + 1) * kMaxParts;
+        a.ctl_zero = f.ctl + slot_of(iter + 2) * kMaxParts;
+        hipLaunchKernelGGL(k_filter_dense, dim3((unsigned)blocks), dim3(kBlk), 0, st, a);
+        return hipGetLastError();
+    }
+    FilterArgs a;
     a.np = g.np;
     a.pro = g.pro;
     a.zmask = zmask;
@@ -662,6 +954,19 @@ hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uin
     a.ctl_next = f.ctl + slot_of(iter + 1) * kMaxParts;
     a.ctl_zero = f.ctl + slot_of(iter + 2) * kMaxParts;
     hipLaunchKernelGGL(k_filter, dim3(f.ngroups * g.np), dim3(kBlk), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_members(int32_t n, int32_t np, const int32_t *pro, int32_t *cnt, int32_t *pos, int32_t *tmp,
+                          int32_t *mem_u, uint2 *mem_sd, long long *off, hipStream_t st) {
+    const int64_t len = (int64_t)np * (n + 1) + 1;
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)len, st);
+    if (e != hipSuccess) return e;
+    const int grid = grid_for((int64_t)np * n, kBlk * 4, 16384);
+    hipLaunchKernelGGL(k_member_flags, dim3(grid), dim3(kBlk), 0, st, n, np, pro, cnt);
+    e = scan_exclusive(cnt, len, pos, tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_member_scatter, dim3(grid), dim3(kBlk), 0, st, n, np, pro, cnt, pos, mem_u, mem_sd, off);
     return hipGetLastError();
 }
 
@@ -758,6 +1063,77 @@ hipError_t launch_canon_negzero(uint2 *adj, int32_t m, hipStream_t st) {
     if (m <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_canon_negzero, dim3(grid_for(m, kBlk * 8, 16384)), dim3(kBlk), 0, st, adj, m);
     return hipGetLastError();
+}
+
+template <int WT, int NP>
+static hipError_t coop_launch(const PersistArgs &a, int grid, hipStream_t st) {
+    void *args[] = {const_cast<PersistArgs *>(&a)};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_persistent<WT, NP>), dim3(grid), dim3(kBlk),
+                                      args, 0, st);
+}
+
+int persistent_grid(const DevGraph &g, int num_cu) {
+    int nb = 0;
+    hipError_t e;
+    if (g.np == 1) e = g.wt == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<1, 1>, kBlk, 0)
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<0, 1>, kBlk, 0);
+    else
+        e = g.wt == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<1, kMaxParts>, kBlk, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<0, kMaxParts>, kBlk, 0);
+    if (e != hipSuccess || nb < 1) return 0;
+    nb = std::min(nb, 8);
+    int grid = nb * num_cu;
+    grid -= grid % kMaxParts;  // whole rounds of the 8 XCDs
+    return grid;
+}
+
+hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg,
+                             hipStream_t st) {
+    PersistArgs a;
+    FilterArgs &fg = a.fg;
+    fg.np = g.np;
+    fg.pro = g.pro;
+    fg.zmask = nullptr;
+    fg.nflags = nullptr;
+    fg.cflags = nullptr;
+    fg.ctl_next = nullptr;
+    fg.ctl_zero = nullptr;
+    DenseFilterArgs &fd = a.fd;
+    fd.np = g.np;
+    int64_t maxlen = 0;
+    for (int k = 0; k < g.np; ++k) maxlen = std::max<int64_t>(maxlen, g.mem_off[k + 1] - g.mem_off[k]);
+    fd.chunks = (int32_t)std::max<int64_t>(1, (maxlen + kDenseChunk - 1) / kDenseChunk);
+    fd.mem_u = g.mem_u;
+    fd.mem_sd = g.mem_sd;
+    for (int k = 0; k <= kMaxParts; ++k) fd.off[k] = k <= g.np ? g.mem_off[k] : g.mem_off[g.np];
+    fd.nflags = nullptr;
+    fd.cflags = nullptr;
+    fd.nflag16 = f.nflag / 16;
+    fd.clear16 = (fd.nflag16 + (int64_t)fd.chunks * g.np - 1) / ((int64_t)fd.chunks * g.np);
+    fd.zmask = nullptr;
+    fd.ctl_next = nullptr;
+    fd.ctl_zero = nullptr;
+    for (int k = 0; k < kMaxParts; ++k) {
+        fg.qse[k] = fd.qse[k] = f.qse[k];
+        fg.qs[k] = fd.qs[k] = f.qs[k];
+    }
+    a.padj = g.padj;
+    a.dist = dist;
+    a.ro_in = g.ro_in;
+    a.adj_in = g.adj_in;
+    a.flags[0] = f.flags[0];
+    a.flags[1] = f.flags[1];
+    a.ctl = f.ctl;
+    a.n = g.n;
+    a.m = g.m;
+    a.ngroups = f.ngroups;
+    a.max_iters = cfg.max_iters;
+    a.alpha_x16 = cfg.alpha_x16;
+    a.direction = cfg.direction;
+    a.filter = cfg.filter;
+    a.spin_ticks = cfg.spin_ticks;
+    if (g.np == 1) return g.wt == 1 ? coop_launch<1, 1>(a, cfg.grid, st) : coop_launch<0, 1>(a, cfg.grid, st);
+    return g.wt == 1 ? coop_launch<1, kMaxParts>(a, cfg.grid, st) : coop_launch<0, kMaxParts>(a, cfg.grid, st);
 }
 
 // ---------------------------------------------------------------------------

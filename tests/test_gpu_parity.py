@@ -23,9 +23,9 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run(G, src, direction=0, loop=0, n=None, layout=0):
+def run(G, src, direction=0, loop=0, n=None, layout=0, filt=0):
     dist = torch.full((n or G.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
-    st = gr.gr_sssp_ex(G.handle, int(src), dist, direction=direction, loop=loop, layout=layout)
+    st = gr.gr_sssp_ex(G.handle, int(src), dist, direction=direction, loop=loop, layout=layout, filter=filt)
     torch.cuda.synchronize()
     return dist.cpu().numpy().view(np.uint32), st
 
@@ -38,8 +38,13 @@ def assert_same(got, want, tag):
             tag, len(bad), v, int(got[v]), int(want[v])))
 
 
-def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate"), flags=gr.GR_FORCE_PARTITION):
-    """Every direction policy, with both push layouts (plain CSR and partitioned)."""
+LOOPS = {"host": 1, "persistent": 2}
+
+
+def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate"), flags=gr.GR_FORCE_PARTITION,
+                   loops=("host", "persistent")):
+    """Every direction policy, with both push layouts (plain CSR and partitioned)
+    and both loop drivers (host-driven, device-driven persistent)."""
     G = gr.Graph.from_csr(g, flags=flags)
     info = G.info()
     layouts = [gr.GR_LAYOUT_PLAIN] + ([gr.GR_LAYOUT_PARTITIONED] if info["partitions"] > 1 else [])
@@ -52,9 +57,11 @@ def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate"), fla
                         continue
                     if d == "pull" and lay != layouts[0]:
                         continue  # pull does not use the push layout
-                    say("case %s src=%d dir=%s layout=%d n=%d m=%d" % (tag, s, d, lay, g.n, g.m))
-                    got, st = run(G, s, DIRS[d], layout=lay)
-                    assert_same(got, want, "%s src %d dir %s layout %d" % (tag, s, d, lay))
+                    for lp in loops:
+                        say("case %s src=%d dir=%s layout=%d loop=%s n=%d m=%d" % (tag, s, d, lay, lp, g.n, g.m))
+                        got, st = run(G, s, DIRS[d], layout=lay, loop=LOOPS[lp])
+                        assert_same(got, want, "%s src %d dir %s layout %d loop %s" % (tag, s, d, lay, lp))
+                        assert st["loop"] == LOOPS[lp]
     finally:
         G.close()
 
@@ -147,6 +154,38 @@ def test_device_input_graph():
     assert ei.value.status == gr.GR_ERR_INVALID_ARG
 
 
+def test_persistent_loop_stats_match_host_loop():
+    # both drivers run the same rounds on a deterministic-size workload (a directed path)
+    L = 300
+    g = gg.from_arcs(L + 1, [(i, i + 1, 1 + i % 7) for i in range(L)])
+    G = gr.Graph.from_csr(g)
+    try:
+        a = run(G, 0, DIRS["push"], loop=LOOPS["host"])[1]
+        b = run(G, 0, DIRS["push"], loop=LOOPS["persistent"])[1]
+        assert a["iterations"] == b["iterations"] == L
+        assert a["edges_pushed"] == b["edges_pushed"] == L
+        assert a["frontier_sum"] == b["frontier_sum"] == L
+    finally:
+        G.close()
+
+
+def test_persistent_barrier_timeout_reports_error_then_recovers():
+    # a 1 us bound on each grid-barrier wait cannot be met by a real round: the
+    # device-driven loop must end (every block leaves) and report GR_ERR_HIP
+    g = gg.grid(300, wseed=3)
+    want = oracle.dijkstra(g, 0)
+    G = gr.Graph.from_csr(g)
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    try:
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_ex(G.handle, 0, dist, loop=LOOPS["persistent"], barrier_timeout_us=1)
+        assert ei.value.status == gr.GR_ERR_HIP and "barrier" in ei.value.message
+        got, _ = run(G, 0, DIRS["push"], loop=LOOPS["persistent"])
+        assert_same(got, want, "after a timed-out query")
+    finally:
+        G.close()
+
+
 def test_errors_on_gpu():
     g = gg.grid(8, wseed=1)
     G = gr.Graph.from_csr(g)
@@ -155,9 +194,10 @@ def test_errors_on_gpu():
         with pytest.raises(gr.GrError) as ei:
             gr.gr_sssp(G.handle, g.n, dist)
         assert ei.value.status == gr.GR_ERR_SOURCE_RANGE
-        with pytest.raises(gr.GrError) as ei:
-            gr.gr_sssp_ex(G.handle, 0, dist, max_iters=3)
-        assert ei.value.status == gr.GR_ERR_ITER_LIMIT
+        for lp in (1, 2):
+            with pytest.raises(gr.GrError) as ei:
+                gr.gr_sssp_ex(G.handle, 0, dist, max_iters=3, loop=lp)
+            assert ei.value.status == gr.GR_ERR_ITER_LIMIT
     finally:
         G.close()
     Gp = gr.Graph.from_csr(g, flags=gr.GR_NO_PULL)
@@ -167,6 +207,24 @@ def test_errors_on_gpu():
         assert ei.value.status == gr.GR_ERR_INVALID_ARG
     finally:
         Gp.close()
+
+
+@pytest.mark.parametrize("wtype", [gg.W_U32, gg.W_F32])
+def test_both_filters_both_layouts(wtype):
+    # the group filter and the streaming filter build the same frontiers
+    g = gg.rmat(14, 16, gseed=31 + wtype, pseed=32, wseed=33, wtype=wtype)
+    G = gr.Graph.from_csr(g, flags=gr.GR_FORCE_PARTITION)
+    try:
+        for s in gg.pick_sources(g, 34, 2):
+            want = oracle.dijkstra(g, int(s))
+            for lay in (gr.GR_LAYOUT_PLAIN, gr.GR_LAYOUT_PARTITIONED):
+                for filt in (1, 2):
+                    for d in (DIRS["push"], DIRS["alternate"]):
+                        say("filters rmat14 w%d src=%d layout=%d filter=%d dir=%d" % (wtype, s, lay, filt, d))
+                        got, _ = run(G, s, d, layout=lay, filt=filt)
+                        assert_same(got, want, "filter %d layout %d dir %d" % (filt, lay, d))
+    finally:
+        G.close()
 
 
 def test_partition_layout_default_choice():
@@ -208,6 +266,11 @@ def test_rmat20_config_f32():
 def test_road2048_config():
     g, srcs = gg.workload("road2048")
     check_all_dirs(g, srcs, "road2048", dirs=("auto",), flags=0)
+
+
+def test_grid2048_config_persistent():
+    g, srcs = gg.workload("grid2048")
+    check_all_dirs(g, srcs, "grid2048", dirs=("push",), flags=0, loops=("persistent",))
 
 
 def test_rmat22_config_sampled_sources():
