@@ -60,6 +60,9 @@ def main():
     ap.add_argument("--loop", type=int, default=0, help="gr_loop_mode (0 auto, 1 host, 2 persistent)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-source batched comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-queries", type=int, default=1500, help="open-loop queries per load level")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -161,6 +164,19 @@ def main():
                          % (done, len(srcs), t_cpu)}
         log("cpu oracle: %s" % cpu)
 
+    batched = None
+    if not args.no_batched and args.workload == "rmat22":
+        batched = measure_batched(G, g, srcs, reached, ms_per_step, torch, np, gr, dev)
+        log("batched: %s" % batched)
+    G.close()
+    del dist
+    torch.cuda.empty_cache()
+
+    serving = None
+    if not args.no_serving:
+        serving = measure_serving(args, torch, np, gr, gg, dev)
+        log("serving: %s" % serving)
+
     out = {
         "metric": "SSSP GTEPS + HBM GB/s (single vs batched); p50/p99 query latency at fixed QPS",
         "value": round(gteps, 4),
@@ -180,9 +196,127 @@ def main():
                    "iterations_per_query": iters / max(args.steps, 1)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
-    G.close()
+
+
+def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev):
+    """64 sources in one gr_sssp_batch launch vs the same 64 as looped single queries."""
+    k = len(srcs)
+    out = torch.empty((k, g.n), dtype=torch.int32, device=dev)
+    s_arr = np.asarray(srcs, np.int32)
+    gr.gr_sssp_batch(G.handle, s_arr, out)  # warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        gr.gr_sssp_batch(G.handle, s_arr, out)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    edges = sum(reached[s] for s in srcs)
+    looped_ms = single_ms * k
+    return {"k": k, "ms_per_launch": round(ms, 3), "gteps": round(edges / (ms * 1e-3) / 1e9, 3),
+            "looped_ms": round(looped_ms, 3), "looped_gteps": round(edges / (looped_ms * 1e-3) / 1e9, 3),
+            "speedup_vs_looped": round(looped_ms / ms, 3)}
+
+
+def measure_serving(args, torch, np, gr, gg, dev):
+    """32 resident graphs; closed-loop capacity Q*, then open-loop Poisson streams at
+    0.5 Q* and 0.8 Q*; latency = completion - scheduled arrival (no coordinated
+    omission).  The same trace is replayed through a non-batching FIFO (max_batch 1)."""
+    t0 = time.time()
+    graphs = gg.serving_graphs()
+    Gs = [gr.Graph.from_csr(x) for x in graphs]
+    deg = [np.diff(x.ro).astype(np.int64) for x in graphs]
+    log("serving graphs: %d (%.1fs)" % (len(Gs), time.time() - t0))
+    rng = np.random.default_rng(201)
+    nq = max(args.serve_queries, 100)
+    # query mix: graph uniform over 32, source uniform over non-isolated vertices
+    nonzero = [np.flatnonzero(d > 0) for d in deg]
+    mix = []
+    for i in range(nq + 200):
+        gi = int(rng.integers(0, len(graphs)))
+        mix.append((gi, int(nonzero[gi][rng.integers(0, len(nonzero[gi]))])))
+    ring = 96  # output buffers per graph (more than the queries a graph has in flight)
+    bufs = [[torch.empty(x.n, dtype=torch.int32, device=dev) for _ in range(ring)] for x in graphs]
+    inf = gr.GR_DIST_INF_U32
+    edges_of = {}
+
+    def serve(queries, arrivals_ns, max_batch):
+        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=4, max_wait_us=200)
+        try:
+            gids = [gr.gr_server_add_graph(srv, G.handle) for G in Gs]
+            tickets = []
+            use = [0] * len(graphs)
+            start = time.monotonic_ns()
+            for (gi, s), at in zip(queries, arrivals_ns):
+                due = start + at
+                while True:
+                    now = time.monotonic_ns()
+                    if now >= due:
+                        break
+                    if due - now > 200000:
+                        time.sleep((due - now - 100000) / 1e9)
+                b = bufs[gi][use[gi] % ring]
+                use[gi] += 1
+                tickets.append((gr.gr_serve_submit(srv, gids[gi], s, b), due, gi, s))
+            lat = []
+            done_at = 0
+            res = {}
+            while len(res) < len(tickets):
+                for t, due, gi, s in tickets:
+                    if t in res:
+                        continue
+                    r = gr.gr_serve_poll(srv, t)
+                    if r is not None:
+                        res[t] = r
+                time.sleep(0.0002)
+            for t, due, gi, s in tickets:
+                r = res[t]
+                assert r["status"] == gr.GR_OK
+                lat.append(r["t_done_ns"] - due)
+                done_at = max(done_at, r["t_done_ns"])
+            span = (done_at - start) / 1e9
+            return np.array(lat) / 1e6, span, res
+        finally:
+            gr.gr_server_destroy(srv)
+
+    def m_reached(gi, s):
+        key = (gi, s)
+        if key not in edges_of:
+            d = torch.empty(graphs[gi].n, dtype=torch.int32, device=dev)
+            gr.gr_sssp(Gs[gi].handle, s, d)
+            dd = d.cpu().numpy().view(np.uint32)
+            edges_of[key] = int(deg[gi][dd != inf].sum())
+        return edges_of[key]
+
+    # closed loop: everything submitted at t = 0
+    warm = mix[:100]
+    serve(warm, [0] * len(warm), 64)
+    closed = mix[100:100 + nq]
+    lat, span, _ = serve(closed, [0] * len(closed), 64)
+    qstar = len(closed) / span
+    log("serving capacity Q* = %.0f queries/s" % qstar)
+    out = {"graphs": len(graphs), "capacity_qps": round(qstar, 1), "levels": []}
+    for frac in (0.5, 0.8):
+        qps = frac * qstar
+        gaps = rng.exponential(1.0 / qps, size=nq)
+        arr = (np.cumsum(gaps) * 1e9).astype(np.int64)
+        trace = mix[100:100 + nq]
+        lat, span, _ = serve(trace, arr, 64)
+        lat1, span1, _ = serve(trace, arr, 1)
+        edges = sum(m_reached(gi, s) for gi, s in trace)
+        out["levels"].append({
+            "offered_qps": round(qps, 1), "achieved_qps": round(len(trace) / span, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "gteps": round(edges / span / 1e9, 3),
+            "fifo_unbatched_p50_ms": round(float(np.percentile(lat1, 50)), 3),
+            "fifo_unbatched_p99_ms": round(float(np.percentile(lat1, 99)), 3)})
+    for G in Gs:
+        G.close()
+    return out
 
 
 if __name__ == "__main__":

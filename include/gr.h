@@ -177,6 +177,31 @@ typedef struct {
 gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, void *stream, const gr_sssp_opts *opts,
                      gr_sssp_stats *stats);
 
+/* Schedule chosen by gr_graph_tune (also what GR_*_AUTO resolve to). */
+typedef struct {
+    int32_t layout;       /* gr_layout that won (PLAIN or PARTITIONED) */
+    int32_t loop;         /* gr_loop_mode that won (HOST or PERSISTENT) */
+    int32_t dense_ratio;  /* streaming filter when frontier size * dense_ratio >= n */
+    int32_t alpha_x16;    /* pull threshold (0 = never pull) */
+    double best_ms;       /* median time of one query with that schedule */
+    double default_ms;    /* the same before tuning */
+    int32_t trials;       /* timed configurations */
+    int32_t from_cache;   /* 1 when read from the tuning cache file */
+} gr_tune_result;
+
+/*
+ * Autotuner: times candidate schedules -- push layout, loop driver, filter
+ * threshold, pull threshold -- with a greedy search (one knob at a time, each
+ * candidate timed as the median of `reps` queries from srcs[0..nsrcs)), and
+ * keeps the fastest as the graph's AUTO configuration.  Every candidate
+ * computes the same distances.  When the environment variable GR_TUNE_CACHE
+ * names a file, results are read from / appended to it, keyed by a signature
+ * of the graph (n, m, weight type, degree statistics).  out may be NULL.
+ * The graph must not be queried concurrently while it is being tuned.
+ */
+gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsrcs, int32_t reps, void *stream,
+                        gr_tune_result *out);
+
 /*
  * k independent SSSP queries on one graph in one batched launch.
  *   srcs      host int32[k], each in [0, n); duplicates allowed

@@ -58,7 +58,8 @@ GR_DIR_PULL = 2
 GR_DIR_ALTERNATE = 3
 
 EXPORTED = [
-    "gr_graph_create_csr", "gr_graph_destroy", "gr_graph_info", "gr_sssp", "gr_sssp_ex", "gr_sssp_batch",
+    "gr_graph_create_csr", "gr_graph_destroy", "gr_graph_info", "gr_graph_tune", "gr_sssp", "gr_sssp_ex",
+    "gr_sssp_batch",
     "gr_server_create", "gr_server_add_graph", "gr_serve_submit", "gr_serve_poll", "gr_server_destroy",
     "gr_status_string", "gr_last_error", "gr_version",
 ]
@@ -88,6 +89,15 @@ class gr_sssp_stats(ctypes.Structure):
                 ("frontier_max", ctypes.c_int32), ("loop", ctypes.c_int32), ("push_launches", ctypes.c_int32),
                 ("layout", ctypes.c_int32), ("push_us", ctypes.c_double), ("pull_us", ctypes.c_double),
                 ("filter_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class gr_tune_result(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_int32), ("loop", ctypes.c_int32), ("dense_ratio", ctypes.c_int32),
+                ("alpha_x16", ctypes.c_int32), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -125,6 +135,7 @@ def lib():
                 "gr_graph_create_csr": [P(vp), i32, i32, vp, vp, vp, ctypes.c_int, u32, vp],
                 "gr_graph_destroy": [vp],
                 "gr_graph_info": [vp, P(i32), P(i32), P(i32), P(ctypes.c_size_t), P(i32), P(i32), P(i32)],
+                "gr_graph_tune": [vp, vp, i32, i32, vp, P(gr_tune_result)],
                 "gr_sssp": [vp, i32, vp, vp],
                 "gr_sssp_ex": [vp, i32, vp, vp, P(gr_sssp_opts), P(gr_sssp_stats)],
                 "gr_sssp_batch": [vp, vp, i32, vp, vp],
@@ -223,6 +234,15 @@ def gr_graph_info(g: int) -> dict:
                 pull_enabled=bool(pe.value), partitions=pa.value)
 
 
+def gr_graph_tune(g: int, srcs, reps=3, stream=None) -> dict:
+    """Times candidate schedules on queries from srcs and keeps the fastest as the graph's AUTO schedule."""
+    s = np.ascontiguousarray(srcs, dtype=np.int32)
+    r = gr_tune_result()
+    _check(lib().gr_graph_tune(g, s.ctypes.data if s.size else None, int(s.size), int(reps), _stream(stream),
+                               ctypes.byref(r)))
+    return r.as_dict()
+
+
 # ---- queries ----------------------------------------------------------------
 
 def gr_sssp(g: int, src: int, dist_out, stream=None) -> None:
@@ -304,6 +324,9 @@ class Graph:
 
     def info(self):
         return gr_graph_info(self.handle)
+
+    def tune(self, srcs, reps=3, stream=None):
+        return gr_graph_tune(self.handle, srcs, reps, stream)
 
     def close(self):
         if self.handle:

@@ -146,6 +146,11 @@ struct gr_graph {
     size_t dev_bytes = 0;
     std::vector<int32_t> h_ro;
     int32_t max_degree = 0;
+    // AUTO schedule: defaults, replaced by gr_graph_tune
+    int32_t auto_layout = GR_LAYOUT_PLAIN;
+    int32_t auto_loop = GR_LOOP_HOST;
+    int32_t auto_dense_ratio = kDenseRatio;
+    int32_t auto_alpha_x16 = 0;
     double locality = 1.0;  // fraction of arcs with |u - v| < locality_span(n)
 };
 
@@ -367,6 +372,7 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
     if (want_part) {
         gr_status s = build_partition(g, n, m, st, sc);
         if (s != GR_OK) return s;
+        g->auto_layout = GR_LAYOUT_PARTITIONED;
     }
     return GR_OK;
 }
@@ -423,9 +429,9 @@ extern "C" gr_status gr_graph_info(const gr_graph *g, int32_t *n, int32_t *m, in
 // ---------------------------------------------------------------------------
 // single-source loop drivers
 
-// AUTO direction: pull when frontier out-edges * alpha_x16 >= 16 * m.  The
-// default never pulls: on the measured graphs push is faster every round.
-static constexpr int32_t kDefaultAlphaX16 = 0;
+// AUTO direction: pull when frontier out-edges * alpha_x16 >= 16 * m; the
+// untuned default (alpha 0) never pulls: on the measured graphs push is faster
+// in every round.
 
 struct RunCfg {
     int loop;
@@ -435,6 +441,7 @@ struct RunCfg {
     bool timing;
     int layout;
     int filter;
+    int32_t dense_ratio;
     int64_t barrier_timeout_us;
     const DevGraph *dg;
 };
@@ -442,7 +449,7 @@ struct RunCfg {
 static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc) {
     rc->loop = o ? o->loop : GR_LOOP_AUTO;
     rc->direction = o ? o->direction : GR_DIR_AUTO;
-    rc->alpha_x16 = (o && o->alpha_x16 > 0) ? o->alpha_x16 : kDefaultAlphaX16;
+    rc->alpha_x16 = (o && o->alpha_x16 > 0) ? o->alpha_x16 : g->auto_alpha_x16;
     rc->max_iters = (o && o->max_iters > 0) ? o->max_iters : (int64_t)g->plain.n + 1;
     const int layout = o ? o->layout : GR_LAYOUT_AUTO;
     if (rc->loop < GR_LOOP_AUTO || rc->loop > GR_LOOP_PERSISTENT)
@@ -455,10 +462,12 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
         return fail(GR_ERR_INVALID_ARG, "unknown layout %d", layout);
     if (layout == GR_LAYOUT_PARTITIONED && !g->has_part)
         return fail(GR_ERR_INVALID_ARG, "partitioned layout requested but the graph has none");
-    rc->dg = (layout == GR_LAYOUT_PLAIN || !g->has_part) ? &g->plain : &g->part;
+    const int lay = layout == GR_LAYOUT_AUTO ? g->auto_layout : layout;
+    rc->dg = (lay == GR_LAYOUT_PLAIN || !g->has_part) ? &g->plain : &g->part;
     rc->layout = rc->dg->np > 1 ? GR_LAYOUT_PARTITIONED : GR_LAYOUT_PLAIN;
     rc->timing = o && o->timing;
     rc->filter = o ? o->filter : 0;
+    rc->dense_ratio = g->auto_dense_ratio;
     rc->barrier_timeout_us = (o && o->barrier_timeout_us > 0) ? o->barrier_timeout_us : 20000000;
     if (rc->filter < 0 || rc->filter > 2) return fail(GR_ERR_INVALID_ARG, "unknown filter mode %d", rc->filter);
     return GR_OK;
@@ -544,7 +553,7 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
         }
         if (timed) (void)hipEventRecord(ev[1], st);
         // the streaming filter pays off once the next frontier is likely large
-        const bool dense = rc.filter == 2 || (rc.filter == 0 && c.Fsum() * kDenseRatio >= (int64_t)dg.n);
+        const bool dense = rc.filter == 2 || (rc.filter == 0 && c.Fsum() * rc.dense_ratio >= (int64_t)dg.n);
         if (e == hipSuccess) e = launch_filter(dg, f, iter, nullptr, dense, st);
         if (timed) (void)hipEventRecord(ev[2], st);
         if (e == hipSuccess)
@@ -586,6 +595,7 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     cfg.alpha_x16 = rc.alpha_x16;
     cfg.direction = rc.direction;
     cfg.filter = rc.filter;
+    cfg.dense_ratio = rc.dense_ratio;
     cfg.spin_ticks = (uint64_t)rc.barrier_timeout_us * (uint64_t)di.wall_khz / 1000ull;
     unsigned long long *hp = pinned_slot();
     if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
@@ -641,7 +651,7 @@ extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, 
     gr_status s = check_opts(g, opts, &rc);
     if (s != GR_OK) return s;
     int loop = rc.loop;
-    if (loop == GR_LOOP_AUTO) loop = GR_LOOP_HOST;
+    if (loop == GR_LOOP_AUTO) loop = g->auto_loop;
     if (loop == GR_LOOP_PERSISTENT)
         return run_persistent(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
     return run_host_loop(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
@@ -894,5 +904,170 @@ extern "C" gr_status gr_server_destroy(gr_server *s) {
     for (std::thread &t : s->workers) t.join();
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     delete s;
+    return GR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+
+static std::string graph_signature(const gr_graph *g) {
+    // n, m, weight type, degree statistics and a hash of the offsets
+    uint64_t h = 1469598103934665603ull;
+    const size_t step = std::max<size_t>(1, g->h_ro.size() / 4096);
+    for (size_t i = 0; i < g->h_ro.size(); i += step) {
+        h ^= (uint64_t)(uint32_t)g->h_ro[i];
+        h *= 1099511628211ull;
+    }
+    char buf[256];
+    snprintf(buf, sizeof buf, "n%d_m%d_w%d_dmax%d_loc%.3f_p%d_h%016llx", g->plain.n, g->plain.m, g->plain.wt,
+             g->max_degree, g->locality, g->has_part ? 8 : 1, (unsigned long long)h);
+    return buf;
+}
+
+static bool cache_lookup(const std::string &sig, gr_tune_result *r) {
+    const char *path = getenv("GR_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char s[300];
+        int lay, loop, dr, al;
+        double ms;
+        if (sscanf(line, "{\"sig\": \"%299[^\"]\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
+                         "\"best_ms\": %lf}",
+                   s, &lay, &loop, &dr, &al, &ms) == 6 &&
+            sig == s) {
+            r->layout = lay;
+            r->loop = loop;
+            r->dense_ratio = dr;
+            r->alpha_x16 = al;
+            r->best_ms = ms;
+            found = true;  // the last matching line wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const std::string &sig, const gr_tune_result &r) {
+    const char *path = getenv("GR_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"sig\": \"%s\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
+               "\"best_ms\": %.6f}\n",
+            sig.c_str(), r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.best_ms);
+    fclose(f);
+}
+
+struct TuneCfg {
+    int32_t layout, loop, dense_ratio, alpha_x16;
+};
+
+static void apply_auto(gr_graph *g, const TuneCfg &c) {
+    g->auto_layout = c.layout;
+    g->auto_loop = c.loop;
+    g->auto_dense_ratio = c.dense_ratio;
+    g->auto_alpha_x16 = c.alpha_x16;
+}
+
+extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsrcs, int32_t reps, void *stream,
+                                   gr_tune_result *out) {
+    if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
+    if (!srcs || nsrcs < 1) return fail(GR_ERR_INVALID_ARG, "no sources to tune with");
+    if (reps < 1) reps = 1;
+    for (int32_t i = 0; i < nsrcs; ++i)
+        if (srcs[i] < 0 || srcs[i] >= g->plain.n)
+            return fail(GR_ERR_SOURCE_RANGE, "srcs[%d] = %d outside [0, %d)", i, srcs[i], g->plain.n);
+    gr_tune_result r{};
+    const std::string sig = graph_signature(g);
+    if (cache_lookup(sig, &r)) {
+        if (r.layout == GR_LAYOUT_PARTITIONED && !g->has_part) r.layout = GR_LAYOUT_PLAIN;
+        if (r.alpha_x16 > 0 && !g->pull) r.alpha_x16 = 0;
+        apply_auto(g, TuneCfg{r.layout, r.loop, r.dense_ratio, r.alpha_x16});
+        r.from_cache = 1;
+        if (out) *out = r;
+        return GR_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *dist = nullptr;
+    HIP_TRY(hipMallocAsync(&dist, sizeof(uint32_t) * (size_t)g->plain.n, st));
+    gr_status status = GR_OK;
+    int trials = 0;
+    auto measure = [&](const TuneCfg &c, double *ms) -> gr_status {
+        gr_sssp_opts o{};
+        o.loop = c.loop;
+        o.layout = c.layout;
+        o.alpha_x16 = c.alpha_x16 > 0 ? c.alpha_x16 : 0;
+        o.direction = c.alpha_x16 > 0 ? GR_DIR_AUTO : GR_DIR_PUSH;
+        const int32_t saved = g->auto_dense_ratio;
+        g->auto_dense_ratio = c.dense_ratio;
+        std::vector<double> t;
+        gr_status s = GR_OK;
+        for (int32_t rep = 0; rep <= reps && s == GR_OK; ++rep) {
+            for (int32_t i = 0; i < nsrcs && s == GR_OK; ++i) {
+                const auto t0 = std::chrono::steady_clock::now();
+                s = gr_sssp_ex(g, srcs[i], dist, st, &o, nullptr);
+                if (s == GR_OK && hipStreamSynchronize(st) != hipSuccess) s = fail(GR_ERR_HIP, "tuning query");
+                const double d = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                                     .count();
+                if (rep > 0) t.push_back(d);  // rep 0 warms up
+            }
+        }
+        g->auto_dense_ratio = saved;
+        ++trials;
+        if (s != GR_OK) return s;
+        std::sort(t.begin(), t.end());
+        *ms = t[t.size() / 2];
+        return GR_OK;
+    };
+    TuneCfg best{g->auto_layout, g->auto_loop, g->auto_dense_ratio, g->auto_alpha_x16};
+    double best_ms = 0;
+    status = measure(best, &best_ms);
+    const double default_ms = best_ms;
+    // greedy: one knob at a time, the others at their best so far
+    std::vector<std::pair<int, std::vector<int32_t>>> knobs;
+    knobs.push_back({0, g->has_part ? std::vector<int32_t>{GR_LAYOUT_PLAIN, GR_LAYOUT_PARTITIONED}
+                                    : std::vector<int32_t>{GR_LAYOUT_PLAIN}});
+    {
+        DeviceInfo di;
+        const bool coop = device_info(g->device, &di) == GR_OK && di.coop &&
+                          persistent_grid(g->plain, di.num_cu) >= kMaxParts;
+        knobs.push_back({1, coop ? std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_PERSISTENT}
+                                 : std::vector<int32_t>{GR_LOOP_HOST}});
+    }
+    knobs.push_back({2, {8, 64, 512}});
+    if (g->pull) knobs.push_back({3, {0, 8, 32}});
+    for (const auto &kv : knobs) {
+        for (int32_t v : kv.second) {
+            if (status != GR_OK) break;
+            TuneCfg c = best;
+            int32_t *field = kv.first == 0 ? &c.layout : kv.first == 1 ? &c.loop : kv.first == 2 ? &c.dense_ratio
+                                                                                               : &c.alpha_x16;
+            if (*field == v) continue;
+            *field = v;
+            double ms = 0;
+            status = measure(c, &ms);
+            if (status == GR_OK && ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    }
+    (void)hipFreeAsync(dist, st);
+    (void)hipStreamSynchronize(st);
+    if (status != GR_OK) return status;
+    apply_auto(g, best);
+    r.layout = best.layout;
+    r.loop = best.loop;
+    r.dense_ratio = best.dense_ratio;
+    r.alpha_x16 = best.alpha_x16;
+    r.best_ms = best_ms;
+    r.default_ms = default_ms;
+    r.trials = trials;
+    cache_store(sig, r);
+    if (out) *out = r;
     return GR_OK;
 }

@@ -73,7 +73,7 @@ struct Frontier {
 constexpr int kCtlSlots = 3;
 constexpr int kCtlWords = 64;       // 3 x 8 counters, then LoopState
 constexpr int kLoopStateWord = 32;  // LoopState at ctl + 32
-constexpr int64_t kDenseRatio = 64;  // streaming filter when |frontier| >= n / 64
+constexpr int32_t kDenseRatio = 64;  // default: streaming filter when |frontier| >= n / 64
 
 // Device-driven loop state.
 struct LoopState {
@@ -118,6 +118,7 @@ struct PersistentCfg {
     int32_t alpha_x16;
     int32_t direction;    // gr_direction
     int32_t filter;       // 0 auto, 1 group, 2 streaming
+    int32_t dense_ratio;  // auto filter: streaming when |frontier| * dense_ratio >= n
     int32_t grid;         // co-resident blocks, a multiple of kMaxParts
     uint64_t spin_ticks;  // grid-barrier wait bound, in wall_clock64 ticks
 };

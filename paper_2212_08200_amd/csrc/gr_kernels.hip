@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
 // candidates dist[u] (+) w of active u into an LDS min per owner.  Then each
 // owner compares with dist[v], stores the improvement (it is the only writer
 // of dist[v] in this launch) and each wave writes its 64-bit bitmap word.
-constexpr int kPullItems = 4;
+constexpr int kPullItems = 8;
 
 template <int WT>
 __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict__ ro_in,
@@ -242,9 +242,11 @@ __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict_
         uint8_t fl[kPullItems];
 #pragma unroll
         for (int it = 0; it < kPullItems; ++it) fl[it] = cflags[arc[it].x];
+        // distances only of active in-neighbours (the loads stay batched:
+        // each one is predicated on its own lane's flag)
         uint32_t du[kPullItems];
 #pragma unroll
-        for (int it = 0; it < kPullItems; ++it) du[it] = dist[arc[it].x];
+        for (int it = 0; it < kPullItems; ++it) du[it] = fl[it] ? dist[arc[it].x] : inf;
         int32_t pos[kPullItems];
 #pragma unroll
         for (int it = 0; it < kPullItems; ++it) pos[it] = 0;
@@ -258,7 +260,7 @@ __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict_
         }
 #pragma unroll
         for (int it = 0; it < kPullItems; ++it) {
-            const bool act = (x0 + it * kBlk < a1) && fl[it] && du[it] != inf;
+            const bool act = (x0 + it * kBlk < a1) && du[it] != inf;
             if (act) atomicMin(&sMin[pos[it]], plus<WT>(du[it], arc[it].y));
         }
     }
@@ -513,7 +515,7 @@ struct PersistArgs {
     uint8_t *flags[2];
     unsigned long long *ctl;
     int32_t n, m, ngroups;
-    int32_t max_iters, alpha_x16, direction, filter;
+    int32_t max_iters, alpha_x16, direction, filter, dense_ratio;
     uint64_t spin_ticks;
 };
 
@@ -564,7 +566,7 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
         if (!grid_sync(ls, (unsigned)G, a.spin_ticks)) break;
         unsigned long long *cn = a.ctl + (((iter + 1) % kCtlSlots) * kMaxParts);
         unsigned long long *cz = a.ctl + (((iter + 2) % kCtlSlots) * kMaxParts);
-        const bool dense = a.filter == 2 || (a.filter == 0 && Fs * kDenseRatio >= a.n);
+        const bool dense = a.filter == 2 || (a.filter == 0 && Fs * a.dense_ratio >= a.n);
         if (dense) {
             const int64_t nvb = (int64_t)a.fd.chunks * NP;
             for (int64_t vb = b; vb < nvb; vb += G) filter_dense(a.fd, vb, nf, cf, nullptr, cn, cz);
@@ -1131,6 +1133,7 @@ hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &
     a.alpha_x16 = cfg.alpha_x16;
     a.direction = cfg.direction;
     a.filter = cfg.filter;
+    a.dense_ratio = cfg.dense_ratio;
     a.spin_ticks = cfg.spin_ticks;
     if (g.np == 1) return g.wt == 1 ? coop_launch<1, 1>(a, cfg.grid, st) : coop_launch<0, 1>(a, cfg.grid, st);
     return g.wt == 1 ? coop_launch<1, kMaxParts>(a, cfg.grid, st) : coop_launch<0, kMaxParts>(a, cfg.grid, st);
