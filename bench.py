@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-source batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-queries", type=int, default=1500, help="open-loop queries per load level")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run one elementwise copy (b = a + 1) of this many MiB and exit: a kernel of "
+                         "known traffic, for scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -82,6 +85,15 @@ def main():
         sys.exit(3)
     gr.lib()  # fails loudly when libgr.so is missing
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.add(a, 1, out=b)  # one elementwise kernel: reads nbytes, writes nbytes
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (nbytes, nbytes))
+        return
 
     t0 = time.time()
     g, srcs = gg.workload(args.workload)

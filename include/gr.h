@@ -124,7 +124,9 @@ gr_status gr_sssp(const gr_graph *g, int32_t src, void *dist_out, void *stream);
 typedef enum {
     GR_LOOP_AUTO = 0,       /* the library's choice (tuned per graph) */
     GR_LOOP_HOST = 1,       /* one launch per operator, host reads the frontier size */
-    GR_LOOP_PERSISTENT = 2  /* one cooperative launch, device-side grid barrier */
+    GR_LOOP_PERSISTENT = 2, /* one cooperative launch, device-side grid barrier */
+    GR_LOOP_QUEUED = 3      /* launches enqueued ahead in chunks; each reads the frontier
+                               size from device memory; the host checks once per chunk */
 } gr_loop_mode;
 
 /* Traversal direction policy (Section III-C: push vs pull). */

@@ -51,6 +51,7 @@ GR_LAYOUT_PARTITIONED = 2
 GR_LOOP_AUTO = 0
 GR_LOOP_HOST = 1
 GR_LOOP_PERSISTENT = 2
+GR_LOOP_QUEUED = 3
 
 GR_DIR_AUTO = 0
 GR_DIR_PUSH = 1

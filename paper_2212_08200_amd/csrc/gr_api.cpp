@@ -151,6 +151,8 @@ struct gr_graph {
     int32_t auto_loop = GR_LOOP_HOST;
     int32_t auto_dense_ratio = kDenseRatio;
     int32_t auto_alpha_x16 = 0;
+    // iterations of the last completed queued-loop query (first chunk size)
+    mutable std::atomic<int32_t> last_iters{0};
     double locality = 1.0;  // fraction of arcs with |u - v| < locality_span(n)
 };
 
@@ -452,7 +454,8 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
     rc->alpha_x16 = (o && o->alpha_x16 > 0) ? o->alpha_x16 : g->auto_alpha_x16;
     rc->max_iters = (o && o->max_iters > 0) ? o->max_iters : (int64_t)g->plain.n + 1;
     const int layout = o ? o->layout : GR_LAYOUT_AUTO;
-    if (rc->loop < GR_LOOP_AUTO || rc->loop > GR_LOOP_PERSISTENT)
+    if (!g->pull) rc->alpha_x16 = 0;  // the device-side AUTO rule must never pick pull then
+    if (rc->loop < GR_LOOP_AUTO || rc->loop > GR_LOOP_QUEUED)
         return fail(GR_ERR_INVALID_ARG, "unknown loop mode %d", rc->loop);
     if (rc->direction < GR_DIR_AUTO || rc->direction > GR_DIR_ALTERNATE)
         return fail(GR_ERR_INVALID_ARG, "unknown direction %d", rc->direction);
@@ -622,6 +625,7 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     local.edges_pushed = (int64_t)ls.edges_pushed;
     local.arcs_pulled = (int64_t)ls.arcs_pulled;
     local.frontier_sum = (int64_t)ls.frontier_sum;
+    local.push_frontier_sum = (int64_t)ls.push_frontier_sum;
     local.frontier_max = (int32_t)ls.frontier_max;
     local.push_launches = 1;
     if (timed) {
@@ -642,6 +646,108 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     return GR_OK;
 }
 
+// Queued loop: iterations are enqueued in chunks without waiting; the host
+// reads the loop state once per chunk, one chunk behind, so the device always
+// has the next chunk queued.  The first chunk covers the iteration count of
+// the previous query on this graph; later chunks grow from 4 to 64.  Launches
+// queued past the end return at once; the call waits for the last chunk so
+// that its state copy has landed before the pinned slot is reused.
+static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
+                            gr_sssp_stats *stats) {
+    DeviceInfo di;
+    gr_status s = device_info(g->device, &di);
+    if (s != GR_OK) return s;
+    unsigned long long *hp = pinned_slot();
+    if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
+    static_assert(2 * sizeof(LoopState) <= 256, "pinned slot holds two loop states");
+    const DevGraph &dg = *rc.dg;
+    PersistentCfg cfg;
+    cfg.grid = di.num_cu * 8;
+    cfg.max_iters = (int32_t)std::min<int64_t>(rc.max_iters, INT32_MAX);
+    cfg.alpha_x16 = rc.alpha_x16;
+    cfg.direction = rc.direction;
+    cfg.filter = rc.filter;
+    cfg.dense_ratio = rc.dense_ratio;
+    cfg.spin_ticks = 0;
+    void *ws = nullptr;
+    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
+    Frontier f;
+    frontier_carve(f, ws, dg);
+    hipEvent_t evc[2] = {nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (auto &x : evc)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+    std::vector<hipEvent_t> tev;  // with timing: begin/end of each advance launch
+    if (e == hipSuccess) e = launch_init(dg, dist, src, f, st);
+    int64_t issued = 0;
+    int c = 0;
+    int64_t K = std::clamp<int64_t>(g->last_iters.load(std::memory_order_relaxed) + 1, 4, 256);
+    LoopState fin{};
+    bool done = false;
+    while (e == hipSuccess && !done) {
+        for (int64_t i = 0; i < K && e == hipSuccess; ++i) {
+            hipEvent_t b = nullptr, en = nullptr;
+            if (rc.timing) {
+                if (hipEventCreate(&b) == hipSuccess) tev.push_back(b); else b = nullptr;
+                if (hipEventCreate(&en) == hipSuccess) tev.push_back(en); else en = nullptr;
+                if (!b || !en) b = en = nullptr;
+            }
+            e = launch_step(dg, dist, f, cfg, issued + i, b, en, st);
+        }
+        issued += K;
+        unsigned long long *slot = hp + (c & 1) * (sizeof(LoopState) / 8);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(slot, f.ctl + kLoopStateWord, sizeof(LoopState), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(evc[c & 1], st);
+        if (e == hipSuccess && c >= 1) {
+            e = hipEventSynchronize(evc[(c - 1) & 1]);
+            LoopState ls;
+            std::memcpy(&ls, hp + ((c - 1) & 1) * (sizeof(LoopState) / 8), sizeof ls);
+            if (e == hipSuccess && ls.status != 0) {
+                fin = ls;
+                done = true;
+            }
+        }
+        ++c;
+        K = std::min<int64_t>(64, 4ll << std::min(c - 1, 4));
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(evc[(c - 1) & 1]);  // the last chunk's copy
+    if (e == hipSuccess && done) std::memcpy(&fin, hp + ((c - 1) & 1) * (sizeof(LoopState) / 8), sizeof fin);
+    gr_sssp_stats local{};
+    local.loop = GR_LOOP_QUEUED;
+    local.layout = rc.layout;
+    local.iterations = (int32_t)fin.iter;
+    local.pull_iterations = (int32_t)fin.pull_iters;
+    local.edges_pushed = (int64_t)fin.edges_pushed;
+    local.arcs_pulled = (int64_t)fin.arcs_pulled;
+    local.frontier_sum = (int64_t)fin.frontier_sum;
+    local.push_frontier_sum = (int64_t)fin.push_frontier_sum;
+    local.frontier_max = (int32_t)fin.frontier_max;
+    local.push_launches = (int32_t)(fin.iter - fin.pull_iters);
+    if (e == hipSuccess && rc.timing) {
+        // advance launches of the executed iterations (the rest returned at once)
+        for (size_t i = 0; i + 1 < tev.size() && (int64_t)(i / 2) < (int64_t)fin.iter; i += 2) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, tev[i], tev[i + 1]);
+            local.push_us += 1e3 * ms;  // push and pull together: the split is not known per launch
+        }
+        if (fin.pull_iters > 0 && fin.pull_iters == fin.iter) {
+            local.pull_us = local.push_us;
+            local.push_us = 0;
+        }
+    }
+    for (auto &x : tev) (void)hipEventDestroy(x);
+    for (auto &x : evc)
+        if (x) (void)hipEventDestroy(x);
+    hipError_t e2 = hipFreeAsync(ws, st);
+    if (e != hipSuccess) return hip_fail(e, "queued loop");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    if (fin.status == 1) g->last_iters.store((int32_t)fin.iter, std::memory_order_relaxed);
+    if (stats) *stats = local;
+    if (fin.status == 2) return fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)rc.max_iters);
+    return GR_OK;
+}
+
 extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, void *stream,
                                 const gr_sssp_opts *opts, gr_sssp_stats *stats) {
     if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
@@ -652,6 +758,8 @@ extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, 
     if (s != GR_OK) return s;
     int loop = rc.loop;
     if (loop == GR_LOOP_AUTO) loop = g->auto_loop;
+    if (loop == GR_LOOP_QUEUED)
+        return run_queued(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
     if (loop == GR_LOOP_PERSISTENT)
         return run_persistent(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
     return run_host_loop(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
@@ -1035,8 +1143,8 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         DeviceInfo di;
         const bool coop = device_info(g->device, &di) == GR_OK && di.coop &&
                           persistent_grid(g->plain, di.num_cu) >= kMaxParts;
-        knobs.push_back({1, coop ? std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_PERSISTENT}
-                                 : std::vector<int32_t>{GR_LOOP_HOST}});
+        knobs.push_back({1, coop ? std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_PERSISTENT}
+                                 : std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED}});
     }
     knobs.push_back({2, {8, 64, 512}});
     if (g->pull) knobs.push_back({3, {0, 8, 32}});

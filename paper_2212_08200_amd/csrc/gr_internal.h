@@ -86,6 +86,7 @@ struct LoopState {
     unsigned long long frontier_sum;
     unsigned long long frontier_max;
     unsigned long long pull_iters;
+    unsigned long long push_frontier_sum;
 };
 
 size_t frontier_bytes(const DevGraph &g);
@@ -126,6 +127,11 @@ struct PersistentCfg {
 int persistent_grid(const DevGraph &g, int num_cu);
 hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg,
                              hipStream_t st);
+// Queued loop: iteration `iter` as two ordinary launches (advance, filter) of
+// cfg.grid blocks that read the frontier size from device memory and do
+// nothing once the loop state says the query has ended.
+hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg, int64_t iter,
+                       hipEvent_t ev_adv_begin, hipEvent_t ev_adv_end, hipStream_t st);
 
 // Graph build helpers.
 hipError_t launch_pack_arcs(const int32_t *col, const uint32_t *w, int32_t m, uint2 *adj, hipStream_t st);

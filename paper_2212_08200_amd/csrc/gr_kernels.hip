@@ -582,9 +582,103 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
                 ls->pull_iters += 1ull;
             } else {
                 ls->edges_pushed += (unsigned long long)Es;
+                ls->push_frontier_sum += (unsigned long long)Fs;
             }
         }
         if (!grid_sync(ls, (unsigned)G, a.spin_ticks)) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Queued loop: the host enqueues iterations ahead of the device, in chunks,
+// without waiting for the frontier size; each iteration is an advance launch
+// and a filter launch of a fixed grid that take their sizes from the counter
+// slot of the iteration.  The kernel boundary orders the two halves (no grid
+// barrier), and once the advance of some iteration finds the frontier empty
+// (or the cap reached) it ends the query in the loop state, after which the
+// launches still queued return at once.
+
+__device__ __forceinline__ unsigned long long loop_status(const LoopState *ls) {
+    return __hip_atomic_load(&ls->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int WT, int NP>
+__global__ __launch_bounds__(kBlk) void k_step_advance(PersistArgs a, int64_t iter) {
+    LoopState *ls = reinterpret_cast<LoopState *>(a.ctl + kLoopStateWord);
+    if (loop_status(ls) != 0ull) return;
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int kb = (int)(b % NP);
+    const int64_t jb = b / NP, B = G / NP;
+    const unsigned long long *cur = a.ctl + ((iter % kCtlSlots) * kMaxParts);
+    int64_t Fs = 0, Es = 0;
+    int32_t Fk = 0, Ek = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const unsigned long long c = cur[k];
+        const int32_t f = (int32_t)(c & 0xFFFFFFFFull), e = (int32_t)(c >> 32);
+        Fs += f;
+        Es += e;
+        if (k == kb) {
+            Fk = f;
+            Ek = e;
+        }
+    }
+    if (Fs == 0 || iter >= a.max_iters) {
+        if (b == 0 && threadIdx.x == 0) {
+            ls->iter = (unsigned long long)iter;
+            __hip_atomic_store(&ls->status, Fs == 0 ? 1ull : 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    bool pull;
+    switch (a.direction) {
+        case 1: pull = false; break;
+        case 2: pull = true; break;
+        case 3: pull = (iter & 1) != 0; break;
+        default: pull = a.alpha_x16 > 0 && Es * a.alpha_x16 >= (int64_t)16 * a.m;
+    }
+    if (b == 0 && threadIdx.x == 0) {
+        ls->frontier_sum += (unsigned long long)Fs;
+        if ((unsigned long long)Fs > ls->frontier_max) ls->frontier_max = (unsigned long long)Fs;
+        if (pull) {
+            ls->arcs_pulled += (unsigned long long)a.m;
+            ls->pull_iters += 1ull;
+        } else {
+            ls->edges_pushed += (unsigned long long)Es;
+            ls->push_frontier_sum += (unsigned long long)Fs;
+        }
+    }
+    uint8_t *cf = a.flags[iter & 1];
+    uint8_t *nf = a.flags[(iter + 1) & 1];
+    if (pull) {
+        const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
+        for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
+    } else {
+        const int32_t per = (int32_t)max<int64_t>(1, ((int64_t)Ek + B - 1) / B);
+        push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], Fk, Ek, per, jb, nf);
+    }
+}
+
+template <int NP>
+__global__ __launch_bounds__(kBlk) void k_step_filter(PersistArgs a, int64_t iter) {
+    const LoopState *ls = reinterpret_cast<const LoopState *>(a.ctl + kLoopStateWord);
+    if (loop_status(ls) != 0ull) return;
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const unsigned long long *cur = a.ctl + ((iter % kCtlSlots) * kMaxParts);
+    int64_t Fs = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) Fs += (int64_t)(cur[k] & 0xFFFFFFFFull);
+    uint8_t *cf = a.flags[iter & 1];
+    uint8_t *nf = a.flags[(iter + 1) & 1];
+    unsigned long long *cn = a.ctl + (((iter + 1) % kCtlSlots) * kMaxParts);
+    unsigned long long *cz = a.ctl + (((iter + 2) % kCtlSlots) * kMaxParts);
+    const bool dense = a.filter == 2 || (a.filter == 0 && Fs * a.dense_ratio >= a.n);
+    if (dense) {
+        const int64_t nvb = (int64_t)a.fd.chunks * NP;
+        for (int64_t vb = b; vb < nvb; vb += G) filter_dense(a.fd, vb, nf, cf, nullptr, cn, cz);
+    } else {
+        const int64_t nvb = (int64_t)a.ngroups * NP;
+        for (int64_t vb = b; vb < nvb; vb += G) filter_group(a.fg, vb, nf, cf, cn, cz);
     }
 }
 
@@ -1089,9 +1183,8 @@ int persistent_grid(const DevGraph &g, int num_cu) {
     return grid;
 }
 
-hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg,
-                             hipStream_t st) {
-    PersistArgs a;
+static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg,
+                         PersistArgs &a) {
     FilterArgs &fg = a.fg;
     fg.np = g.np;
     fg.pro = g.pro;
@@ -1135,8 +1228,33 @@ hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &
     a.filter = cfg.filter;
     a.dense_ratio = cfg.dense_ratio;
     a.spin_ticks = cfg.spin_ticks;
+}
+
+hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg,
+                             hipStream_t st) {
+    PersistArgs a;
+    persist_args(g, dist, f, cfg, a);
     if (g.np == 1) return g.wt == 1 ? coop_launch<1, 1>(a, cfg.grid, st) : coop_launch<0, 1>(a, cfg.grid, st);
     return g.wt == 1 ? coop_launch<1, kMaxParts>(a, cfg.grid, st) : coop_launch<0, kMaxParts>(a, cfg.grid, st);
+}
+
+hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg, int64_t iter,
+                       hipEvent_t ev_adv_begin, hipEvent_t ev_adv_end, hipStream_t st) {
+    PersistArgs a;
+    persist_args(g, dist, f, cfg, a);
+    const dim3 grid((unsigned)cfg.grid), blk(kBlk);
+    if (ev_adv_begin) (void)hipEventRecord(ev_adv_begin, st);
+    if (g.np == 1) {
+        if (g.wt == 1) hipLaunchKernelGGL((k_step_advance<1, 1>), grid, blk, 0, st, a, iter);
+        else hipLaunchKernelGGL((k_step_advance<0, 1>), grid, blk, 0, st, a, iter);
+    } else {
+        if (g.wt == 1) hipLaunchKernelGGL((k_step_advance<1, kMaxParts>), grid, blk, 0, st, a, iter);
+        else hipLaunchKernelGGL((k_step_advance<0, kMaxParts>), grid, blk, 0, st, a, iter);
+    }
+    if (ev_adv_end) (void)hipEventRecord(ev_adv_end, st);
+    if (g.np == 1) hipLaunchKernelGGL((k_step_filter<1>), grid, blk, 0, st, a, iter);
+    else hipLaunchKernelGGL((k_step_filter<kMaxParts>), grid, blk, 0, st, a, iter);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -38,13 +38,13 @@ def assert_same(got, want, tag):
             tag, len(bad), v, int(got[v]), int(want[v])))
 
 
-LOOPS = {"host": 1, "persistent": 2}
+LOOPS = {"host": 1, "persistent": 2, "queued": 3}
 
 
 def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate"), flags=gr.GR_FORCE_PARTITION,
-                   loops=("host", "persistent")):
+                   loops=("host", "persistent", "queued")):
     """Every direction policy, with both push layouts (plain CSR and partitioned)
-    and both loop drivers (host-driven, device-driven persistent)."""
+    and every loop driver (host-driven, device-driven persistent, queued)."""
     G = gr.Graph.from_csr(g, flags=flags)
     info = G.info()
     layouts = [gr.GR_LAYOUT_PLAIN] + ([gr.GR_LAYOUT_PARTITIONED] if info["partitions"] > 1 else [])
@@ -161,10 +161,17 @@ def test_persistent_loop_stats_match_host_loop():
     G = gr.Graph.from_csr(g)
     try:
         a = run(G, 0, DIRS["push"], loop=LOOPS["host"])[1]
-        b = run(G, 0, DIRS["push"], loop=LOOPS["persistent"])[1]
-        assert a["iterations"] == b["iterations"] == L
-        assert a["edges_pushed"] == b["edges_pushed"] == L
-        assert a["frontier_sum"] == b["frontier_sum"] == L
+        for lp in ("persistent", "queued", "queued"):  # queued twice: the second starts from a predicted chunk
+            b = run(G, 0, DIRS["push"], loop=LOOPS[lp])[1]
+            assert a["iterations"] == b["iterations"] == L, lp
+            assert a["edges_pushed"] == b["edges_pushed"] == L, lp
+            assert a["frontier_sum"] == b["frontier_sum"] == L, lp
+            assert a["push_frontier_sum"] == b["push_frontier_sum"] == L, lp
+        dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        for lp in ("host", "persistent", "queued"):
+            st = gr.gr_sssp_ex(G.handle, 0, dist, loop=LOOPS[lp], timing=1)
+            torch.cuda.synchronize()
+            assert st["push_us"] > 0 and st["iterations"] == L, lp
     finally:
         G.close()
 
@@ -194,10 +201,13 @@ def test_errors_on_gpu():
         with pytest.raises(gr.GrError) as ei:
             gr.gr_sssp(G.handle, g.n, dist)
         assert ei.value.status == gr.GR_ERR_SOURCE_RANGE
-        for lp in (1, 2):
+        for lp in (1, 2, 3):
             with pytest.raises(gr.GrError) as ei:
                 gr.gr_sssp_ex(G.handle, 0, dist, max_iters=3, loop=lp)
             assert ei.value.status == gr.GR_ERR_ITER_LIMIT
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_ex(G.handle, 0, dist, loop=4)
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
     finally:
         G.close()
     Gp = gr.Graph.from_csr(g, flags=gr.GR_NO_PULL)
@@ -268,9 +278,9 @@ def test_road2048_config():
     check_all_dirs(g, srcs, "road2048", dirs=("auto",), flags=0)
 
 
-def test_grid2048_config_persistent():
+def test_grid2048_config_device_loops():
     g, srcs = gg.workload("grid2048")
-    check_all_dirs(g, srcs, "grid2048", dirs=("push",), flags=0, loops=("persistent",))
+    check_all_dirs(g, srcs, "grid2048", dirs=("push",), flags=0, loops=("persistent", "queued"))
 
 
 def test_rmat22_config_sampled_sources():
