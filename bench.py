@@ -57,7 +57,9 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--layout", type=int, default=0, help="gr_layout (0 auto, 1 plain, 2 partitioned)")
     ap.add_argument("--direction", type=int, default=0, help="gr_direction (0 auto, 1 push, 2 pull)")
-    ap.add_argument("--loop", type=int, default=0, help="gr_loop_mode (0 auto, 1 host, 2 persistent)")
+    ap.add_argument("--loop", type=int, default=0, help="gr_loop_mode (0 auto, 1 host, 2 persistent, 3 queued)")
+    ap.add_argument("--delta", type=float, default=0.0,
+                    help="near-far split width in weight units (0: the graph's default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-source batched comparison")
@@ -108,7 +110,8 @@ def main():
     srcs = [int(s) for s in srcs]
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    opts = dict(loop=args.loop, direction=args.direction, layout=args.layout)
+    opts = dict(loop=args.loop, direction=args.direction, layout=args.layout,
+                delta=gr.delta_bits(args.delta, g.wtype) if args.delta > 0 else 0)
 
     # m_reached per source (from the GPU result of its first run)
     reached = {}
@@ -204,7 +207,8 @@ def main():
         "data": "synthetic (seeded generator)",
         "config": {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m,
                    "layout": {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?") if stats_last else None,
-                   "loop": {1: "host", 2: "persistent"}.get(stats_last["loop"], "?") if stats_last else None,
+                   "loop": {1: "host", 2: "persistent", 3: "queued"}.get(stats_last["loop"], "?") if stats_last else None,
+                   "delta": args.delta or None,
                    "iterations_per_query": iters / max(args.steps, 1)},
         "roofline": roof,
         "cpu_baseline": cpu,

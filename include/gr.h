@@ -155,7 +155,16 @@ typedef struct {
                            2 stream the per-partition member lists (large frontiers) */
     int32_t barrier_timeout_us; /* device-driven loop: bound on one grid-barrier wait;
                                    0 = 20 s.  Exceeding it ends the query with GR_ERR_HIP. */
+    uint32_t delta;     /* near-far split width, in the weight type (a uint32 value, or the
+                           bits of a positive finite binary32): improved vertices whose
+                           distance is not below the threshold are held back until the
+                           frontier runs empty, then the threshold rises to the smallest
+                           held-back distance (+) delta.  0 = the graph's default (off
+                           unless gr_graph_tune chose one); GR_DELTA_OFF = off.  Needs
+                           push: GR_DIR_PULL / GR_DIR_ALTERNATE are GR_ERR_INVALID_ARG. */
 } gr_sssp_opts;
+
+#define GR_DELTA_OFF 0xFFFFFFFFu
 
 typedef struct {
     int32_t iterations;        /* advance/filter rounds executed */
@@ -189,11 +198,13 @@ typedef struct {
     double default_ms;    /* the same before tuning */
     int32_t trials;       /* timed configurations */
     int32_t from_cache;   /* 1 when read from the tuning cache file */
+    uint32_t delta;       /* chosen near-far split width (weight-type bits; 0 = off) */
+    int32_t reserved;
 } gr_tune_result;
 
 /*
  * Autotuner: times candidate schedules -- push layout, loop driver, filter
- * threshold, pull threshold -- with a greedy search (one knob at a time, each
+ * threshold, pull threshold, near-far split width -- with a greedy search (one knob at a time, each
  * candidate timed as the median of `reps` queries from srcs[0..nsrcs)), and
  * keeps the fastest as the graph's AUTO configuration.  Every candidate
  * computes the same distances.  When the environment variable GR_TUNE_CACHE

@@ -52,6 +52,15 @@ GR_LOOP_AUTO = 0
 GR_LOOP_HOST = 1
 GR_LOOP_PERSISTENT = 2
 GR_LOOP_QUEUED = 3
+GR_DELTA_OFF = 0xFFFFFFFF
+
+
+def delta_bits(value, wt) -> int:
+    """The gr_sssp_opts.delta encoding of a split width: the value for uint32
+    weights, the binary32 bit pattern for fp32 weights."""
+    if int(wt) == GR_W_F32:
+        return int(np.array([value], np.float32).view(np.uint32)[0])
+    return int(value)
 
 GR_DIR_AUTO = 0
 GR_DIR_PUSH = 1
@@ -80,7 +89,7 @@ class GrError(RuntimeError):
 class gr_sssp_opts(ctypes.Structure):
     _fields_ = [("loop", ctypes.c_int32), ("direction", ctypes.c_int32), ("alpha_x16", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("layout", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("filter", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32)]
+                ("filter", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32), ("delta", ctypes.c_uint32)]
 
 
 class gr_sssp_stats(ctypes.Structure):
@@ -98,7 +107,8 @@ class gr_sssp_stats(ctypes.Structure):
 class gr_tune_result(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("loop", ctypes.c_int32), ("dense_ratio", ctypes.c_int32),
                 ("alpha_x16", ctypes.c_int32), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
-                ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+                ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("delta", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -251,9 +261,10 @@ def gr_sssp(g: int, src: int, dist_out, stream=None) -> None:
 
 
 def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
-               max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, barrier_timeout_us=0) -> dict:
+               max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, barrier_timeout_us=0, delta=0) -> dict:
+    """delta: near-far split width as weight-type bits (see delta_bits), 0 = graph default, GR_DELTA_OFF = off."""
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
-                     timing=timing, filter=filter, barrier_timeout_us=barrier_timeout_us)
+                     timing=timing, filter=filter, barrier_timeout_us=barrier_timeout_us, delta=delta)
     st = gr_sssp_stats()
     _check(lib().gr_sssp_ex(g, int(src), _ptr(dist_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()

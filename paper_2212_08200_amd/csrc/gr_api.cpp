@@ -12,6 +12,7 @@
 #include <unordered_map>
 #include <cstdarg>
 #include <cmath>
+#include <cfloat>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -151,6 +152,7 @@ struct gr_graph {
     int32_t auto_loop = GR_LOOP_HOST;
     int32_t auto_dense_ratio = kDenseRatio;
     int32_t auto_alpha_x16 = 0;
+    uint32_t auto_delta = 0;  // near-far split width (0: off)
     // iterations of the last completed queued-loop query (first chunk size)
     mutable std::atomic<int32_t> last_iters{0};
     double locality = 1.0;  // fraction of arcs with |u - v| < locality_span(n)
@@ -444,6 +446,7 @@ struct RunCfg {
     int layout;
     int filter;
     int32_t dense_ratio;
+    uint32_t delta;  // near-far split width (weight-type bits); 0 = off
     int64_t barrier_timeout_us;
     const DevGraph *dg;
 };
@@ -473,6 +476,21 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
     rc->dense_ratio = g->auto_dense_ratio;
     rc->barrier_timeout_us = (o && o->barrier_timeout_us > 0) ? o->barrier_timeout_us : 20000000;
     if (rc->filter < 0 || rc->filter > 2) return fail(GR_ERR_INVALID_ARG, "unknown filter mode %d", rc->filter);
+    uint32_t d = (o && o->delta) ? o->delta : g->auto_delta;
+    if (d == GR_DELTA_OFF) d = 0;
+    if (d && g->plain.wt == GR_W_F32) {
+        float x;
+        std::memcpy(&x, &d, 4);
+        if (!(x > 0.f && x <= FLT_MAX)) return fail(GR_ERR_INVALID_ARG, "delta must be a positive finite binary32");
+    }
+    rc->delta = d;
+    if (d) {
+        if (rc->direction == GR_DIR_PULL || rc->direction == GR_DIR_ALTERNATE)
+            return fail(GR_ERR_INVALID_ARG, "the near-far split runs push only");
+        rc->alpha_x16 = 0;
+        // each raise of the threshold settles at least one vertex for good
+        if (!(o && o->max_iters > 0)) rc->max_iters = std::min<int64_t>(8 * ((int64_t)g->plain.n + 1), INT32_MAX);
+    }
     return GR_OK;
 }
 
@@ -486,12 +504,6 @@ static bool choose_pull(const gr_graph *g, const RunCfg &rc, int64_t iter, int64
     }
 }
 
-static void read_counts(const unsigned long long *h, FrontierCounts *c) {
-    for (int k = 0; k < kMaxParts; ++k) {
-        c->F[k] = (int32_t)(h[k] & 0xFFFFFFFFull);
-        c->E[k] = (int32_t)(h[k] >> 32);
-    }
-}
 
 static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
                                gr_sssp_stats *stats) {
@@ -515,36 +527,37 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
         for (auto &x : ev)
             if (hipEventCreate(&x) != hipSuccess) x = nullptr;
     const bool timed = rc.timing && ev[0] && ev[1] && ev[2];
-    hipError_t e = launch_init(dg, dist, src, f, st);
-    // Frontier 0 = {src}: its counts are known on the host.
+    const bool split = rc.delta != 0;
+    uint32_t T = split ? next_threshold(0u, rc.delta, dg.wt) : kInfU32;
+    hipError_t e = launch_init(dg, dist, src, f, T, split, st);
+    // Frontier 0 = {src}: its counts are known on the host for one partition.
     FrontierCounts c{};
-    {
-        const int64_t stride = (int64_t)dg.n + 1;
-        if (dg.np == 1) {
-            const int32_t d = g->h_ro[src + 1] - g->h_ro[src];
-            c.F[0] = d > 0 ? 1 : 0;
-            c.E[0] = d;
-        } else {
-            e = e == hipSuccess ? hipMemcpyAsync(hp, f.ctl, sizeof(unsigned long long) * kMaxParts,
-                                                 hipMemcpyDeviceToHost, st)
-                                : e;
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            read_counts(hp, &c);
-        }
-        (void)stride;
+    if (dg.np == 1) {
+        const int32_t d = g->h_ro[src + 1] - g->h_ro[src];
+        c.F[0] = d > 0 ? 1 : 0;
+        c.E[0] = d;
+    } else {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hp, f.ctl, sizeof(unsigned long long) * kSlotWords, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        read_counts(hp, &c);
     }
     int64_t iter = 0;
-    while (e == hipSuccess && c.Fsum() > 0) {
+    while (e == hipSuccess) {
+        // An empty frontier ends the query unless the near-far split holds
+        // vertices back: then the round only raises the threshold and filters.
+        const bool idle = c.Fsum() == 0;
+        if (idle && (!split || c.far_count == 0)) break;
         if (iter >= rc.max_iters) {
             status = fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)rc.max_iters);
             break;
         }
+        if (idle) T = next_threshold(c.far_min, rc.delta, dg.wt);
         const int64_t E = c.Esum();
-        const bool pull = choose_pull(g, rc, iter, E);
-        local.frontier_sum += c.Fsum();
-        local.frontier_max = std::max<int64_t>(local.frontier_max, c.Fsum());
+        const bool pull = !idle && choose_pull(g, rc, iter, E);
         if (timed) (void)hipEventRecord(ev[0], st);
-        if (pull) {
+        if (idle) {
+        } else if (pull) {
             e = launch_pull(dg, dist, f, iter, st);
             local.pull_iterations++;
             local.arcs_pulled += dg.m;
@@ -554,13 +567,15 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
             local.push_frontier_sum += c.Fsum();
             local.push_launches++;
         }
+        local.frontier_sum += c.Fsum();
+        local.frontier_max = std::max<int64_t>(local.frontier_max, c.Fsum());
         if (timed) (void)hipEventRecord(ev[1], st);
         // the streaming filter pays off once the next frontier is likely large
         const bool dense = rc.filter == 2 || (rc.filter == 0 && c.Fsum() * rc.dense_ratio >= (int64_t)dg.n);
-        if (e == hipSuccess) e = launch_filter(dg, f, iter, nullptr, dense, st);
+        if (e == hipSuccess) e = launch_filter(dg, f, iter, nullptr, dense, dist, split, T, st);
         if (timed) (void)hipEventRecord(ev[2], st);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(hp, counters_after(f, iter), sizeof(unsigned long long) * kMaxParts,
+            e = hipMemcpyAsync(hp, counters_after(f, iter), sizeof(unsigned long long) * kSlotWords,
                                hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) break;
@@ -599,6 +614,7 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     cfg.direction = rc.direction;
     cfg.filter = rc.filter;
     cfg.dense_ratio = rc.dense_ratio;
+    cfg.delta = rc.delta;
     cfg.spin_ticks = (uint64_t)rc.barrier_timeout_us * (uint64_t)di.wall_khz / 1000ull;
     unsigned long long *hp = pinned_slot();
     if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
@@ -608,7 +624,8 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     frontier_carve(f, ws, dg);
     hipEvent_t ev[2] = {nullptr, nullptr};
     const bool timed = rc.timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
-    hipError_t e = launch_init(dg, dist, src, f, st);
+    hipError_t e = launch_init(dg, dist, src, f, rc.delta ? next_threshold(0u, rc.delta, dg.wt) : kInfU32,
+                               rc.delta != 0, st);
     if (e == hipSuccess && timed) e = hipEventRecord(ev[0], st);
     if (e == hipSuccess) e = launch_persistent(dg, dist, f, cfg, st);
     if (e == hipSuccess && timed) e = hipEventRecord(ev[1], st);
@@ -668,6 +685,7 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     cfg.direction = rc.direction;
     cfg.filter = rc.filter;
     cfg.dense_ratio = rc.dense_ratio;
+    cfg.delta = rc.delta;
     cfg.spin_ticks = 0;
     void *ws = nullptr;
     HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
@@ -678,7 +696,9 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     for (auto &x : evc)
         if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
     std::vector<hipEvent_t> tev;  // with timing: begin/end of each advance launch
-    if (e == hipSuccess) e = launch_init(dg, dist, src, f, st);
+    if (e == hipSuccess)
+        e = launch_init(dg, dist, src, f, rc.delta ? next_threshold(0u, rc.delta, dg.wt) : kInfU32, rc.delta != 0,
+                        st);
     int64_t issued = 0;
     int c = 0;
     int64_t K = std::clamp<int64_t>(g->last_iters.load(std::memory_order_relaxed) + 1, 4, 256);
@@ -799,7 +819,7 @@ static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, ui
     if (e == hipSuccess) e = hipMemcpyAsync(w.srcs, sv.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_batch_init(dg, w, k, st);
     // The filter of "iteration -1" turns the source flags into frontier 0.
-    if (e == hipSuccess) e = launch_filter(dg, w.f, -1, nullptr, false, st);
+    if (e == hipSuccess) e = launch_filter(dg, w.f, -1, nullptr, false, nullptr, false, kInfU32, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(hp, counters_after(w.f, -1), sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -813,7 +833,9 @@ static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, ui
             break;
         }
         e = launch_batch_push(dg, w, iter, F, E, di.num_cu, st);
-        if (e == hipSuccess) e = launch_filter(dg, w.f, iter, w.mask[iter & 1], (int64_t)F * kDenseRatio >= dg.n, st);
+        if (e == hipSuccess)
+            e = launch_filter(dg, w.f, iter, w.mask[iter & 1], (int64_t)F * kDenseRatio >= dg.n, nullptr, false,
+                              kInfU32, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hp, counters_after(w.f, iter), sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1042,15 +1064,17 @@ static bool cache_lookup(const std::string &sig, gr_tune_result *r) {
     while (fgets(line, sizeof line, f)) {
         char s[300];
         int lay, loop, dr, al;
+        unsigned dl;
         double ms;
         if (sscanf(line, "{\"sig\": \"%299[^\"]\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
-                         "\"best_ms\": %lf}",
-                   s, &lay, &loop, &dr, &al, &ms) == 6 &&
+                         "\"delta\": %u, \"best_ms\": %lf}",
+                   s, &lay, &loop, &dr, &al, &dl, &ms) == 7 &&
             sig == s) {
             r->layout = lay;
             r->loop = loop;
             r->dense_ratio = dr;
             r->alpha_x16 = al;
+            r->delta = dl;
             r->best_ms = ms;
             found = true;  // the last matching line wins
         }
@@ -1065,13 +1089,14 @@ static void cache_store(const std::string &sig, const gr_tune_result &r) {
     FILE *f = fopen(path, "a");
     if (!f) return;
     fprintf(f, "{\"sig\": \"%s\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
-               "\"best_ms\": %.6f}\n",
-            sig.c_str(), r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.best_ms);
+               "\"delta\": %u, \"best_ms\": %.6f}\n",
+            sig.c_str(), r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.best_ms);
     fclose(f);
 }
 
 struct TuneCfg {
     int32_t layout, loop, dense_ratio, alpha_x16;
+    uint32_t delta;
 };
 
 static void apply_auto(gr_graph *g, const TuneCfg &c) {
@@ -1079,6 +1104,43 @@ static void apply_auto(gr_graph *g, const TuneCfg &c) {
     g->auto_loop = c.loop;
     g->auto_dense_ratio = c.dense_ratio;
     g->auto_alpha_x16 = c.alpha_x16;
+    g->auto_delta = c.delta;
+}
+
+// Near-far split widths to try: multiples of the mean weight of a sample of
+// arcs (weight-type bits).
+static std::vector<uint32_t> delta_candidates(const gr_graph *g, hipStream_t st) {
+    std::vector<uint32_t> out;
+    const int32_t m = g->plain.m;
+    if (m <= 0) return out;
+    const int32_t ns = std::min<int32_t>(m, 4096);
+    std::vector<uint2> h((size_t)ns);
+    if (hipMemcpyAsync(h.data(), g->plain.adj, sizeof(uint2) * (size_t)ns, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return out;
+    double mean = 0;
+    for (const uint2 &a : h) {
+        if (g->plain.wt == GR_W_F32) {
+            float x;
+            std::memcpy(&x, &a.y, 4);
+            mean += x;
+        } else {
+            mean += a.y;
+        }
+    }
+    mean /= ns;
+    for (double f : {0.25, 1.0, 4.0, 16.0}) {
+        const double d = mean * f;
+        uint32_t bits;
+        if (g->plain.wt == GR_W_F32) {
+            const float x = (float)std::max(d, 1e-30);
+            std::memcpy(&bits, &x, 4);
+        } else {
+            bits = (uint32_t)std::min(std::max(d, 1.0), 4.0e9);
+        }
+        out.push_back(bits);
+    }
+    return out;
 }
 
 extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsrcs, int32_t reps, void *stream,
@@ -1094,7 +1156,8 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
     if (cache_lookup(sig, &r)) {
         if (r.layout == GR_LAYOUT_PARTITIONED && !g->has_part) r.layout = GR_LAYOUT_PLAIN;
         if (r.alpha_x16 > 0 && !g->pull) r.alpha_x16 = 0;
-        apply_auto(g, TuneCfg{r.layout, r.loop, r.dense_ratio, r.alpha_x16});
+        if (r.delta) r.alpha_x16 = 0;
+        apply_auto(g, TuneCfg{r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta});
         r.from_cache = 1;
         if (out) *out = r;
         return GR_OK;
@@ -1110,6 +1173,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         o.layout = c.layout;
         o.alpha_x16 = c.alpha_x16 > 0 ? c.alpha_x16 : 0;
         o.direction = c.alpha_x16 > 0 ? GR_DIR_AUTO : GR_DIR_PUSH;
+        o.delta = c.delta ? c.delta : GR_DELTA_OFF;
         const int32_t saved = g->auto_dense_ratio;
         g->auto_dense_ratio = c.dense_ratio;
         std::vector<double> t;
@@ -1131,7 +1195,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         *ms = t[t.size() / 2];
         return GR_OK;
     };
-    TuneCfg best{g->auto_layout, g->auto_loop, g->auto_dense_ratio, g->auto_alpha_x16};
+    TuneCfg best{g->auto_layout, g->auto_loop, g->auto_dense_ratio, g->auto_alpha_x16, g->auto_delta};
     double best_ms = 0;
     status = measure(best, &best_ms);
     const double default_ms = best_ms;
@@ -1148,14 +1212,27 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
     }
     knobs.push_back({2, {8, 64, 512}});
     if (g->pull) knobs.push_back({3, {0, 8, 32}});
+    {
+        std::vector<int32_t> ds{0};
+        for (uint32_t d : delta_candidates(g, st)) ds.push_back((int32_t)d);
+        knobs.push_back({4, ds});
+    }
     for (const auto &kv : knobs) {
         for (int32_t v : kv.second) {
             if (status != GR_OK) break;
             TuneCfg c = best;
-            int32_t *field = kv.first == 0 ? &c.layout : kv.first == 1 ? &c.loop : kv.first == 2 ? &c.dense_ratio
-                                                                                               : &c.alpha_x16;
-            if (*field == v) continue;
-            *field = v;
+            if (kv.first == 4) {
+                if (c.delta == (uint32_t)v) continue;
+                c.delta = (uint32_t)v;
+                if (c.delta) c.alpha_x16 = 0;  // the split runs push only
+            } else if (kv.first == 3 && c.delta) {
+                continue;
+            } else {
+                int32_t *field = kv.first == 0 ? &c.layout : kv.first == 1 ? &c.loop : kv.first == 2 ? &c.dense_ratio
+                                                                                                   : &c.alpha_x16;
+                if (*field == v) continue;
+                *field = v;
+            }
             double ms = 0;
             status = measure(c, &ms);
             if (status == GR_OK && ms < best_ms) {
@@ -1172,6 +1249,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
     r.loop = best.loop;
     r.dense_ratio = best.dense_ratio;
     r.alpha_x16 = best.alpha_x16;
+    r.delta = best.delta;
     r.best_ms = best_ms;
     r.default_ms = default_ms;
     r.trials = trials;

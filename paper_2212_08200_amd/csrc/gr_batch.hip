@@ -206,6 +206,7 @@ void batch_carve(BatchWs &w, void *base, const DevGraph &g) {
     for (int i = 0; i < 2; ++i) {
         f.flags[i] = reinterpret_cast<uint8_t *>(p);
         p += align256((size_t)nv);
+        f.far[i] = nullptr;  // no near-far split for batched queries
     }
     for (int k = 0; k < kMaxParts; ++k) {
         f.qse[k] = nullptr;

@@ -54,14 +54,21 @@ struct DevGraph {
 // Per-query frontier workspace (device memory).
 //   flags[2]         frontier as one byte per vertex (current / next, by
 //                    iteration parity), padded to whole groups
-//   qse[k], qs[k]    sparse frontier of partition k: (first arc, u) and the
-//                    exclusive prefix sum of the arc counts
-//   ctl              3 slots x kMaxParts packed counters (low 32 bits = F_k,
-//                    high 32 bits = E_k), rotated over three iterations so that
-//                    a slot is cleared one iteration after its last use; then
-//                    the device-driven loop state
+//   far[2]           near-far split: one byte per vertex that was improved
+//                    but held back because its distance is not below the
+//                    current threshold (read / written by iteration parity)
+//   qse[k], qs[k]    sparse frontier of partition k: (first arc, dist[u]) --
+//                    (first arc, u) for batched queries -- and the exclusive
+//                    prefix sum of the arc counts
+//   ctl              3 slots of kSlotWords counters, rotated over three
+//                    iterations so that a slot is cleared one iteration after
+//                    its last use: word k < 8 packs F_k (low 32 bits) and E_k
+//                    (high 32 bits) of partition k, word 8 counts held-back
+//                    vertices and word 9 holds the max of ~dist over them;
+//                    then the device-driven loop state
 struct Frontier {
     uint8_t *flags[2];
+    uint8_t *far[2];
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
     unsigned long long *ctl;
@@ -71,8 +78,11 @@ struct Frontier {
 };
 
 constexpr int kCtlSlots = 3;
-constexpr int kCtlWords = 64;       // 3 x 8 counters, then LoopState
-constexpr int kLoopStateWord = 32;  // LoopState at ctl + 32
+constexpr int kSlotWords = 16;
+constexpr int kFarCountWord = 8;    // within a slot
+constexpr int kFarMaxInvWord = 9;   // within a slot: max of ~dist[u] over held-back u
+constexpr int kCtlWords = 64;       // 3 slots of 16 words, then LoopState
+constexpr int kLoopStateWord = 48;  // LoopState at ctl + 48
 constexpr int32_t kDenseRatio = 64;  // default: streaming filter when |frontier| >= n / 64
 
 // Device-driven loop state.
@@ -87,7 +97,10 @@ struct LoopState {
     unsigned long long frontier_max;
     unsigned long long pull_iters;
     unsigned long long push_frontier_sum;
+    unsigned long long threshold;  // near-far: distances below it are pushed now
 };
+static_assert(kLoopStateWord + sizeof(LoopState) / 8 <= kCtlWords, "loop state fits the control block");
+static_assert(kCtlSlots * kSlotWords <= kLoopStateWord, "counter slots fit below the loop state");
 
 size_t frontier_bytes(const DevGraph &g);
 void frontier_carve(Frontier &f, void *base, const DevGraph &g);
@@ -96,20 +109,33 @@ void frontier_carve(Frontier &f, void *base, const DevGraph &g);
 struct FrontierCounts {
     int32_t F[kMaxParts];
     int32_t E[kMaxParts];
+    int64_t far_count;  // held-back vertices (near-far split)
+    uint32_t far_min;   // their smallest distance (bits)
     int64_t Fsum() const;
     int64_t Esum() const;
 };
+void read_counts(const unsigned long long *slot, FrontierCounts *c);
+
+// Near-far threshold after the near frontier ran empty: far_min (+) delta in
+// the weight type, and always above far_min so that the smallest held-back
+// vertex is released.
+uint32_t next_threshold(uint32_t far_min, uint32_t delta, int wt);
 
 // ---- launch wrappers (gr_kernels.hip) -------------------------------------
-hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Frontier &f, hipStream_t st);
+// threshold: first near-far threshold (kInfU32 when the split is off); with
+// use_far the held-back flags are cleared too.
+hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Frontier &f, uint32_t threshold,
+                       bool use_far, hipStream_t st);
 hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, const FrontierCounts &c,
                        int num_cu, hipStream_t st);
 hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st);
 // zmask: optional per-vertex 64-bit masks (batched queries) cleared by the filter.
 // dense: stream the membership lists (large frontiers) instead of visiting
 // the 4096-vertex groups that hold flags (small frontiers).
+// use_far: near-far split at `threshold` (needs dist): flagged or held-back
+// vertices below it join the frontier, the others are held back.
 hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uint64_t *zmask, bool dense,
-                         hipStream_t st);
+                         const uint32_t *dist, bool use_far, uint32_t threshold, hipStream_t st);
 // Device address of the counter slot filled by the filter of iteration `iter`.
 unsigned long long *counters_after(const Frontier &f, int64_t iter);
 
@@ -122,6 +148,7 @@ struct PersistentCfg {
     int32_t dense_ratio;  // auto filter: streaming when |frontier| * dense_ratio >= n
     int32_t grid;         // co-resident blocks, a multiple of kMaxParts
     uint64_t spin_ticks;  // grid-barrier wait bound, in wall_clock64 ticks
+    uint32_t delta;       // near-far split width (weight-type bits); 0 = off
 };
 // Largest co-resident grid for the graph's layout (0 if none).
 int persistent_grid(const DevGraph &g, int num_cu);

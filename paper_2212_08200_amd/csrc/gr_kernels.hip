@@ -14,8 +14,9 @@
 //             (Section III-C): each vertex takes the min over its in-arcs from
 //             active vertices; one owner per vertex, no global atomics on dist.
 //   k_filter  deduplicated, compacted next frontier from the flags, written
-//             as per-partition queues of (first arc, u) plus the prefix sum of
-//             arc counts, and the totals the convergence test reads.
+//             as per-partition queues of (first arc, dist[u]) -- (first arc, u)
+//             for batched queries -- plus the prefix sum of arc counts, and
+//             the totals the convergence test reads.
 //
 // Partitioned push layout: arcs are grouped by destination range into up to
 // eight partitions; block b of the push works on partition b % 8.  Workgroups
@@ -31,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 
 namespace gr {
 
@@ -67,10 +69,12 @@ struct InitArgs {
     int32_t src;
     const int32_t *pro;
     uint8_t *flags0, *flags1;
+    uint8_t *far0, *far1;  // NULL when the near-far split is off
     int64_t nflag;  // bytes per flag array (multiple of 16)
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
     unsigned long long *ctl;
+    uint32_t threshold;
 };
 
 __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
@@ -82,18 +86,23 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
     for (int64_t w = tid; w < a.nflag / 16; w += stride) {
         uint4 z = make_uint4(0u, 0u, 0u, 0u);
         reinterpret_cast<uint4 *>(a.flags1)[w] = z;
+        if (a.far0) {
+            reinterpret_cast<uint4 *>(a.far0)[w] = z;
+            reinterpret_cast<uint4 *>(a.far1)[w] = z;
+        }
         if (w == sw) reinterpret_cast<uint32_t *>(&z)[(src >> 2) & 3] = 1u << ((src & 3) * 8);
         reinterpret_cast<uint4 *>(a.flags0)[w] = z;
     }
     if (blockIdx.x == 0) {
         if (threadIdx.x < kCtlWords) a.ctl[threadIdx.x] = 0ull;
         __syncthreads();
+        if (threadIdx.x == 0) reinterpret_cast<LoopState *>(a.ctl + kLoopStateWord)->threshold = a.threshold;
         if (threadIdx.x < a.np) {
             const int k = threadIdx.x;
             const int32_t st = a.pro[(int64_t)src * a.np + k];
             const int32_t d = a.pro[(int64_t)(src + 1) * a.np + k] - st;
             if (d > 0) {
-                a.qse[k][0] = make_uint2((uint32_t)st, (uint32_t)src);
+                a.qse[k][0] = make_uint2((uint32_t)st, 0u);  // (first arc, dist[src])
                 a.qs[k][0] = 0;
                 a.ctl[k] = 1ull | ((unsigned long long)d << 32);
             }
@@ -143,13 +152,14 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
     int32_t e = beg;
     while (e < end) {
         const int32_t cnt = min(kWin, F - i0);
-        // dist[u] is read now rather than when the filter ran: a value lowered
-        // since then (earlier in this advance) saves relaxations.
+        // entries carry dist[u] as the filter read it (after the previous
+        // advance): a coalesced read there instead of a random one per entry
+        // and partition here
         for (int t = threadIdx.x; t < cnt; t += kBlk) {
             const uint2 q = qse[i0 + t];
             sS[t] = s[i0 + t];
             sRow[t] = q.x;
-            sDu[t] = dist[q.y];
+            sDu[t] = q.y;
         }
         // sS[cnt] bounds the window's ranks; entries past it are padded with
         // INT32_MAX so that the search below needs no bounds test.
@@ -299,24 +309,73 @@ struct FilterArgs {
     int32_t np;
     const int32_t *pro;
     uint64_t *zmask;  // when set (batched queries): per-vertex masks cleared by partition-0 blocks
+    const uint32_t *dist;  // single-source: entries are (first arc, dist[u]); NULL (batched): (first arc, u)
     const uint8_t *nflags;
     uint8_t *cflags;
+    const uint8_t *far_cur;  // near-far split (NULL: off): held-back flags read ...
+    uint8_t *far_next;       // ... and written
+    uint32_t threshold;
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
     unsigned long long *ctl_next;
     unsigned long long *ctl_zero;
 };
 
+// Bytes of a 16-byte flag word that are non-zero, as 16 bits.
+__device__ __forceinline__ uint32_t nonzero_bytes(uint4 w) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        const uint32_t word = b < 4 ? w.x : b < 8 ? w.y : b < 12 ? w.z : w.w;
+        m |= (((word >> ((b & 3) * 8)) & 0xFFu) != 0u ? 1u : 0u) << b;
+    }
+    return m;
+}
+
+// The inverse: byte b of the word is 1 when bit b is set.
+__device__ __forceinline__ uint4 bytes_of_bits(uint32_t m) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        w[q] = 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) w[q] |= ((m >> (q * 4 + b)) & 1u) << (b * 8);
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Near-far split of 16 consecutive vertices from base: of the candidates
+// (bits of cand), those at or above the threshold are held back (returned).
+__device__ __forceinline__ uint32_t held_back(const uint32_t *__restrict__ dist, int64_t base, uint32_t cand,
+                                              uint32_t T, uint32_t *cnt, uint32_t *inv) {
+    uint32_t held = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        if ((cand >> b) & 1u) {
+            const uint32_t du = dist[base + b];
+            if (du >= T) {
+                held |= 1u << b;
+                *cnt += 1u;
+                *inv = max(*inv, ~du);
+            }
+        }
+    }
+    return held;
+}
+
 // a: the iteration-independent arguments (kernel-argument resident); the
-// flags and counter slots of the iteration are passed separately.
+// flags, held-back flags, threshold and counter slots of the iteration are
+// passed separately.
 __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t vb, const uint8_t *__restrict__ nflags,
                                              uint8_t *__restrict__ cflags, unsigned long long *ctl_next,
-                                             unsigned long long *ctl_zero) {
+                                             unsigned long long *ctl_zero, const uint8_t *__restrict__ far_cur,
+                                             uint8_t *__restrict__ far_next, uint32_t T) {
     __shared__ unsigned long long sh_base;
+    __shared__ uint32_t sh_far_cnt, sh_far_inv;
     const int np = a.np;
     const int32_t g = (int32_t)(vb / np);
     const int k = (int)(vb % np);
-    if (vb == 0 && threadIdx.x < kMaxParts) ctl_zero[threadIdx.x] = 0ull;
+    if (vb == 0 && threadIdx.x < kSlotWords) ctl_zero[threadIdx.x] = 0ull;
     if (a.zmask && k == 0)
         for (int t = threadIdx.x; t < kGroupVerts; t += kBlk) a.zmask[(int64_t)g * kGroupVerts + t] = 0ull;
     {
@@ -327,12 +386,35 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t vb, co
                 make_uint4(0u, 0u, 0u, 0u);
     }
     const int64_t base = (int64_t)g * kGroupVerts + threadIdx.x * kVpt;
-    const uint4 fw = reinterpret_cast<const uint4 *>(nflags)[base >> 4];
-    uint32_t mask16 = 0;
-#pragma unroll
-    for (int b = 0; b < 16; ++b) {
-        const uint32_t word = b < 4 ? fw.x : b < 8 ? fw.y : b < 12 ? fw.z : fw.w;
-        mask16 |= (((word >> ((b & 3) * 8)) & 0xFFu) != 0u ? 1u : 0u) << b;
+    uint32_t mask16 = nonzero_bytes(reinterpret_cast<const uint4 *>(nflags)[base >> 4]);
+    if (far_cur) {
+        // near-far split: candidates are the flagged and the held-back
+        // vertices; those below T join the frontier, the others are held back
+        // again.  The threads whose 16 vertices lie in this block's share of
+        // the group write the share's next held-back flags and count them.
+        if (threadIdx.x == 0) {
+            sh_far_cnt = 0u;
+            sh_far_inv = 0u;
+        }
+        mask16 |= nonzero_bytes(reinterpret_cast<const uint4 *>(far_cur)[base >> 4]);
+        uint32_t cnt = 0u, inv = 0u;
+        const uint32_t held = held_back(a.dist, base, mask16, T, &cnt, &inv);
+        mask16 &= ~held;
+        const int share16 = kGroupVerts / 16 / np;
+        const bool mine = (int)threadIdx.x >= k * share16 && (int)threadIdx.x < (k + 1) * share16;
+        __syncthreads();
+        if (mine) {
+            reinterpret_cast<uint4 *>(far_next)[base >> 4] = bytes_of_bits(held);
+            if (cnt) {
+                atomicAdd(&sh_far_cnt, cnt);
+                atomicMax(&sh_far_inv, inv);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && sh_far_cnt) {
+            atomicAdd(ctl_next + kFarCountWord, (unsigned long long)sh_far_cnt);
+            atomicMax(ctl_next + kFarMaxInvWord, (unsigned long long)sh_far_inv);
+        }
     }
     if (!__syncthreads_or(mask16 != 0)) return;  // uniform per block
 
@@ -362,7 +444,7 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t vb, co
             const int32_t st = a.pro[u * np + k];
             const int32_t d = a.pro[(u + 1) * np + k] - st;
             if (d > 0) {
-                qse[pos] = make_uint2((uint32_t)st, (uint32_t)u);
+                qse[pos] = make_uint2((uint32_t)st, a.dist ? a.dist[u] : (uint32_t)u);
                 qs[pos] = spos;
                 ++pos;
                 spos += d;
@@ -372,7 +454,7 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t vb, co
 }
 
 __global__ __launch_bounds__(kBlk) void k_filter(FilterArgs a) {
-    filter_group(a, blockIdx.x, a.nflags, a.cflags, a.ctl_next, a.ctl_zero);
+    filter_group(a, blockIdx.x, a.nflags, a.cflags, a.ctl_next, a.ctl_zero, a.far_cur, a.far_next, a.threshold);
 }
 
 // Streaming filter for large frontiers: block b works on partition b % np and
@@ -394,6 +476,10 @@ struct DenseFilterArgs {
     int64_t clear16;  // uint4 words of flags each block clears
     int64_t nflag16;
     uint64_t *zmask;  // when set: per-vertex masks to clear (same share as the flags)
+    const uint32_t *dist;  // as in FilterArgs
+    const uint8_t *far_cur;  // as in FilterArgs
+    uint8_t *far_next;
+    uint32_t threshold;
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
     unsigned long long *ctl_next;
@@ -402,19 +488,46 @@ struct DenseFilterArgs {
 
 __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t vb, const uint8_t *__restrict__ nflags,
                                              uint8_t *__restrict__ cflags, uint64_t *zmask,
-                                             unsigned long long *ctl_next, unsigned long long *ctl_zero) {
+                                             unsigned long long *ctl_next, unsigned long long *ctl_zero,
+                                             const uint8_t *__restrict__ far_cur, uint8_t *__restrict__ far_next,
+                                             uint32_t T) {
     __shared__ unsigned long long sh_base;
+    __shared__ uint32_t sh_far_cnt, sh_far_inv;
     const int np = a.np;
     const int k = (int)(vb % np);
     const int64_t j = vb / np;
-    if (vb == 0 && threadIdx.x < kMaxParts) ctl_zero[threadIdx.x] = 0ull;
+    if (vb == 0 && threadIdx.x < kSlotWords) ctl_zero[threadIdx.x] = 0ull;
     {
+        // this block's share of the flags: clear the current ones and, with
+        // the near-far split, write the next held-back flags of the share
         const int64_t c0 = vb * a.clear16;
         const int64_t c1 = min(c0 + a.clear16, a.nflag16);
+        uint32_t cnt = 0u, inv = 0u;
+        if (far_cur && threadIdx.x == 0) {
+            sh_far_cnt = 0u;
+            sh_far_inv = 0u;
+        }
         for (int64_t w = c0 + threadIdx.x; w < c1; w += kBlk) {
             reinterpret_cast<uint4 *>(cflags)[w] = make_uint4(0u, 0u, 0u, 0u);
             if (zmask)
                 for (int q = 0; q < 16; ++q) zmask[w * 16 + q] = 0ull;
+            if (far_cur) {
+                const uint32_t cand = nonzero_bytes(reinterpret_cast<const uint4 *>(nflags)[w]) |
+                                      nonzero_bytes(reinterpret_cast<const uint4 *>(far_cur)[w]);
+                reinterpret_cast<uint4 *>(far_next)[w] = bytes_of_bits(held_back(a.dist, w * 16, cand, T, &cnt, &inv));
+            }
+        }
+        if (far_cur) {
+            __syncthreads();
+            if (cnt) {
+                atomicAdd(&sh_far_cnt, cnt);
+                atomicMax(&sh_far_inv, inv);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0 && sh_far_cnt) {
+                atomicAdd(ctl_next + kFarCountWord, (unsigned long long)sh_far_cnt);
+                atomicMax(ctl_next + kFarMaxInvWord, (unsigned long long)sh_far_inv);
+            }
         }
     }
     const int64_t lo = a.off[k] + j * kDenseChunk;
@@ -432,9 +545,12 @@ __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t v
         sd[it] = a.mem_sd[m];
     }
     int32_t x[2] = {0, 0}, tot[2];
+    uint32_t du[kDenseItems];
 #pragma unroll
     for (int it = 0; it < kDenseItems; ++it) {
-        on[it] = (m0 + it < hi) && nflags[u[it]] != 0;
+        on[it] = (m0 + it < hi) && (nflags[u[it]] != 0 || (far_cur && far_cur[u[it]] != 0));
+        du[it] = (on[it] && a.dist) ? a.dist[u[it]] : 0u;
+        if (far_cur) on[it] = on[it] && du[it] < T;
         if (on[it]) {
             x[0] += 1;
             x[1] += (int32_t)sd[it].y;
@@ -450,7 +566,7 @@ __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t v
 #pragma unroll
     for (int it = 0; it < kDenseItems; ++it) {
         if (on[it]) {
-            a.qse[k][pos] = make_uint2(sd[it].x, (uint32_t)u[it]);
+            a.qse[k][pos] = make_uint2(sd[it].x, a.dist ? du[it] : (uint32_t)u[it]);
             a.qs[k][pos] = spos;
             ++pos;
             spos += (int32_t)sd[it].y;
@@ -459,7 +575,8 @@ __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t v
 }
 
 __global__ __launch_bounds__(kBlk) void k_filter_dense(DenseFilterArgs a) {
-    filter_dense(a, blockIdx.x, a.nflags, a.cflags, a.zmask, a.ctl_next, a.ctl_zero);
+    filter_dense(a, blockIdx.x, a.nflags, a.cflags, a.zmask, a.ctl_next, a.ctl_zero, a.far_cur, a.far_next,
+                 a.threshold);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,11 +630,54 @@ struct PersistArgs {
     const int32_t *ro_in;
     const uint2 *adj_in;
     uint8_t *flags[2];
+    uint8_t *far[2];      // NULL when the near-far split is off
     unsigned long long *ctl;
     int32_t n, m, ngroups;
     int32_t max_iters, alpha_x16, direction, filter, dense_ratio;
+    uint32_t delta;
     uint64_t spin_ticks;
 };
+
+// Totals of the frontier in a counter slot, and partition kb's share.
+struct SlotTotals {
+    int64_t Fs, Es, far_cnt;
+    int32_t Fk, Ek;
+    uint32_t far_min;
+};
+
+template <int NP>
+__device__ __forceinline__ SlotTotals slot_totals(const unsigned long long *cur, int kb) {
+    SlotTotals t{0, 0, 0, 0, 0, 0u};
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const unsigned long long c = __hip_atomic_load(cur + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t f = (int32_t)(c & 0xFFFFFFFFull), e = (int32_t)(c >> 32);
+        t.Fs += f;
+        t.Es += e;
+        if (k == kb) {
+            t.Fk = f;
+            t.Ek = e;
+        }
+    }
+    t.far_cnt = (int64_t)__hip_atomic_load(cur + kFarCountWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t.far_min = ~(uint32_t)__hip_atomic_load(cur + kFarMaxInvWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return t;
+}
+
+template <int WT>
+__device__ __forceinline__ uint32_t next_threshold_dev(uint32_t far_min, uint32_t delta) {
+    const uint32_t t = plus<WT>(far_min, delta);
+    return t > far_min ? t : far_min + 1u;
+}
+
+__device__ __forceinline__ bool pick_pull(const PersistArgs &a, int64_t iter, int64_t Es) {
+    switch (a.direction) {
+        case 1: return false;
+        case 2: return true;
+        case 3: return (iter & 1) != 0;
+        default: return a.alpha_x16 > 0 && Es * a.alpha_x16 >= (int64_t)16 * a.m;
+    }
+}
 
 template <int WT, int NP>
 __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
@@ -526,63 +686,55 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
     const int kb = (int)(b % NP);
     const int64_t jb = b / NP, B = G / NP;
     for (int64_t iter = 0;; ++iter) {
-        const unsigned long long *cur = a.ctl + ((iter % kCtlSlots) * kMaxParts);
-        int64_t Fs = 0, Es = 0;
-        int32_t Fk = 0, Ek = 0;
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const unsigned long long c = __hip_atomic_load(cur + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int32_t f = (int32_t)(c & 0xFFFFFFFFull), e = (int32_t)(c >> 32);
-            Fs += f;
-            Es += e;
-            if (k == kb) {
-                Fk = f;
-                Ek = e;
-            }
-        }
-        if (Fs == 0 || iter >= a.max_iters) {
+        const SlotTotals t = slot_totals<NP>(a.ctl + (iter % kCtlSlots) * kSlotWords, kb);
+        if ((t.Fs == 0 && t.far_cnt == 0) || iter >= a.max_iters) {
             if (b == 0 && threadIdx.x == 0) {
-                ls->status = Fs == 0 ? 1ull : 2ull;
+                ls->status = t.Fs == 0 && t.far_cnt == 0 ? 1ull : 2ull;
                 ls->iter = (unsigned long long)iter;
             }
             break;
         }
-        bool pull;
-        switch (a.direction) {
-            case 1: pull = false; break;
-            case 2: pull = true; break;
-            case 3: pull = (iter & 1) != 0; break;
-            default: pull = a.alpha_x16 > 0 && Es * a.alpha_x16 >= (int64_t)16 * a.m;
-        }
+        // An empty frontier with held-back vertices: this round only raises
+        // the near-far threshold and filters.
+        const bool idle = t.Fs == 0;
+        const bool pull = !idle && pick_pull(a, iter, t.Es);
         uint8_t *cf = a.flags[iter & 1];
         uint8_t *nf = a.flags[(iter + 1) & 1];
-        if (pull) {
+        if (idle) {
+            if (b == 0 && threadIdx.x == 0)
+                __hip_atomic_store(&ls->threshold, (unsigned long long)next_threshold_dev<WT>(t.far_min, a.delta),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (pull) {
             const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
             for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
         } else {
-            const int32_t per = (int32_t)max<int64_t>(1, ((int64_t)Ek + B - 1) / B);
-            push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], Fk, Ek, per, jb, nf);
+            const int32_t per = (int32_t)max<int64_t>(1, ((int64_t)t.Ek + B - 1) / B);
+            push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf);
         }
         if (!grid_sync(ls, (unsigned)G, a.spin_ticks)) break;
-        unsigned long long *cn = a.ctl + (((iter + 1) % kCtlSlots) * kMaxParts);
-        unsigned long long *cz = a.ctl + (((iter + 2) % kCtlSlots) * kMaxParts);
-        const bool dense = a.filter == 2 || (a.filter == 0 && Fs * a.dense_ratio >= a.n);
+        unsigned long long *cn = a.ctl + ((iter + 1) % kCtlSlots) * kSlotWords;
+        unsigned long long *cz = a.ctl + ((iter + 2) % kCtlSlots) * kSlotWords;
+        const uint32_t T =
+            (uint32_t)__hip_atomic_load(&ls->threshold, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint8_t *fc = a.far[0] ? a.far[iter & 1] : nullptr;
+        uint8_t *fn = a.far[0] ? a.far[(iter + 1) & 1] : nullptr;
+        const bool dense = a.filter == 2 || (a.filter == 0 && t.Fs * a.dense_ratio >= a.n);
         if (dense) {
             const int64_t nvb = (int64_t)a.fd.chunks * NP;
-            for (int64_t vb = b; vb < nvb; vb += G) filter_dense(a.fd, vb, nf, cf, nullptr, cn, cz);
+            for (int64_t vb = b; vb < nvb; vb += G) filter_dense(a.fd, vb, nf, cf, nullptr, cn, cz, fc, fn, T);
         } else {
             const int64_t nvb = (int64_t)a.ngroups * NP;
-            for (int64_t vb = b; vb < nvb; vb += G) filter_group(a.fg, vb, nf, cf, cn, cz);
+            for (int64_t vb = b; vb < nvb; vb += G) filter_group(a.fg, vb, nf, cf, cn, cz, fc, fn, T);
         }
-        if (b == 0 && threadIdx.x == 0) {
-            ls->frontier_sum += (unsigned long long)Fs;
-            if ((unsigned long long)Fs > ls->frontier_max) ls->frontier_max = (unsigned long long)Fs;
+        if (b == 0 && threadIdx.x == 0 && !idle) {
+            ls->frontier_sum += (unsigned long long)t.Fs;
+            if ((unsigned long long)t.Fs > ls->frontier_max) ls->frontier_max = (unsigned long long)t.Fs;
             if (pull) {
                 ls->arcs_pulled += (unsigned long long)a.m;
                 ls->pull_iters += 1ull;
             } else {
-                ls->edges_pushed += (unsigned long long)Es;
-                ls->push_frontier_sum += (unsigned long long)Fs;
+                ls->edges_pushed += (unsigned long long)t.Es;
+                ls->push_frontier_sum += (unsigned long long)t.Fs;
             }
         }
         if (!grid_sync(ls, (unsigned)G, a.spin_ticks)) break;
@@ -609,43 +761,29 @@ __global__ __launch_bounds__(kBlk) void k_step_advance(PersistArgs a, int64_t it
     const int64_t G = gridDim.x, b = blockIdx.x;
     const int kb = (int)(b % NP);
     const int64_t jb = b / NP, B = G / NP;
-    const unsigned long long *cur = a.ctl + ((iter % kCtlSlots) * kMaxParts);
-    int64_t Fs = 0, Es = 0;
-    int32_t Fk = 0, Ek = 0;
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        const unsigned long long c = cur[k];
-        const int32_t f = (int32_t)(c & 0xFFFFFFFFull), e = (int32_t)(c >> 32);
-        Fs += f;
-        Es += e;
-        if (k == kb) {
-            Fk = f;
-            Ek = e;
-        }
-    }
-    if (Fs == 0 || iter >= a.max_iters) {
+    const SlotTotals t = slot_totals<NP>(a.ctl + (iter % kCtlSlots) * kSlotWords, kb);
+    if ((t.Fs == 0 && t.far_cnt == 0) || iter >= a.max_iters) {
         if (b == 0 && threadIdx.x == 0) {
             ls->iter = (unsigned long long)iter;
-            __hip_atomic_store(&ls->status, Fs == 0 ? 1ull : 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ls->status, t.Fs == 0 && t.far_cnt == 0 ? 1ull : 2ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }
-    bool pull;
-    switch (a.direction) {
-        case 1: pull = false; break;
-        case 2: pull = true; break;
-        case 3: pull = (iter & 1) != 0; break;
-        default: pull = a.alpha_x16 > 0 && Es * a.alpha_x16 >= (int64_t)16 * a.m;
+    if (t.Fs == 0) {  // held-back vertices only: raise the threshold, the filter releases them
+        if (b == 0 && threadIdx.x == 0) ls->threshold = next_threshold_dev<WT>(t.far_min, a.delta);
+        return;
     }
+    const bool pull = pick_pull(a, iter, t.Es);
     if (b == 0 && threadIdx.x == 0) {
-        ls->frontier_sum += (unsigned long long)Fs;
-        if ((unsigned long long)Fs > ls->frontier_max) ls->frontier_max = (unsigned long long)Fs;
+        ls->frontier_sum += (unsigned long long)t.Fs;
+        if ((unsigned long long)t.Fs > ls->frontier_max) ls->frontier_max = (unsigned long long)t.Fs;
         if (pull) {
             ls->arcs_pulled += (unsigned long long)a.m;
             ls->pull_iters += 1ull;
         } else {
-            ls->edges_pushed += (unsigned long long)Es;
-            ls->push_frontier_sum += (unsigned long long)Fs;
+            ls->edges_pushed += (unsigned long long)t.Es;
+            ls->push_frontier_sum += (unsigned long long)t.Fs;
         }
     }
     uint8_t *cf = a.flags[iter & 1];
@@ -654,8 +792,8 @@ __global__ __launch_bounds__(kBlk) void k_step_advance(PersistArgs a, int64_t it
         const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
         for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
     } else {
-        const int32_t per = (int32_t)max<int64_t>(1, ((int64_t)Ek + B - 1) / B);
-        push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], Fk, Ek, per, jb, nf);
+        const int32_t per = (int32_t)max<int64_t>(1, ((int64_t)t.Ek + B - 1) / B);
+        push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf);
     }
 }
 
@@ -664,21 +802,21 @@ __global__ __launch_bounds__(kBlk) void k_step_filter(PersistArgs a, int64_t ite
     const LoopState *ls = reinterpret_cast<const LoopState *>(a.ctl + kLoopStateWord);
     if (loop_status(ls) != 0ull) return;
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const unsigned long long *cur = a.ctl + ((iter % kCtlSlots) * kMaxParts);
-    int64_t Fs = 0;
-#pragma unroll
-    for (int k = 0; k < NP; ++k) Fs += (int64_t)(cur[k] & 0xFFFFFFFFull);
+    const SlotTotals t = slot_totals<NP>(a.ctl + (iter % kCtlSlots) * kSlotWords, 0);
     uint8_t *cf = a.flags[iter & 1];
     uint8_t *nf = a.flags[(iter + 1) & 1];
-    unsigned long long *cn = a.ctl + (((iter + 1) % kCtlSlots) * kMaxParts);
-    unsigned long long *cz = a.ctl + (((iter + 2) % kCtlSlots) * kMaxParts);
-    const bool dense = a.filter == 2 || (a.filter == 0 && Fs * a.dense_ratio >= a.n);
+    unsigned long long *cn = a.ctl + ((iter + 1) % kCtlSlots) * kSlotWords;
+    unsigned long long *cz = a.ctl + ((iter + 2) % kCtlSlots) * kSlotWords;
+    const uint32_t T = (uint32_t)ls->threshold;
+    const uint8_t *fc = a.far[0] ? a.far[iter & 1] : nullptr;
+    uint8_t *fn = a.far[0] ? a.far[(iter + 1) & 1] : nullptr;
+    const bool dense = a.filter == 2 || (a.filter == 0 && t.Fs * a.dense_ratio >= a.n);
     if (dense) {
         const int64_t nvb = (int64_t)a.fd.chunks * NP;
-        for (int64_t vb = b; vb < nvb; vb += G) filter_dense(a.fd, vb, nf, cf, nullptr, cn, cz);
+        for (int64_t vb = b; vb < nvb; vb += G) filter_dense(a.fd, vb, nf, cf, nullptr, cn, cz, fc, fn, T);
     } else {
         const int64_t nvb = (int64_t)a.ngroups * NP;
-        for (int64_t vb = b; vb < nvb; vb += G) filter_group(a.fg, vb, nf, cf, cn, cz);
+        for (int64_t vb = b; vb < nvb; vb += G) filter_group(a.fg, vb, nf, cf, cn, cz, fc, fn, T);
     }
 }
 
@@ -931,7 +1069,32 @@ static hipError_t scan_exclusive(const int32_t *in, int64_t len, int32_t *out, i
 
 static inline int slot_of(int64_t i) { return (int)(((i % kCtlSlots) + kCtlSlots) % kCtlSlots); }
 
-unsigned long long *counters_after(const Frontier &f, int64_t iter) { return f.ctl + slot_of(iter + 1) * kMaxParts; }
+unsigned long long *counters_after(const Frontier &f, int64_t iter) { return f.ctl + slot_of(iter + 1) * kSlotWords; }
+
+void read_counts(const unsigned long long *h, FrontierCounts *c) {
+    for (int k = 0; k < kMaxParts; ++k) {
+        c->F[k] = (int32_t)(h[k] & 0xFFFFFFFFull);
+        c->E[k] = (int32_t)(h[k] >> 32);
+    }
+    c->far_count = (int64_t)h[kFarCountWord];
+    c->far_min = ~(uint32_t)h[kFarMaxInvWord];
+}
+
+uint32_t next_threshold(uint32_t far_min, uint32_t delta, int wt) {
+    uint32_t t;
+    if (wt == 1) {
+        float a, d;
+        std::memcpy(&a, &far_min, 4);
+        std::memcpy(&d, &delta, 4);
+        float r = a + d;
+        if (!(r <= 3.40282347e38f)) r = 3.40282347e38f;
+        std::memcpy(&t, &r, 4);
+    } else {
+        const uint64_t r = (uint64_t)far_min + delta;
+        t = r >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)r;
+    }
+    return t > far_min ? t : far_min + 1u;
+}
 
 int64_t FrontierCounts::Fsum() const {
     int64_t s = 0;
@@ -945,7 +1108,8 @@ int64_t FrontierCounts::Esum() const {
     return s;
 }
 
-hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Frontier &f, hipStream_t st) {
+hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Frontier &f, uint32_t threshold,
+                       bool use_far, hipStream_t st) {
     InitArgs a;
     a.dist = dist;
     a.n = g.n;
@@ -955,6 +1119,9 @@ hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Fro
     a.pro = g.pro;
     a.flags0 = f.flags[0];
     a.flags1 = f.flags[1];
+    a.far0 = use_far ? f.far[0] : nullptr;
+    a.far1 = use_far ? f.far[1] : nullptr;
+    a.threshold = threshold;
     a.nflag = f.nflag;
     for (int k = 0; k < kMaxParts; ++k) {
         a.qse[k] = f.qse[k];
@@ -1011,7 +1178,8 @@ hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int
 }
 
 hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uint64_t *zmask, bool dense,
-                         hipStream_t st) {
+                         const uint32_t *dist, bool use_far, uint32_t threshold, hipStream_t st) {
+    if (use_far && (!dist || !f.far[0])) return hipErrorInvalidValue;
     const int p = (int)(iter & 1);
     if (dense) {
         DenseFilterArgs a;
@@ -1028,12 +1196,16 @@ hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uin
         a.nflag16 = f.nflag / 16;
         a.clear16 = (a.nflag16 + blocks - 1) / blocks;
         a.zmask = zmask;
+        a.dist = dist;
         for (int k = 0; k < kMaxParts; ++k) {
             a.qse[k] = f.qse[k];
             a.qs[k] = f.qs[k];
         }
-        a.ctl_next = f.ctl + slot_of(iter + 1) * kMaxParts;
-        a.ctl_zero = f.ctl + slot_of(iter + 2) * kMaxParts;
+        a.ctl_next = f.ctl + slot_of(iter + 1) * kSlotWords;
+        a.ctl_zero = f.ctl + slot_of(iter + 2) * kSlotWords;
+        a.far_cur = use_far ? f.far[p] : nullptr;
+        a.far_next = use_far ? f.far[p ^ 1] : nullptr;
+        a.threshold = threshold;
         hipLaunchKernelGGL(k_filter_dense, dim3((unsigned)blocks), dim3(kBlk), 0, st, a);
         return hipGetLastError();
     }
@@ -1041,14 +1213,18 @@ hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uin
     a.np = g.np;
     a.pro = g.pro;
     a.zmask = zmask;
+    a.dist = dist;
     a.nflags = f.flags[p ^ 1];
     a.cflags = f.flags[p];
     for (int k = 0; k < kMaxParts; ++k) {
         a.qse[k] = f.qse[k];
         a.qs[k] = f.qs[k];
     }
-    a.ctl_next = f.ctl + slot_of(iter + 1) * kMaxParts;
-    a.ctl_zero = f.ctl + slot_of(iter + 2) * kMaxParts;
+    a.ctl_next = f.ctl + slot_of(iter + 1) * kSlotWords;
+    a.ctl_zero = f.ctl + slot_of(iter + 2) * kSlotWords;
+    a.far_cur = use_far ? f.far[p] : nullptr;
+    a.far_next = use_far ? f.far[p ^ 1] : nullptr;
+    a.threshold = threshold;
     hipLaunchKernelGGL(k_filter, dim3(f.ngroups * g.np), dim3(kBlk), 0, st, a);
     return hipGetLastError();
 }
@@ -1189,6 +1365,10 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     fg.np = g.np;
     fg.pro = g.pro;
     fg.zmask = nullptr;
+    fg.dist = dist;
+    fg.far_cur = nullptr;
+    fg.far_next = nullptr;
+    fg.threshold = 0u;
     fg.nflags = nullptr;
     fg.cflags = nullptr;
     fg.ctl_next = nullptr;
@@ -1206,6 +1386,10 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     fd.nflag16 = f.nflag / 16;
     fd.clear16 = (fd.nflag16 + (int64_t)fd.chunks * g.np - 1) / ((int64_t)fd.chunks * g.np);
     fd.zmask = nullptr;
+    fd.dist = dist;
+    fd.far_cur = nullptr;
+    fd.far_next = nullptr;
+    fd.threshold = 0u;
     fd.ctl_next = nullptr;
     fd.ctl_zero = nullptr;
     for (int k = 0; k < kMaxParts; ++k) {
@@ -1218,6 +1402,9 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     a.adj_in = g.adj_in;
     a.flags[0] = f.flags[0];
     a.flags[1] = f.flags[1];
+    a.far[0] = cfg.delta ? f.far[0] : nullptr;
+    a.far[1] = cfg.delta ? f.far[1] : nullptr;
+    a.delta = cfg.delta;
     a.ctl = f.ctl;
     a.n = g.n;
     a.m = g.m;
@@ -1265,7 +1452,7 @@ static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t frontier_bytes(const DevGraph &g) {
     const int64_t ng = groups_for(g.n);
     size_t b = 0;
-    b += 2 * align256((size_t)ng * kGroupVerts);
+    b += 4 * align256((size_t)ng * kGroupVerts);  // flags, held-back flags
     for (int k = 0; k < g.np; ++k) {
         const size_t c = (size_t)(g.cap[k] > 0 ? g.cap[k] : 1);
         b += align256(c * 8) + align256(c * 4);
@@ -1282,6 +1469,10 @@ void frontier_carve(Frontier &f, void *base, const DevGraph &g) {
     char *p = static_cast<char *>(base);
     for (int i = 0; i < 2; ++i) {
         f.flags[i] = reinterpret_cast<uint8_t *>(p);
+        p += align256((size_t)f.nflag);
+    }
+    for (int i = 0; i < 2; ++i) {
+        f.far[i] = reinterpret_cast<uint8_t *>(p);
         p += align256((size_t)f.nflag);
     }
     for (int k = 0; k < kMaxParts; ++k) {

@@ -23,9 +23,10 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run(G, src, direction=0, loop=0, n=None, layout=0, filt=0):
+def run(G, src, direction=0, loop=0, n=None, layout=0, filt=0, delta=0):
     dist = torch.full((n or G.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
-    st = gr.gr_sssp_ex(G.handle, int(src), dist, direction=direction, loop=loop, layout=layout, filter=filt)
+    st = gr.gr_sssp_ex(G.handle, int(src), dist, direction=direction, loop=loop, layout=layout, filter=filt,
+                       delta=delta)
     torch.cuda.synchronize()
     return dist.cpu().numpy().view(np.uint32), st
 
@@ -286,3 +287,84 @@ def test_grid2048_config_device_loops():
 def test_rmat22_config_sampled_sources():
     g, srcs = gg.workload("rmat22")
     check_all_dirs(g, srcs[:2], "rmat22", dirs=("auto", "push"), flags=0)
+
+
+# ------------------------------------------------------------ near-far split
+
+@pytest.mark.parametrize("wtype", [gg.W_U32, gg.W_F32])
+def test_near_far_split_all_loops_filters(wtype):
+    # held-back vertices, threshold raises and both filters, under every loop
+    # driver; widths from below one weight to above the diameter
+    graphs = [("rmat13", gg.rmat(13, 16, gseed=41, pseed=42, wseed=43, wtype=wtype), gr.GR_FORCE_PARTITION),
+              ("grid48", gg.grid(48, wseed=44, wtype=wtype), 0)]
+    for tag, g, flags in graphs:
+        G = gr.Graph.from_csr(g, flags=flags)
+        info = G.info()
+        layouts = [gr.GR_LAYOUT_PLAIN] + ([gr.GR_LAYOUT_PARTITIONED] if info["partitions"] > 1 else [])
+        mean_w = float(np.mean(g.w.view(np.float32))) if wtype == gg.W_F32 else float(np.mean(g.w))
+        try:
+            for s in gg.pick_sources(g, 45, 2):
+                want = oracle.dijkstra(g, int(s))
+                for f in (0.5, 4.0, 1e6):
+                    d = gr.delta_bits(mean_w * f if wtype == gg.W_F32 else max(1, int(mean_w * f)), wtype)
+                    for lay in layouts:
+                        for lp in ("host", "persistent", "queued"):
+                            for filt in (0, 1, 2):
+                                say("near-far %s w%d src=%d delta=%#x layout=%d loop=%s filter=%d" % (
+                                    tag, wtype, s, d, lay, lp, filt))
+                                got, st = run(G, s, DIRS["push"], layout=lay, loop=LOOPS[lp], filt=filt, delta=d)
+                                assert_same(got, want, "near-far %s delta %#x layout %d loop %s filter %d" % (
+                                    tag, d, lay, lp, filt))
+        finally:
+            G.close()
+
+
+def test_near_far_cuts_relaxations_and_rejects_bad_widths():
+    g = gg.grid(64, wseed=2)  # uint32 U[1,100]
+    G = gr.Graph.from_csr(g)
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    try:
+        base = run(G, 0, DIRS["push"], loop=LOOPS["host"])[1]
+        split = run(G, 0, DIRS["push"], loop=LOOPS["host"], delta=50)[1]
+        assert split["edges_pushed"] < base["edges_pushed"]
+        assert split["iterations"] > base["iterations"]
+        off = run(G, 0, DIRS["push"], loop=LOOPS["host"], delta=gr.GR_DELTA_OFF)[1]
+        assert off["edges_pushed"] == base["edges_pushed"]
+        for d in (gr.GR_DIR_PULL, gr.GR_DIR_ALTERNATE):
+            with pytest.raises(gr.GrError) as ei:
+                gr.gr_sssp_ex(G.handle, 0, dist, direction=d, delta=50)
+            assert ei.value.status == gr.GR_ERR_INVALID_ARG
+    finally:
+        G.close()
+    gf = gg.grid(16, wseed=3, wtype=gg.W_F32)
+    Gf = gr.Graph.from_csr(gf)
+    try:
+        for bits in (0x7FC00000, 0x7F800000, 0x80000001):  # NaN, +inf, -denormal
+            with pytest.raises(gr.GrError) as ei:
+                gr.gr_sssp_ex(Gf.handle, 0, dist[:gf.n], delta=bits)
+            assert ei.value.status == gr.GR_ERR_INVALID_ARG
+    finally:
+        Gf.close()
+
+
+def test_near_far_configs():
+    g, srcs = gg.workload("road2048")
+    G = gr.Graph.from_csr(g)
+    try:
+        want = oracle.dijkstra(g, int(srcs[0]))
+        for lp in ("host", "queued"):
+            say("near-far road2048 loop=%s" % lp)
+            got, st = run(G, srcs[0], DIRS["push"], loop=LOOPS[lp], delta=2000)
+            assert_same(got, want, "road2048 near-far loop %s" % lp)
+    finally:
+        G.close()
+    g, srcs = gg.workload("rmat20")  # fp32 weights in (0, 1]
+    G = gr.Graph.from_csr(g)
+    try:
+        want = oracle.dijkstra(g, int(srcs[0]))
+        for lp in ("host", "queued"):
+            say("near-far rmat20 loop=%s" % lp)
+            got, _ = run(G, srcs[0], DIRS["push"], loop=LOOPS[lp], delta=gr.delta_bits(0.25, gg.W_F32))
+            assert_same(got, want, "rmat20 near-far loop %s" % lp)
+    finally:
+        G.close()
