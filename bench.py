@@ -124,7 +124,7 @@ def main():
     for i in range(max(args.warmup, 1)):
         s, st = run(i)
     torch.cuda.synchronize()
-    for s in sorted(set(srcs[i % len(srcs)] for i in range(args.steps))):
+    for s in sorted(set(srcs[(args.warmup + i) % len(srcs)] for i in range(args.steps))):
         if s not in reached:
             gr.gr_sssp_ex(G.handle, s, dist, stream=stream, **opts)
             d = dist.cpu().numpy().view(np.uint32)
@@ -134,32 +134,49 @@ def main():
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     edges = 0
-    push_us = 0.0
-    alg_bytes = 0
-    launches = 0
     iters = 0
+    q_bytes = 0
     stats_last = None
     for i in range(args.steps):
-        s, st = run(args.warmup + i, timing=1)
+        s, st = run(args.warmup + i)
         edges += reached[s]
-        push_us += st["push_us"]
-        alg_bytes += 12 * st["edges_pushed"] + 20 * st["push_frontier_sum"]
-        launches += st["push_launches"]
         iters += st["iterations"]
+        q_bytes += 12 * st["edges_pushed"] + 20 * st["push_frontier_sum"]
         stats_last = st
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_per_step = 1e3 * t_total / args.steps
     gteps = edges / t_total / 1e9
-    log("timed: %.3f ms/step, %.2f GTEPS, %d iterations/step" % (ms_per_step, gteps, iters // args.steps))
+    log("timed: %.3f ms/step, %.2f GTEPS, %d iterations/step, %.0f M relaxations/step" % (
+        ms_per_step, gteps, iters // args.steps, q_bytes / 12e6 / args.steps))
 
+    # Kernel roofline: the same steps again, now with HIP events around every
+    # advance launch on the query's stream (outside the timed region: the
+    # events add gaps between launches).
+    push_us = 0.0
+    alg_bytes = 0
+    launches = 0
+    for i in range(args.steps):
+        s, st = run(args.warmup + i, timing=1)
+        push_us += st["push_us"]
+        alg_bytes += 12 * st["edges_pushed"] + 20 * st["push_frontier_sum"]
+        launches += st["push_launches"]
+    torch.cuda.synchronize()
     roof = None
     if launches and push_us > 0:
         achieved = alg_bytes / (push_us * 1e-6) / 1e9
-        roof = {"kernel": "k_push", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        kern = {2: "k_persistent", 3: "k_step_advance"}.get(stats_last["loop"], "k_push")
+        loop_name = {1: "host", 2: "persistent", 3: "queued"}.get(stats_last["loop"], "?")
+        traffic = counter_traffic(kern, args.workload, loop_name)
+        roof = {"kernel": kern, "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": int(alg_bytes / launches), "avg_launch_us": round(push_us / launches, 2),
-                "launches": launches}
+                "launches": launches,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                # whole query: algorithmic bytes of all rounds over the timed wall clock
+                "query_gbs": round(q_bytes / t_total / 1e9, 1),
+                "query_frac": round(q_bytes / t_total / 1e9 / HBM_PEAK_GBS, 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -216,6 +233,31 @@ def main():
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def counter_traffic(kernel, workload, loop):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when that summary is for another kernel / workload or the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    src = "".join(open(os.path.join(ROOT, "paper_2212_08200_amd", "csrc", f)).read()
+                  for f in ("gr_kernels.hip", "gr_device.h", "gr_internal.h"))
+    if fields.get("kernel_sources_sha256") != hashlib.sha256(src.encode()).hexdigest():
+        return None
+    if fields.get("loop") not in (None, loop):
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev):
