@@ -12,11 +12,17 @@ inputs resident in HBM.
 Prints ONE JSON line on stdout:
   value       GTEPS = sum over steps of m_reached(src) / wall time, where
               m_reached = out-degree sum of the vertices the query reaches
-  roofline    algorithmic bytes of the push (advance) kernel per launch --
-              12 B per relaxed edge (arc 8 B + dist 4 B) + 20 B per frontier
-              vertex (queue 4, offsets 8, dist 4, next-queue 4) -- divided by
-              its launch time measured with HIP events on the query's stream,
-              against the 8 TB/s HBM3E peak
+  roofline    algorithmic bytes of the dominant kernel per launch -- 12 B
+              per relaxed edge (arc 8 B + dist 4 B) + 20 B per frontier vertex
+              (queue 4, offsets 8, dist 4, next-queue 4) -- divided by its
+              launch time measured with HIP events on the query's stream (in
+              a second pass over the same steps, outside the timed region),
+              against the 8 TB/s HBM3E peak.  The kernel is k_step (every
+              phase of a round) for the queued loop, k_push (the advance)
+              for the host-driven loop.  traffic: HBM bytes per launch from
+              the committed rocprofv3 counter summary when it matches the
+              current kernel sources, else null; query_gbs / query_frac: the
+              query's algorithmic bytes over the timed wall clock.
   cpu_baseline  the CPU oracle (binary-heap Dijkstra, one core) on a bounded
               sample of the same workload's sources
 Progress goes to stderr.
@@ -58,6 +64,9 @@ def main():
     ap.add_argument("--layout", type=int, default=0, help="gr_layout (0 auto, 1 plain, 2 partitioned)")
     ap.add_argument("--direction", type=int, default=0, help="gr_direction (0 auto, 1 push, 2 pull)")
     ap.add_argument("--loop", type=int, default=0, help="gr_loop_mode (0 auto, 1 host, 2 persistent, 3 queued)")
+    ap.add_argument("--alpha", type=int, default=0,
+                    help="direction switch: pull when frontier out-edges * alpha / 16 >= m (0: graph default)")
+    ap.add_argument("--filter", type=int, default=0, help="filter (0 auto, 1 group, 2 streaming member lists)")
     ap.add_argument("--delta", type=float, default=0.0,
                     help="near-far split width in weight units (0: the graph's default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
@@ -110,7 +119,7 @@ def main():
     srcs = [int(s) for s in srcs]
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    opts = dict(loop=args.loop, direction=args.direction, layout=args.layout,
+    opts = dict(loop=args.loop, direction=args.direction, layout=args.layout, filter=args.filter, alpha_x16=args.alpha,
                 delta=gr.delta_bits(args.delta, g.wtype) if args.delta > 0 else 0)
 
     # m_reached per source (from the GPU result of its first run)
@@ -153,19 +162,26 @@ def main():
     # Kernel roofline: the same steps again, now with HIP events around every
     # advance launch on the query's stream (outside the timed region: the
     # events add gaps between launches).
+    # The queued loop runs every phase (advance, filter, small round) in one
+    # kernel, k_step: its launches are timed together (all of them, including
+    # the few queued past the end of a query) against the round's bytes.
     push_us = 0.0
     alg_bytes = 0
     launches = 0
     for i in range(args.steps):
         s, st = run(args.warmup + i, timing=1)
-        push_us += st["push_us"]
         alg_bytes += 12 * st["edges_pushed"] + 20 * st["push_frontier_sum"]
-        launches += st["push_launches"]
+        if st["loop"] == 3:
+            push_us += st["push_us"] + st["filter_us"]
+            launches += st["launches"]
+        else:
+            push_us += st["push_us"]
+            launches += st["push_launches"]
     torch.cuda.synchronize()
     roof = None
     if launches and push_us > 0:
         achieved = alg_bytes / (push_us * 1e-6) / 1e9
-        kern = {2: "k_persistent", 3: "k_step_advance"}.get(stats_last["loop"], "k_push")
+        kern = {2: "k_persistent", 3: "k_step"}.get(stats_last["loop"], "k_push")
         loop_name = {1: "host", 2: "persistent", 3: "queued"}.get(stats_last["loop"], "?")
         traffic = counter_traffic(kern, args.workload, loop_name)
         roof = {"kernel": kern, "bound": "hbm",

@@ -151,8 +151,11 @@ typedef struct {
     int32_t max_iters;  /* iteration cap; 0 = n + 1 (never reached for w >= 0) */
     int32_t layout;     /* gr_layout */
     int32_t timing;     /* 1: time every operator launch with HIP events (stats *_us fields) */
-    int32_t filter;     /* 0 auto, 1 visit the 4096-vertex groups holding flags (small frontiers),
-                           2 stream the per-partition member lists (large frontiers) */
+    int32_t filter;     /* 0 auto, 1 always the per-group flag scan, 2 always the
+                           per-partition member-list scan, 3 auto plus small rounds: in
+                           the queued loop, a round that improved at most 2^18 vertices
+                           hands the next round a list of them instead of a filter pass
+                           (graphs of degree <= 64, push only, no near-far split) */
     int32_t barrier_timeout_us; /* device-driven loop: bound on one grid-barrier wait;
                                    0 = 20 s.  Exceeding it ends the query with GR_ERR_HIP. */
     uint32_t delta;     /* near-far split width, in the weight type (a uint32 value, or the
@@ -180,6 +183,9 @@ typedef struct {
     double push_us;            /* with opts.timing: summed push / pull / filter launch times */
     double pull_us;
     double filter_us;
+    int32_t small_rounds;      /* queued loop: rounds expanded from a candidate list */
+    int32_t launches;          /* kernel launches of the loop (queued: including the ones
+                                  enqueued past the end, which return at once) */
 } gr_sssp_stats;
 
 /* gr_sssp with an explicit schedule; opts and stats may be NULL.  stats are
@@ -199,7 +205,7 @@ typedef struct {
     int32_t trials;       /* timed configurations */
     int32_t from_cache;   /* 1 when read from the tuning cache file */
     uint32_t delta;       /* chosen near-far split width (weight-type bits; 0 = off) */
-    int32_t reserved;
+    int32_t small;        /* 1: small rounds (filter 3) in the queued loop */
 } gr_tune_result;
 
 /*

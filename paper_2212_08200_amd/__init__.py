@@ -98,7 +98,7 @@ class gr_sssp_stats(ctypes.Structure):
                 ("frontier_sum", ctypes.c_int64), ("push_frontier_sum", ctypes.c_int64),
                 ("frontier_max", ctypes.c_int32), ("loop", ctypes.c_int32), ("push_launches", ctypes.c_int32),
                 ("layout", ctypes.c_int32), ("push_us", ctypes.c_double), ("pull_us", ctypes.c_double),
-                ("filter_us", ctypes.c_double)]
+                ("filter_us", ctypes.c_double), ("small_rounds", ctypes.c_int32), ("launches", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,7 +108,7 @@ class gr_tune_result(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("loop", ctypes.c_int32), ("dense_ratio", ctypes.c_int32),
                 ("alpha_x16", ctypes.c_int32), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
                 ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("delta", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32)]
+                ("small", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -149,10 +149,11 @@ struct gr_graph {
     int32_t max_degree = 0;
     // AUTO schedule: defaults, replaced by gr_graph_tune
     int32_t auto_layout = GR_LAYOUT_PLAIN;
-    int32_t auto_loop = GR_LOOP_HOST;
+    int32_t auto_loop = GR_LOOP_QUEUED;
     int32_t auto_dense_ratio = kDenseRatio;
     int32_t auto_alpha_x16 = 0;
     uint32_t auto_delta = 0;  // near-far split width (0: off)
+    bool auto_small = false;  // queued loop: small rounds
     // iterations of the last completed queued-loop query (first chunk size)
     mutable std::atomic<int32_t> last_iters{0};
     double locality = 1.0;  // fraction of arcs with |u - v| < locality_span(n)
@@ -446,6 +447,7 @@ struct RunCfg {
     int layout;
     int filter;
     int32_t dense_ratio;
+    bool small;      // queued loop: small rounds from candidate lists
     uint32_t delta;  // near-far split width (weight-type bits); 0 = off
     int64_t barrier_timeout_us;
     const DevGraph *dg;
@@ -475,7 +477,9 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
     rc->filter = o ? o->filter : 0;
     rc->dense_ratio = g->auto_dense_ratio;
     rc->barrier_timeout_us = (o && o->barrier_timeout_us > 0) ? o->barrier_timeout_us : 20000000;
-    if (rc->filter < 0 || rc->filter > 2) return fail(GR_ERR_INVALID_ARG, "unknown filter mode %d", rc->filter);
+    if (rc->filter < 0 || rc->filter > 3) return fail(GR_ERR_INVALID_ARG, "unknown filter mode %d", rc->filter);
+    rc->small = rc->filter == 3 || (rc->filter == 0 && g->auto_small);
+    if (rc->filter == 3) rc->filter = 0;
     uint32_t d = (o && o->delta) ? o->delta : g->auto_delta;
     if (d == GR_DELTA_OFF) d = 0;
     if (d && g->plain.wt == GR_W_F32) {
@@ -567,6 +571,7 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
             local.push_frontier_sum += c.Fsum();
             local.push_launches++;
         }
+        local.launches += 2;
         local.frontier_sum += c.Fsum();
         local.frontier_max = std::max<int64_t>(local.frontier_max, c.Fsum());
         if (timed) (void)hipEventRecord(ev[1], st);
@@ -615,6 +620,7 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     cfg.filter = rc.filter;
     cfg.dense_ratio = rc.dense_ratio;
     cfg.delta = rc.delta;
+    cfg.small = 0;
     cfg.spin_ticks = (uint64_t)rc.barrier_timeout_us * (uint64_t)di.wall_khz / 1000ull;
     unsigned long long *hp = pinned_slot();
     if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
@@ -645,6 +651,7 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     local.push_frontier_sum = (int64_t)ls.push_frontier_sum;
     local.frontier_max = (int32_t)ls.frontier_max;
     local.push_launches = 1;
+    local.launches = 1;
     if (timed) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
@@ -663,12 +670,16 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     return GR_OK;
 }
 
-// Queued loop: iterations are enqueued in chunks without waiting; the host
-// reads the loop state once per chunk, one chunk behind, so the device always
-// has the next chunk queued.  The first chunk covers the iteration count of
-// the previous query on this graph; later chunks grow from 4 to 64.  Launches
-// queued past the end return at once; the call waits for the last chunk so
-// that its state copy has landed before the pinned slot is reused.
+// Queued loop: launches of the step kernel are enqueued in chunks without
+// waiting; the host reads the loop state once per chunk, one chunk behind, so
+// the device always has the next chunk queued.  The first chunk covers the
+// launch count of the previous query on this graph; later chunks grow from 4
+// to 64.  Launches queued past the end return at once; the call waits for the
+// last chunk so that its state copy has landed before the pinned slot is
+// reused.
+static constexpr int64_t kPhaseLogCap = 1 << 16;
+static constexpr int32_t kSmallMaxDegree = 64;
+
 static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
                             gr_sssp_stats *stats) {
     DeviceInfo di;
@@ -687,32 +698,42 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     cfg.dense_ratio = rc.dense_ratio;
     cfg.delta = rc.delta;
     cfg.spin_ticks = 0;
+    // Small rounds (filter 3, or the tuned default) need push-only rounds
+    // (they consume the flags), no near-far split, and a bounded degree (a
+    // block expands its heavier vertices alone).
+    cfg.small = rc.small && rc.delta == 0 && g->max_degree <= kSmallMaxDegree &&
+                (rc.direction == GR_DIR_PUSH || (rc.direction == GR_DIR_AUTO && rc.alpha_x16 == 0));
     void *ws = nullptr;
     HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
     Frontier f;
     frontier_carve(f, ws, dg);
+    int8_t *plog = nullptr;
     hipEvent_t evc[2] = {nullptr, nullptr};
     hipError_t e = hipSuccess;
     for (auto &x : evc)
         if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
-    std::vector<hipEvent_t> tev;  // with timing: begin/end of each advance launch
+    if (e == hipSuccess && rc.timing) {
+        e = hipMallocAsync(reinterpret_cast<void **>(&plog), (size_t)kPhaseLogCap, st);
+        if (e == hipSuccess) e = hipMemsetAsync(plog, 0, (size_t)kPhaseLogCap, st);
+    }
+    std::vector<hipEvent_t> tev;  // with timing: begin/end of each launch
     if (e == hipSuccess)
         e = launch_init(dg, dist, src, f, rc.delta ? next_threshold(0u, rc.delta, dg.wt) : kInfU32, rc.delta != 0,
                         st);
     int64_t issued = 0;
     int c = 0;
-    int64_t K = std::clamp<int64_t>(g->last_iters.load(std::memory_order_relaxed) + 1, 4, 256);
+    int64_t K = std::clamp<int64_t>(g->last_iters.load(std::memory_order_relaxed) + 1, 4, 512);
     LoopState fin{};
     bool done = false;
     while (e == hipSuccess && !done) {
         for (int64_t i = 0; i < K && e == hipSuccess; ++i) {
             hipEvent_t b = nullptr, en = nullptr;
-            if (rc.timing) {
+            if (rc.timing && issued + i < kPhaseLogCap) {
                 if (hipEventCreate(&b) == hipSuccess) tev.push_back(b); else b = nullptr;
                 if (hipEventCreate(&en) == hipSuccess) tev.push_back(en); else en = nullptr;
                 if (!b || !en) b = en = nullptr;
             }
-            e = launch_step(dg, dist, f, cfg, issued + i, b, en, st);
+            e = launch_step(dg, dist, f, cfg, issued + i, plog, plog ? kPhaseLogCap : 0, b, en, st);
         }
         issued += K;
         unsigned long long *slot = hp + (c & 1) * (sizeof(LoopState) / 8);
@@ -743,13 +764,20 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     local.frontier_sum = (int64_t)fin.frontier_sum;
     local.push_frontier_sum = (int64_t)fin.push_frontier_sum;
     local.frontier_max = (int32_t)fin.frontier_max;
+    local.small_rounds = (int32_t)fin.small_rounds;
     local.push_launches = (int32_t)(fin.iter - fin.pull_iters);
-    if (e == hipSuccess && rc.timing) {
-        // advance launches of the executed iterations (the rest returned at once)
-        for (size_t i = 0; i + 1 < tev.size() && (int64_t)(i / 2) < (int64_t)fin.iter; i += 2) {
+    local.launches = (int32_t)std::min<int64_t>(issued, INT32_MAX);
+    if (e == hipSuccess && plog) {
+        // launch times by what each launch ran: advances and small rounds
+        // count as push (pull rounds are not split out here), filters as filter
+        std::vector<int8_t> h((size_t)std::min<int64_t>(issued, kPhaseLogCap));
+        e = hipMemcpyAsync(h.data(), plog, h.size(), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        for (size_t i = 0; e == hipSuccess && 2 * i + 1 < tev.size() && i < h.size(); ++i) {
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, tev[i], tev[i + 1]);
-            local.push_us += 1e3 * ms;  // push and pull together: the split is not known per launch
+            (void)hipEventElapsedTime(&ms, tev[2 * i], tev[2 * i + 1]);
+            // launches that returned at once (query over) count with the filters
+            (h[i] == 1 || h[i] == 3 ? local.push_us : local.filter_us) += 1e3 * ms;
         }
         if (fin.pull_iters > 0 && fin.pull_iters == fin.iter) {
             local.pull_us = local.push_us;
@@ -759,10 +787,14 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     for (auto &x : tev) (void)hipEventDestroy(x);
     for (auto &x : evc)
         if (x) (void)hipEventDestroy(x);
+    if (plog) (void)hipFreeAsync(plog, st);
     hipError_t e2 = hipFreeAsync(ws, st);
     if (e != hipSuccess) return hip_fail(e, "queued loop");
     if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
-    if (fin.status == 1) g->last_iters.store((int32_t)fin.iter, std::memory_order_relaxed);
+    // launches this query needed: about 2 per round, 1 per small round
+    if (fin.status == 1)
+        g->last_iters.store((int32_t)std::min<int64_t>(2 * (int64_t)fin.iter - (int64_t)fin.small_rounds + 1, INT32_MAX),
+                            std::memory_order_relaxed);
     if (stats) *stats = local;
     if (fin.status == 2) return fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)rc.max_iters);
     return GR_OK;
@@ -1065,16 +1097,18 @@ static bool cache_lookup(const std::string &sig, gr_tune_result *r) {
         char s[300];
         int lay, loop, dr, al;
         unsigned dl;
+        int sm;
         double ms;
         if (sscanf(line, "{\"sig\": \"%299[^\"]\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
-                         "\"delta\": %u, \"best_ms\": %lf}",
-                   s, &lay, &loop, &dr, &al, &dl, &ms) == 7 &&
+                         "\"delta\": %u, \"small\": %d, \"best_ms\": %lf}",
+                   s, &lay, &loop, &dr, &al, &dl, &sm, &ms) == 8 &&
             sig == s) {
             r->layout = lay;
             r->loop = loop;
             r->dense_ratio = dr;
             r->alpha_x16 = al;
             r->delta = dl;
+            r->small = sm;
             r->best_ms = ms;
             found = true;  // the last matching line wins
         }
@@ -1089,14 +1123,15 @@ static void cache_store(const std::string &sig, const gr_tune_result &r) {
     FILE *f = fopen(path, "a");
     if (!f) return;
     fprintf(f, "{\"sig\": \"%s\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
-               "\"delta\": %u, \"best_ms\": %.6f}\n",
-            sig.c_str(), r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.best_ms);
+               "\"delta\": %u, \"small\": %d, \"best_ms\": %.6f}\n",
+            sig.c_str(), r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small, r.best_ms);
     fclose(f);
 }
 
 struct TuneCfg {
     int32_t layout, loop, dense_ratio, alpha_x16;
     uint32_t delta;
+    int32_t small;
 };
 
 static void apply_auto(gr_graph *g, const TuneCfg &c) {
@@ -1105,6 +1140,7 @@ static void apply_auto(gr_graph *g, const TuneCfg &c) {
     g->auto_dense_ratio = c.dense_ratio;
     g->auto_alpha_x16 = c.alpha_x16;
     g->auto_delta = c.delta;
+    g->auto_small = c.small != 0;
 }
 
 // Near-far split widths to try: multiples of the mean weight of a sample of
@@ -1157,7 +1193,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         if (r.layout == GR_LAYOUT_PARTITIONED && !g->has_part) r.layout = GR_LAYOUT_PLAIN;
         if (r.alpha_x16 > 0 && !g->pull) r.alpha_x16 = 0;
         if (r.delta) r.alpha_x16 = 0;
-        apply_auto(g, TuneCfg{r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta});
+        apply_auto(g, TuneCfg{r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small});
         r.from_cache = 1;
         if (out) *out = r;
         return GR_OK;
@@ -1174,6 +1210,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         o.alpha_x16 = c.alpha_x16 > 0 ? c.alpha_x16 : 0;
         o.direction = c.alpha_x16 > 0 ? GR_DIR_AUTO : GR_DIR_PUSH;
         o.delta = c.delta ? c.delta : GR_DELTA_OFF;
+        o.filter = c.small ? 3 : 0;
         const int32_t saved = g->auto_dense_ratio;
         g->auto_dense_ratio = c.dense_ratio;
         std::vector<double> t;
@@ -1195,7 +1232,8 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         *ms = t[t.size() / 2];
         return GR_OK;
     };
-    TuneCfg best{g->auto_layout, g->auto_loop, g->auto_dense_ratio, g->auto_alpha_x16, g->auto_delta};
+    TuneCfg best{g->auto_layout, g->auto_loop, g->auto_dense_ratio, g->auto_alpha_x16, g->auto_delta,
+                 g->auto_small ? 1 : 0};
     double best_ms = 0;
     status = measure(best, &best_ms);
     const double default_ms = best_ms;
@@ -1217,6 +1255,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         for (uint32_t d : delta_candidates(g, st)) ds.push_back((int32_t)d);
         knobs.push_back({4, ds});
     }
+    if (g->max_degree <= kSmallMaxDegree) knobs.push_back({5, {0, 1}});
     for (const auto &kv : knobs) {
         for (int32_t v : kv.second) {
             if (status != GR_OK) break;
@@ -1225,6 +1264,9 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
                 if (c.delta == (uint32_t)v) continue;
                 c.delta = (uint32_t)v;
                 if (c.delta) c.alpha_x16 = 0;  // the split runs push only
+            } else if (kv.first == 5) {
+                if (c.small == v || c.loop != GR_LOOP_QUEUED || c.delta) continue;
+                c.small = v;
             } else if (kv.first == 3 && c.delta) {
                 continue;
             } else {
@@ -1250,6 +1292,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
     r.dense_ratio = best.dense_ratio;
     r.alpha_x16 = best.alpha_x16;
     r.delta = best.delta;
+    r.small = best.small;
     r.best_ms = best_ms;
     r.default_ms = default_ms;
     r.trials = trials;

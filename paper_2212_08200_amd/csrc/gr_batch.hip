@@ -203,10 +203,13 @@ void batch_carve(BatchWs &w, void *base, const DevGraph &g) {
     f.ngroups = (int32_t)ng;
     f.nflag = nv;
     f.np = 1;
+    f.cand_cap = 0;
+    f.ccount = nullptr;
     for (int i = 0; i < 2; ++i) {
         f.flags[i] = reinterpret_cast<uint8_t *>(p);
         p += align256((size_t)nv);
         f.far[i] = nullptr;  // no near-far split for batched queries
+        f.cand[i] = nullptr;  // no small rounds either
     }
     for (int k = 0; k < kMaxParts; ++k) {
         f.qse[k] = nullptr;

@@ -60,6 +60,8 @@ struct DevGraph {
 //   qse[k], qs[k]    sparse frontier of partition k: (first arc, dist[u]) --
 //                    (first arc, u) for batched queries -- and the exclusive
 //                    prefix sum of the arc counts
+//   cand[2]          queued loop: candidate lists (improved vertices, with
+//                    repeats) that let small rounds skip the flag scan
 //   ctl              3 slots of kSlotWords counters, rotated over three
 //                    iterations so that a slot is cleared one iteration after
 //                    its last use: word k < 8 packs F_k (low 32 bits) and E_k
@@ -69,6 +71,9 @@ struct DevGraph {
 struct Frontier {
     uint8_t *flags[2];
     uint8_t *far[2];
+    int32_t *cand[2];  // candidate lists of the small rounds (queued loop)
+    unsigned long long *ccount;  // their counters: 3 rounds x kCandRegions
+    int32_t cand_cap;
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
     unsigned long long *ctl;
@@ -77,11 +82,12 @@ struct Frontier {
     int32_t np;
 };
 
+constexpr int kCandRegions = 64;  // regions of a small-round candidate list
 constexpr int kCtlSlots = 3;
 constexpr int kSlotWords = 16;
 constexpr int kFarCountWord = 8;    // within a slot
 constexpr int kFarMaxInvWord = 9;   // within a slot: max of ~dist[u] over held-back u
-constexpr int kCtlWords = 64;       // 3 slots of 16 words, then LoopState
+constexpr int kCtlWords = 80;       // 3 slots of 16 words, LoopState, candidate counters
 constexpr int kLoopStateWord = 48;  // LoopState at ctl + 48
 constexpr int32_t kDenseRatio = 64;  // default: streaming filter when |frontier| >= n / 64
 
@@ -98,8 +104,13 @@ struct LoopState {
     unsigned long long pull_iters;
     unsigned long long push_frontier_sum;
     unsigned long long threshold;  // near-far: distances below it are pushed now
+    unsigned long long st_round[2];  // queued loop state machine, by launch parity: round ...
+    unsigned long long st_phase[2];  // ... and phase the launch runs
+    unsigned long long small_rounds;
 };
-static_assert(kLoopStateWord + sizeof(LoopState) / 8 <= kCtlWords, "loop state fits the control block");
+constexpr int kActiveWord = 72;  // 3 counters (rounds mod 3): small-round vertices that had arcs
+static_assert(kLoopStateWord + sizeof(LoopState) / 8 <= kActiveWord, "loop state fits the control block");
+static_assert(kActiveWord + 3 <= kCtlWords, "round counters fit the control block");
 static_assert(kCtlSlots * kSlotWords <= kLoopStateWord, "counter slots fit below the loop state");
 
 size_t frontier_bytes(const DevGraph &g);
@@ -149,16 +160,20 @@ struct PersistentCfg {
     int32_t grid;         // co-resident blocks, a multiple of kMaxParts
     uint64_t spin_ticks;  // grid-barrier wait bound, in wall_clock64 ticks
     uint32_t delta;       // near-far split width (weight-type bits); 0 = off
+    int32_t small;        // queued loop: rounds from a short candidate list may skip the filter
 };
 // Largest co-resident grid for the graph's layout (0 if none).
 int persistent_grid(const DevGraph &g, int num_cu);
 hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg,
                              hipStream_t st);
-// Queued loop: iteration `iter` as two ordinary launches (advance, filter) of
-// cfg.grid blocks that read the frontier size from device memory and do
-// nothing once the loop state says the query has ended.
-hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg, int64_t iter,
-                       hipEvent_t ev_adv_begin, hipEvent_t ev_adv_end, hipStream_t st);
+// Queued loop: launch number `launch` of the step kernel (cfg.grid blocks),
+// which runs the phase the loop state names (advance, filter or a small
+// round) and does nothing once the query has ended.
+// phase_log (optional, timing): one byte per launch, what it ran: 1 advance,
+// 2 filter, 3 small round, 4 nothing.
+hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg, int64_t launch,
+                       int8_t *phase_log, int64_t phase_log_cap, hipEvent_t ev_begin, hipEvent_t ev_end,
+                       hipStream_t st);
 
 // Graph build helpers.
 hipError_t launch_pack_arcs(const int32_t *col, const uint32_t *w, int32_t m, uint2 *adj, hipStream_t st);

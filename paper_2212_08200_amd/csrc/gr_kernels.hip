@@ -69,6 +69,7 @@ struct InitArgs {
     const int32_t *pro;
     uint8_t *flags0, *flags1;
     uint8_t *far0, *far1;  // NULL when the near-far split is off
+    unsigned long long *ccount;  // candidate-list counters (queued loop), NULL if absent
     int64_t nflag;  // bytes per flag array (multiple of 16)
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
         if (threadIdx.x < kCtlWords) a.ctl[threadIdx.x] = 0ull;
         __syncthreads();
         if (threadIdx.x == 0) reinterpret_cast<LoopState *>(a.ctl + kLoopStateWord)->threshold = a.threshold;
+        if (a.ccount && threadIdx.x < 3 * kCandRegions) a.ccount[threadIdx.x] = 0ull;
         if (threadIdx.x < a.np) {
             const int k = threadIdx.x;
             const int32_t st = a.pro[(int64_t)src * a.np + k];
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
 // [j*per, min(E, (j+1)*per)).  It finds the entry holding its first rank with
 // a 256-way search, then walks windows of up to kWin consecutive entries
 // staged in LDS; each lane maps its rank to an entry by binary search in LDS.
-constexpr int kPushItems = 8;
+constexpr int kPushItems = 16;
 // Smallest arc range a block of the device-sized advance takes (one pass of
 // its 256 lanes x 8 items).
 constexpr int32_t kMinChunk = kBlk * kPushItems;
@@ -134,13 +136,55 @@ struct PushArgs {
     uint8_t *nflags;
 };
 
+// Candidate list of the small-frontier rounds: the vertices a round
+// improved, appended in any order and with repeats; the flag bytes decide
+// which copy is expanded.  A wave reserves room for all its lanes' appends
+// with one atomic add; appends past the capacity are dropped but still
+// counted, so an overflowing count tells the next round to scan the flags.
+struct CandOut {
+    int32_t *list;              // NULL: no appends
+    unsigned long long *count;
+    int32_t cap;
+};
+
+// All lanes of the wave call this (convergent); lane l appends its c values
+// vals[0..c).  Returns nothing; values past cap are dropped.
+template <int N>
+__device__ __forceinline__ void wave_append(const CandOut &o, const uint32_t (&vals)[N], const bool (&take)[N]) {
+    int32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) c += take[i] ? 1 : 0;
+    const int lane = threadIdx.x & 63;
+    int32_t inc = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
+    }
+    const int32_t total = __shfl(inc, 63, 64);
+    if (total == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(o.count, (unsigned long long)total);
+    base = __shfl(base, 0, 64);
+    int64_t pos = (int64_t)base + (inc - c);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (take[i]) {
+            if (pos < o.cap) o.list[pos] = (int32_t)vals[i];
+            ++pos;
+        }
+    }
+}
+
 // Arc ranks [j*per, min(E, (j+1)*per)) of one partition's frontier
 // (F entries (first arc, u) with arc-count prefix sums s), by one block.
+// With cand.list set, improved vertices are also appended to the candidate
+// list (small rounds follow when it stays short).
 template <int WT>
 __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint32_t *__restrict__ dist,
                                            const uint2 *__restrict__ qse, const int32_t *__restrict__ s,
                                            int32_t F, int32_t E, int32_t per, int64_t j,
-                                           uint8_t *__restrict__ nflags) {
+                                           uint8_t *__restrict__ nflags, const CandOut &cand) {
     __shared__ int32_t sS[kWin + 1];
     __shared__ uint32_t sRow[kWin];
     __shared__ uint32_t sDu[kWin];
@@ -169,7 +213,10 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
             sS[t] = (t == cnt) ? ((i0 + cnt < F) ? s[i0 + cnt] : E) : INT32_MAX;
         __syncthreads();
         const int32_t wend = min(end, sS[cnt]);
-        for (int32_t x0 = e + threadIdx.x; x0 < wend; x0 += kBlk * kPushItems) {
+        // The pass loop is uniform over the block (x0b), so the waves stay
+        // convergent for the candidate appends.
+        for (int32_t x0b = e; x0b < wend; x0b += kBlk * kPushItems) {
+            const int32_t x0 = x0b + (int32_t)threadIdx.x;
             // Ranks past the window end are clamped to its last rank, so every
             // item does the same unconditional LDS reads and loads (keeping them
             // batched); only the commit is predicated.
@@ -199,9 +246,15 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
                 nd[it] = plus<WT>(sDu[pos[it]], arc[it].y);
                 cur[it] = dist[arc[it].x];
             }
+            bool take[kPushItems];
+            uint32_t vv[kPushItems];
 #pragma unroll
-            for (int it = 0; it < kPushItems; ++it)
-                if (x0 + it * kBlk < wend && nd[it] < cur[it]) relax_commit(dist, nflags, arc[it].x, nd[it]);
+            for (int it = 0; it < kPushItems; ++it) {
+                take[it] = x0 + it * kBlk < wend && nd[it] < cur[it];
+                vv[it] = arc[it].x;
+                if (take[it]) relax_commit(dist, nflags, arc[it].x, nd[it]);
+            }
+            if (cand.list) wave_append<kPushItems>(cand, vv, take);
         }
         i0 += cnt;
         e = wend;
@@ -213,7 +266,8 @@ template <int WT, int NP>
 __global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
     const int k = (NP == 1) ? 0 : (int)(blockIdx.x % NP);
     const int64_t j = (NP == 1) ? blockIdx.x : blockIdx.x / NP;
-    push_range<WT>(a.padj, a.dist, a.qse[k], a.qs[k], a.F[k], a.E[k], a.per[k], j, a.nflags);
+    push_range<WT>(a.padj, a.dist, a.qse[k], a.qs[k], a.F[k], a.E[k], a.per[k], j, a.nflags,
+                   CandOut{nullptr, nullptr, 0});
 }
 
 // ---------------------------------------------------------------------------
@@ -296,15 +350,13 @@ __global__ __launch_bounds__(kBlk) void k_pull(int32_t n, const int32_t *__restr
 }
 
 // ---------------------------------------------------------------------------
-// filter: one block per (group of 4096 vertices, partition k); block b works
-// on group b / np and partition b % np, so with 8 partitions the queue of
-// partition k is written on the XCD whose push blocks read it.  Thread t owns
-// vertices [base + 16 t, base + 16 t + 16), so each queue slice is in vertex
-// order.  A block reserves its slice of partition k's queue and of that
-// queue's arc prefix sum with one 64-bit atomic add of (count | arcs << 32).
-// It also clears its share of the current frontier's flags (so they can hold
-// the frontier after next); block 0 clears the counter slot that was last
-// used one iteration ago.
+// filter: one block per group of 4096 vertices.  Thread t owns vertices
+// [base + 16 t, base + 16 t + 16), so each queue slice is in vertex order.  A
+// block reserves its slice of partition k's queue and of that queue's arc
+// prefix sum with one 64-bit atomic add of (count | arcs << 32) per partition.
+// It also clears the group's current flags (so they can hold the frontier
+// after next); block 0 clears the counter slot that was last used one
+// iteration ago.
 constexpr int kVpt = kGroupVerts / kBlk;  // 16
 
 struct FilterArgs {
@@ -365,35 +417,53 @@ __device__ __forceinline__ uint32_t held_back(const uint32_t *__restrict__ dist,
     return held;
 }
 
+// Offsets of u's arcs in every partition: first[k] = pro[u*NP + k], and
+// end[k] = pro[(u+1)*NP + k] (rows of NP ints, 32-byte aligned for NP = 8).
+template <int NP>
+__device__ __forceinline__ void arc_rows(const int32_t *__restrict__ pro, int64_t u, int32_t (&first)[NP],
+                                         int32_t (&end)[NP]) {
+    if constexpr (NP == 8) {
+        const uint4 *r = reinterpret_cast<const uint4 *>(pro + u * 8);
+        const uint4 a0 = r[0], a1 = r[1], b0 = r[2], b1 = r[3];
+        first[0] = a0.x; first[1] = a0.y; first[2] = a0.z; first[3] = a0.w;
+        first[4] = a1.x; first[5] = a1.y; first[6] = a1.z; first[7] = a1.w;
+        end[0] = b0.x; end[1] = b0.y; end[2] = b0.z; end[3] = b0.w;
+        end[4] = b1.x; end[5] = b1.y; end[6] = b1.z; end[7] = b1.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            first[k] = pro[u * NP + k];
+            end[k] = pro[(u + 1) * NP + k];
+        }
+    }
+}
+
+// Group filter: block g takes the 4096 vertices of group g for every
+// partition.  Thread t owns vertices g*4096 + 16t .. +15: it reads their flag
+// bytes as one 16-byte word, clears the matching word of the current flags
+// and, for each flagged vertex, reads its offset rows once; one block-wide
+// scan of the per-partition counts (entries, arcs) and one atomic per
+// partition reserve the block's slices of the partition queues.
 // a: the iteration-independent arguments (kernel-argument resident); the
 // flags, held-back flags, threshold and counter slots of the iteration are
 // passed separately.
-__device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t vb, const uint8_t *__restrict__ nflags,
+template <int NP>
+__device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t g, const uint8_t *__restrict__ nflags,
                                              uint8_t *__restrict__ cflags, unsigned long long *ctl_next,
                                              unsigned long long *ctl_zero, const uint8_t *__restrict__ far_cur,
                                              uint8_t *__restrict__ far_next, uint32_t T) {
-    __shared__ unsigned long long sh_base;
+    __shared__ unsigned long long sh_base[NP];
     __shared__ uint32_t sh_far_cnt, sh_far_inv;
-    const int np = a.np;
-    const int32_t g = (int32_t)(vb / np);
-    const int k = (int)(vb % np);
-    if (vb == 0 && threadIdx.x < kSlotWords) ctl_zero[threadIdx.x] = 0ull;
-    if (a.zmask && k == 0)
-        for (int t = threadIdx.x; t < kGroupVerts; t += kBlk) a.zmask[(int64_t)g * kGroupVerts + t] = 0ull;
-    {
-        // this block's share of the group's current flags: 4096 / np bytes
-        const int share16 = kGroupVerts / 16 / np;
-        if ((int)threadIdx.x < share16)
-            reinterpret_cast<uint4 *>(cflags)[(int64_t)g * (kGroupVerts / 16) + k * share16 + threadIdx.x] =
-                make_uint4(0u, 0u, 0u, 0u);
-    }
-    const int64_t base = (int64_t)g * kGroupVerts + threadIdx.x * kVpt;
+    if (g == 0 && threadIdx.x < kSlotWords) ctl_zero[threadIdx.x] = 0ull;
+    if (a.zmask)
+        for (int t = threadIdx.x; t < kGroupVerts; t += kBlk) a.zmask[g * kGroupVerts + t] = 0ull;
+    const int64_t base = g * kGroupVerts + threadIdx.x * kVpt;
     uint32_t mask16 = nonzero_bytes(reinterpret_cast<const uint4 *>(nflags)[base >> 4]);
+    reinterpret_cast<uint4 *>(cflags)[base >> 4] = make_uint4(0u, 0u, 0u, 0u);
     if (far_cur) {
         // near-far split: candidates are the flagged and the held-back
         // vertices; those below T join the frontier, the others are held back
-        // again.  The threads whose 16 vertices lie in this block's share of
-        // the group write the share's next held-back flags and count them.
+        // again (each thread writes the next held-back flags of its 16)
         if (threadIdx.x == 0) {
             sh_far_cnt = 0u;
             sh_far_inv = 0u;
@@ -402,15 +472,11 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t vb, co
         uint32_t cnt = 0u, inv = 0u;
         const uint32_t held = held_back(a.dist, base, mask16, T, &cnt, &inv);
         mask16 &= ~held;
-        const int share16 = kGroupVerts / 16 / np;
-        const bool mine = (int)threadIdx.x >= k * share16 && (int)threadIdx.x < (k + 1) * share16;
+        reinterpret_cast<uint4 *>(far_next)[base >> 4] = bytes_of_bits(held);
         __syncthreads();
-        if (mine) {
-            reinterpret_cast<uint4 *>(far_next)[base >> 4] = bytes_of_bits(held);
-            if (cnt) {
-                atomicAdd(&sh_far_cnt, cnt);
-                atomicMax(&sh_far_inv, inv);
-            }
+        if (cnt) {
+            atomicAdd(&sh_far_cnt, cnt);
+            atomicMax(&sh_far_inv, inv);
         }
         __syncthreads();
         if (threadIdx.x == 0 && sh_far_cnt) {
@@ -420,43 +486,55 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t vb, co
     }
     if (!__syncthreads_or(mask16 != 0)) return;  // uniform per block
 
-    int32_t x[2] = {0, 0}, tot[2];
-    for (int b = 0; b < kVpt; ++b) {
-        if ((mask16 >> b) & 1u) {
-            const int64_t u = base + b;
-            const int32_t d = a.pro[(u + 1) * np + k] - a.pro[u * np + k];
-            if (d > 0) {
-                x[0] += 1;
-                x[1] += d;
-            }
+    // x[k] = entries of partition k, x[NP + k] = their arcs
+    int32_t x[2 * NP], tot[2 * NP];
+#pragma unroll
+    for (int i = 0; i < 2 * NP; ++i) x[i] = 0;
+    for (uint32_t mm = mask16; mm; mm &= mm - 1) {
+        const int64_t u = base + __builtin_ctz(mm);
+        int32_t f[NP], e[NP];
+        arc_rows<NP>(a.pro, u, f, e);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int32_t d = e[k] - f[k];
+            x[k] += d > 0 ? 1 : 0;
+            x[NP + k] += d;
         }
     }
-    block_scan<2>(x, tot);
-    if (threadIdx.x == 0)
-        sh_base = tot[0] ? atomicAdd(ctl_next + k, (unsigned long long)tot[0] | ((unsigned long long)tot[1] << 32))
-                         : 0ull;
+    block_scan<2 * NP>(x, tot);
+    if (threadIdx.x < NP) {
+        const int k = threadIdx.x;
+        sh_base[k] = tot[k] ? atomicAdd(ctl_next + k, (unsigned long long)tot[k] |
+                                                          ((unsigned long long)tot[NP + k] << 32))
+                            : 0ull;
+    }
     __syncthreads();
-    int32_t pos = (int32_t)(sh_base & 0xFFFFFFFFull) + x[0];
-    int32_t spos = (int32_t)(sh_base >> 32) + x[1];
-    uint2 *__restrict__ qse = a.qse[k];
-    int32_t *__restrict__ qs = a.qs[k];
-    for (int b = 0; b < kVpt; ++b) {
-        if ((mask16 >> b) & 1u) {
-            const int64_t u = base + b;
-            const int32_t st = a.pro[u * np + k];
-            const int32_t d = a.pro[(u + 1) * np + k] - st;
+    int32_t pos[NP], spos[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        pos[k] = (int32_t)(sh_base[k] & 0xFFFFFFFFull) + x[k];
+        spos[k] = (int32_t)(sh_base[k] >> 32) + x[NP + k];
+    }
+    for (uint32_t mm = mask16; mm; mm &= mm - 1) {
+        const int64_t u = base + __builtin_ctz(mm);
+        int32_t f[NP], e[NP];
+        arc_rows<NP>(a.pro, u, f, e);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int32_t d = e[k] - f[k];
             if (d > 0) {
-                qse[pos] = make_uint2((uint32_t)st, (uint32_t)u);
-                qs[pos] = spos;
-                ++pos;
-                spos += d;
+                a.qse[k][pos[k]] = make_uint2((uint32_t)f[k], (uint32_t)u);
+                a.qs[k][pos[k]] = spos[k];
+                ++pos[k];
+                spos[k] += d;
             }
         }
     }
 }
 
+template <int NP>
 __global__ __launch_bounds__(kBlk) void k_filter(FilterArgs a) {
-    filter_group(a, blockIdx.x, a.nflags, a.cflags, a.ctl_next, a.ctl_zero, a.far_cur, a.far_next, a.threshold);
+    filter_group<NP>(a, blockIdx.x, a.nflags, a.cflags, a.ctl_next, a.ctl_zero, a.far_cur, a.far_next, a.threshold);
 }
 
 // Streaming filter for large frontiers: block b works on partition b % np and
@@ -640,6 +718,16 @@ struct PersistArgs {
     int32_t max_iters, alpha_x16, direction, filter, dense_ratio;
     uint32_t delta;
     uint64_t spin_ticks;
+    // queued loop, small rounds: the CSR as given, the candidate lists (in
+    // kCandRegions regions of cand_region entries) and their counters
+    const int32_t *ro;
+    const uint2 *adj;
+    int32_t *cand[2];
+    unsigned long long *ccount;  // 3 rounds x kCandRegions
+    int32_t cand_region;
+    int32_t small;
+    int8_t *phase_log;  // timing: phase each launch ran (NULL: off)
+    int64_t phase_log_cap;
 };
 
 // Totals of the frontier in a counter slot, and partition kb's share.
@@ -713,7 +801,8 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
             for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
         } else {
             const int32_t per = (int32_t)max<int64_t>(kMinChunk, ((int64_t)t.Ek + B - 1) / B);
-            push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf);
+            push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf,
+                           CandOut{nullptr, nullptr, 0});
         }
         if (!grid_sync(ls, (unsigned)G, a.spin_ticks)) break;
         unsigned long long *cn = a.ctl + ((iter + 1) % kCtlSlots) * kSlotWords;
@@ -727,8 +816,7 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
             const int64_t nvb = (int64_t)a.fd.chunks * NP;
             for (int64_t vb = b; vb < nvb; vb += G) filter_dense(a.fd, vb, nf, cf, nullptr, cn, cz, fc, fn, T);
         } else {
-            const int64_t nvb = (int64_t)a.ngroups * NP;
-            for (int64_t vb = b; vb < nvb; vb += G) filter_group(a.fg, vb, nf, cf, cn, cz, fc, fn, T);
+            for (int64_t vb = b; vb < a.ngroups; vb += G) filter_group<NP>(a.fg, vb, nf, cf, cn, cz, fc, fn, T);
         }
         if (b == 0 && threadIdx.x == 0 && !idle) {
             ls->frontier_sum += (unsigned long long)t.Fs;
@@ -746,82 +834,343 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Queued loop: the host enqueues iterations ahead of the device, in chunks,
-// without waiting for the frontier size; each iteration is an advance launch
-// and a filter launch of a fixed grid that take their sizes from the counter
-// slot of the iteration.  The kernel boundary orders the two halves (no grid
-// barrier), and once the advance of some iteration finds the frontier empty
-// (or the cap reached) it ends the query in the loop state, after which the
-// launches still queued return at once.
+// Queued loop: the host enqueues launches of one step kernel ahead of the
+// device, in chunks, without waiting for frontier sizes.  The step kernel is
+// a small state machine kept in the loop state: each launch runs one phase of
+// the round it finds there and writes the phase the next launch runs (by
+// launch parity, so blocks of one launch never see the next launch's state).
+// The kernel boundary orders the phases (no grid barrier).  Once some phase
+// finds the frontier empty (or the cap reached) it ends the query, after
+// which the launches still queued return at once.
+//
+// Phases of round r:
+//   advance      push (or pull) from the round's queues; then filter
+//   filter       the flag scan that builds the next round's queues
+//   after-small  round r - 1 was a small round: if its candidate list did not
+//                overflow, round r is another small round (advance and filter
+//                in one launch); otherwise this launch runs round r - 1's
+//                filter and round r continues with a normal advance
+// A round's candidate list is split into kCandRegions regions with their own
+// counters (block b appends to region b % kCandRegions), so that appends do
+// not all contend for one counter.
 
 __device__ __forceinline__ unsigned long long loop_status(const LoopState *ls) {
     return __hip_atomic_load(&ls->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int WT, int NP>
-__global__ __launch_bounds__(kBlk) void k_step_advance(PersistArgs a, int64_t iter) {
-    LoopState *ls = reinterpret_cast<LoopState *>(a.ctl + kLoopStateWord);
-    if (loop_status(ls) != 0ull) return;
-    const int64_t G = gridDim.x, b = blockIdx.x;
-    const int kb = (int)(b % NP);
-    const int64_t jb = b / NP, B = G / NP;
-    const SlotTotals t = slot_totals<NP>(a.ctl + (iter % kCtlSlots) * kSlotWords, kb);
-    if ((t.Fs == 0 && t.far_cnt == 0) || iter >= a.max_iters) {
-        if (b == 0 && threadIdx.x == 0) {
-            ls->iter = (unsigned long long)iter;
-            __hip_atomic_store(&ls->status, t.Fs == 0 && t.far_cnt == 0 ? 1ull : 2ull, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+enum : int { kPhaseAdvance = 0, kPhaseFilter = 1, kPhaseAfterSmall = 2 };
+// phase log entries (timing): what a launch ran
+enum : int8_t { kRanAdvance = 1, kRanFilter = 2, kRanSmall = 3, kRanIdle = 4 };
+
+// Candidate regions of one round, summed by a block: sPre[r] = candidates in
+// regions before r (each region capped at its size), sPre[kCandRegions] = N.
+// Returns the uncapped total; *ovf = some region overflowed.
+__device__ __forceinline__ int64_t cand_prefix(const unsigned long long *cnt, int32_t rsize, int32_t *sPre,
+                                               int *sOvf) {
+    __shared__ unsigned long long sTot;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const unsigned long long c = cnt[lane];
+        const int32_t cc = (int32_t)min(c, (unsigned long long)rsize);
+        int32_t inc = cc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t t = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += t;
         }
-        return;
-    }
-    if (t.Fs == 0) {  // held-back vertices only: raise the threshold, the filter releases them
-        if (b == 0 && threadIdx.x == 0) ls->threshold = next_threshold_dev<WT>(t.far_min, a.delta);
-        return;
-    }
-    const bool pull = pick_pull(a, iter, t.Es);
-    if (b == 0 && threadIdx.x == 0) {
-        ls->frontier_sum += (unsigned long long)t.Fs;
-        if ((unsigned long long)t.Fs > ls->frontier_max) ls->frontier_max = (unsigned long long)t.Fs;
-        if (pull) {
-            ls->arcs_pulled += (unsigned long long)a.m;
-            ls->pull_iters += 1ull;
-        } else {
-            ls->edges_pushed += (unsigned long long)t.Es;
-            ls->push_frontier_sum += (unsigned long long)t.Fs;
+        sPre[lane] = inc - cc;
+        if (lane == 63) sPre[64] = inc;
+        const unsigned long long any = __ballot(c > (unsigned long long)rsize);
+        unsigned long long tot = c;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, 64);
+        if (lane == 0) {
+            *sOvf = any != 0ull;
+            sTot = tot;
         }
     }
-    uint8_t *cf = a.flags[iter & 1];
-    uint8_t *nf = a.flags[(iter + 1) & 1];
-    if (pull) {
-        const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
-        for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
-    } else {
-        // at least kMinChunk arcs per block: small frontiers use few blocks
-        const int32_t per = (int32_t)max<int64_t>(kMinChunk, ((int64_t)t.Ek + B - 1) / B);
-        push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf);
+    __syncthreads();
+    return (int64_t)sTot;
+}
+
+// Small round r (push only): the frontier is the candidate list of round
+// r - 1.  Each candidate is claimed by an atomic clear of its flag byte (so
+// repeats expand once, and the flags of the round are left clear); a claimed
+// vertex with at most kLight arcs is expanded by its own thread
+// (thread-mapped), the others are gathered in LDS and expanded by the whole
+// block over the prefix sum of their degrees (block-mapped, the push's
+// search).  Improved vertices are marked in the next flags and appended to
+// the next candidate list.  Used only on graphs whose largest degree is small
+// (see run_queued), so one block's share stays bounded.
+constexpr int kLight = 8;
+
+template <int WT>
+__device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, LoopState *ls, const int32_t *sPre) {
+    __shared__ int32_t hS[kBlk + 1];
+    __shared__ int32_t hStart[kBlk];
+    __shared__ int32_t hDeg[kBlk];
+    __shared__ uint32_t hDu[kBlk];
+    __shared__ int32_t hCount;
+    const int64_t nin = sPre[kCandRegions];
+    const int32_t R = a.cand_region;
+    const int32_t *__restrict__ cin = a.cand[r & 1];
+    const int region = (int)(blockIdx.x % kCandRegions);
+    const CandOut co{a.cand[(r + 1) & 1] + (int64_t)region * R, a.ccount + ((r + 1) % 3) * kCandRegions + region, R};
+    unsigned int *curw = reinterpret_cast<unsigned int *>(a.flags[r & 1]);
+    uint8_t *nf = a.flags[(r + 1) & 1];
+    int32_t st_win = 0, st_arcs = 0;
+    for (int64_t j0 = (int64_t)blockIdx.x * kBlk; j0 < nin; j0 += (int64_t)gridDim.x * kBlk) {
+        if (threadIdx.x == 0) hCount = 0;
+        __syncthreads();
+        const int64_t j = j0 + threadIdx.x;
+        int32_t v = -1;
+        if (j < nin) {
+            int q = 0;  // region of j: largest q with sPre[q] <= j
+#pragma unroll
+            for (int b = kCandRegions / 2; b >= 1; b >>= 1) q = (sPre[q + b] <= j) ? q + b : q;
+            v = cin[(int64_t)q * R + (j - sPre[q])];
+        }
+        bool win = false;
+        if (v >= 0) {
+            const unsigned int m = 0xFFu << ((v & 3) * 8);
+            win = (atomicAnd(curw + (v >> 2), ~m) & m) != 0u;
+        }
+        int32_t st = 0, deg = 0;
+        uint32_t du = 0;
+        if (win) {
+            st = a.ro[v];
+            deg = a.ro[v + 1] - st;
+            du = a.dist[v];
+            st_win += deg > 0 ? 1 : 0;  // as the filter, which drops vertices without arcs
+            st_arcs += deg;
+        }
+        const bool light = win && deg <= kLight;
+        if (win && !light) {
+            const int h = atomicAdd(&hCount, 1);
+            hStart[h] = st;
+            hDeg[h] = deg;
+            hDu[h] = du;
+        }
+        {  // thread-mapped expansion
+            uint2 arc[kLight];
+            uint32_t cur[kLight], nd[kLight], vv[kLight];
+            bool take[kLight];
+#pragma unroll
+            for (int it = 0; it < kLight; ++it)
+                arc[it] = (light && it < deg) ? load_arc(a.adj + st + it) : make_uint2(0u, 0u);
+#pragma unroll
+            for (int it = 0; it < kLight; ++it) {
+                nd[it] = plus<WT>(du, arc[it].y);
+                cur[it] = (light && it < deg) ? a.dist[arc[it].x] : 0u;
+            }
+#pragma unroll
+            for (int it = 0; it < kLight; ++it) {
+                take[it] = light && it < deg && nd[it] < cur[it];
+                vv[it] = arc[it].x;
+                if (take[it]) relax_commit(a.dist, nf, arc[it].x, nd[it]);
+            }
+            wave_append<kLight>(co, vv, take);
+        }
+        __syncthreads();
+        const int hc = hCount;
+        if (hc > 0) {  // block-mapped expansion of the heavier vertices
+            int32_t x[1] = {(int)threadIdx.x < hc ? hDeg[threadIdx.x] : 0}, tot[1];
+            block_scan<1>(x, tot);
+            if ((int)threadIdx.x < hc) hS[threadIdx.x] = x[0];
+            for (int t = hc + threadIdx.x; t <= kBlk; t += kBlk) hS[t] = (t == hc) ? tot[0] : INT32_MAX;
+            __syncthreads();
+            const int32_t H = tot[0];
+            for (int32_t x0b = 0; x0b < H; x0b += kBlk * kPushItems) {
+                int32_t xr[kPushItems], pos[kPushItems];
+#pragma unroll
+                for (int it = 0; it < kPushItems; ++it) {
+                    xr[it] = min(x0b + (int32_t)threadIdx.x + it * kBlk, H - 1);
+                    pos[it] = 0;
+                }
+#pragma unroll
+                for (int b = kBlk / 2; b >= 1; b >>= 1) {
+#pragma unroll
+                    for (int it = 0; it < kPushItems; ++it) {
+                        const int32_t p = pos[it] + b;
+                        pos[it] = (hS[p] <= xr[it]) ? p : pos[it];
+                    }
+                }
+                uint2 arc[kPushItems];
+#pragma unroll
+                for (int it = 0; it < kPushItems; ++it)
+                    arc[it] = load_arc(a.adj + hStart[pos[it]] + (xr[it] - hS[pos[it]]));
+                uint32_t nd[kPushItems], cur[kPushItems], vv[kPushItems];
+                bool take[kPushItems];
+#pragma unroll
+                for (int it = 0; it < kPushItems; ++it) {
+                    nd[it] = plus<WT>(hDu[pos[it]], arc[it].y);
+                    cur[it] = a.dist[arc[it].x];
+                }
+#pragma unroll
+                for (int it = 0; it < kPushItems; ++it) {
+                    take[it] = x0b + (int32_t)threadIdx.x + it * kBlk < H && nd[it] < cur[it];
+                    vv[it] = arc[it].x;
+                    if (take[it]) relax_commit(a.dist, nf, arc[it].x, nd[it]);
+                }
+                wave_append<kPushItems>(co, vv, take);
+            }
+        }
+        __syncthreads();  // LDS reuse
+    }
+    int32_t x[2] = {st_win, st_arcs}, tot[2];
+    block_scan<2>(x, tot);
+    if (threadIdx.x == 0 && tot[0] > 0) {
+        atomicAdd(a.ctl + kActiveWord + r % 3, (unsigned long long)tot[0]);
+        atomicAdd(&ls->frontier_sum, (unsigned long long)tot[0]);
+        atomicAdd(&ls->push_frontier_sum, (unsigned long long)tot[0]);
+        atomicAdd(&ls->edges_pushed, (unsigned long long)tot[1]);
     }
 }
 
+// Normal filter of round r (flag scan), shared by the filter phase and the
+// after-small phase.  Fs: the size estimate of the next frontier.
 template <int NP>
-__global__ __launch_bounds__(kBlk) void k_step_filter(PersistArgs a, int64_t iter) {
-    const LoopState *ls = reinterpret_cast<const LoopState *>(a.ctl + kLoopStateWord);
-    if (loop_status(ls) != 0ull) return;
+__device__ __forceinline__ void step_filter(const PersistArgs &a, int64_t r, const LoopState *ls, int64_t Fs) {
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const SlotTotals t = slot_totals<NP>(a.ctl + (iter % kCtlSlots) * kSlotWords, 0);
-    uint8_t *cf = a.flags[iter & 1];
-    uint8_t *nf = a.flags[(iter + 1) & 1];
-    unsigned long long *cn = a.ctl + ((iter + 1) % kCtlSlots) * kSlotWords;
-    unsigned long long *cz = a.ctl + ((iter + 2) % kCtlSlots) * kSlotWords;
+    uint8_t *cf = a.flags[r & 1];
+    uint8_t *nf = a.flags[(r + 1) & 1];
+    unsigned long long *cn = a.ctl + ((r + 1) % kCtlSlots) * kSlotWords;
+    unsigned long long *cz = a.ctl + ((r + 2) % kCtlSlots) * kSlotWords;
     const uint32_t T = (uint32_t)ls->threshold;
-    const uint8_t *fc = a.far[0] ? a.far[iter & 1] : nullptr;
-    uint8_t *fn = a.far[0] ? a.far[(iter + 1) & 1] : nullptr;
-    const bool dense = a.filter == 2 || (a.filter == 0 && t.Fs * a.dense_ratio >= a.n);
+    const uint8_t *fc = a.far[0] ? a.far[r & 1] : nullptr;
+    uint8_t *fn = a.far[0] ? a.far[(r + 1) & 1] : nullptr;
+    const bool dense = a.filter == 2 || (a.filter == 0 && Fs * a.dense_ratio >= a.n);
     if (dense) {
         const int64_t nvb = (int64_t)a.fd.chunks * NP;
         for (int64_t vb = b; vb < nvb; vb += G) filter_dense(a.fd, vb, nf, cf, nullptr, cn, cz, fc, fn, T);
     } else {
-        const int64_t nvb = (int64_t)a.ngroups * NP;
-        for (int64_t vb = b; vb < nvb; vb += G) filter_group(a.fg, vb, nf, cf, cn, cz, fc, fn, T);
+        for (int64_t vb = b; vb < a.ngroups; vb += G) filter_group<NP>(a.fg, vb, nf, cf, cn, cz, fc, fn, T);
+    }
+}
+
+template <int WT, int NP>
+__global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
+    __shared__ int32_t sPre[kCandRegions + 1];
+    __shared__ int sOvf;
+    LoopState *ls = reinterpret_cast<LoopState *>(a.ctl + kLoopStateWord);
+    if (loop_status(ls) != 0ull) return;
+    const int par = (int)(launch & 1);
+    const int64_t r = (int64_t)ls->st_round[par];
+    const int phase = (int)ls->st_phase[par];
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const bool lead = b == 0 && threadIdx.x == 0;
+    int8_t ran = kRanIdle;
+    int64_t next_r = r;
+    int next_phase = -1;  // -1: the query ended in this launch
+    const int32_t R = a.cand_region;
+    if (phase == kPhaseAfterSmall) {
+        const int64_t total = cand_prefix(a.ccount + (r % 3) * kCandRegions, R, sPre, &sOvf);
+        if (total == 0) {
+            // round r - 1 improved nothing: the query ends; round r - 1 counts
+            // if some vertex it claimed had arcs
+            if (lead) {
+                ls->iter = (unsigned long long)(a.ctl[kActiveWord + (r - 1) % 3] ? r : r - 1);
+                __hip_atomic_store(&ls->status, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else if (!sOvf && r < a.max_iters) {
+            if (lead) a.ctl[kActiveWord + (r + 1) % 3] = 0ull;  // counter of round r + 1
+            if (b == 0 && threadIdx.x < kCandRegions) a.ccount[((r + 2) % 3) * kCandRegions + threadIdx.x] = 0ull;
+            // the queue counter slot a filter of round r would clear (a filter of
+            // round r + 1 may run later and add into it)
+            if (b == 0 && threadIdx.x < kSlotWords)
+                a.ctl[((r + 2) % kCtlSlots) * kSlotWords + threadIdx.x] = 0ull;
+            if (lead) ls->small_rounds += 1ull;
+            small_round<WT>(a, r, ls, sPre);
+            ran = kRanSmall;
+            next_r = r + 1;
+            next_phase = kPhaseAfterSmall;
+        } else if (r >= a.max_iters) {
+            if (lead) {
+                ls->iter = (unsigned long long)r;
+                __hip_atomic_store(&ls->status, 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else {
+            // too many candidates: round r - 1's filter, then a normal round r
+            step_filter<NP>(a, r - 1, ls, total);
+            ran = kRanFilter;
+            next_phase = kPhaseAdvance;
+        }
+    } else if (phase == kPhaseAdvance) {
+        const int kb = (int)(b % NP);
+        const int64_t jb = b / NP, B = G / NP;
+        const SlotTotals t = slot_totals<NP>(a.ctl + (r % kCtlSlots) * kSlotWords, kb);
+        if ((t.Fs == 0 && t.far_cnt == 0) || r >= a.max_iters) {
+            if (lead) {
+                ls->iter = (unsigned long long)r;
+                __hip_atomic_store(&ls->status, t.Fs == 0 && t.far_cnt == 0 ? 1ull : 2ull, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else {
+            next_phase = kPhaseFilter;
+            // counters of round r + 2's list (last read when round r - 1 began)
+            if (b == 0 && threadIdx.x < kCandRegions) a.ccount[((r + 2) % 3) * kCandRegions + threadIdx.x] = 0ull;
+            if (t.Fs == 0) {  // held-back vertices only: raise the threshold, the filter releases them
+                if (lead) ls->threshold = next_threshold_dev<WT>(t.far_min, a.delta);
+            } else {
+                const bool pull = pick_pull(a, r, t.Es);
+                if (lead) {
+                    ls->frontier_sum += (unsigned long long)t.Fs;
+                    if ((unsigned long long)t.Fs > ls->frontier_max) ls->frontier_max = (unsigned long long)t.Fs;
+                    if (pull) {
+                        ls->arcs_pulled += (unsigned long long)a.m;
+                        ls->pull_iters += 1ull;
+                    } else {
+                        ls->edges_pushed += (unsigned long long)t.Es;
+                        ls->push_frontier_sum += (unsigned long long)t.Fs;
+                    }
+                }
+                uint8_t *cf = a.flags[r & 1];
+                uint8_t *nf = a.flags[(r + 1) & 1];
+                if (pull) {
+                    const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
+                    for (int64_t vb = b; vb < nvb; vb += G)
+                        pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
+                } else {
+                    // Candidate appends only when this round cannot improve many
+                    // more vertices than the list holds (a too-long list just
+                    // sends the next round to the flag scan).
+                    const bool app = a.small && t.Es <= 4 * (int64_t)R * kCandRegions;
+                    const int region = (int)(b % kCandRegions);
+                    const CandOut co{app ? a.cand[(r + 1) & 1] + (int64_t)region * R : nullptr,
+                                     a.ccount + ((r + 1) % 3) * kCandRegions + region, R};
+                    // at least kMinChunk arcs per block: small frontiers use few blocks
+                    const int32_t per = (int32_t)max<int64_t>(kMinChunk, ((int64_t)t.Ek + B - 1) / B);
+                    push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf, co);
+                    if (a.small && !app && lead) a.ccount[((r + 1) % 3) * kCandRegions] = (unsigned long long)R + 1ull;
+                }
+            }
+            ran = kRanAdvance;
+        }
+    } else {  // kPhaseFilter
+        const int64_t Fs = slot_totals<NP>(a.ctl + (r % kCtlSlots) * kSlotWords, 0).Fs;
+        step_filter<NP>(a, r, ls, Fs);
+        ran = kRanFilter;
+        next_r = r + 1;
+        next_phase = kPhaseAdvance;
+        if (a.small && b == 0) {
+            // the next round takes the candidate list if it did not overflow
+            // and is not empty (block 0 reads the counters after its share of
+            // the filter; the push that appended ended with the last launch)
+            const int64_t total = cand_prefix(a.ccount + ((r + 1) % 3) * kCandRegions, R, sPre, &sOvf);
+            if (lead) {
+                if (!sOvf && total > 0) {
+                    next_phase = kPhaseAfterSmall;
+                    a.ctl[kActiveWord + (r + 1) % 3] = 0ull;
+                }
+            }
+        }
+    }
+    if (lead) {
+        if (a.phase_log && launch < a.phase_log_cap) a.phase_log[launch] = ran;
+        if (next_phase >= 0) {
+            ls->st_round[par ^ 1] = (unsigned long long)next_r;
+            ls->st_phase[par ^ 1] = (unsigned long long)next_phase;
+        }
     }
 }
 
@@ -1124,6 +1473,7 @@ hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Fro
     a.pro = g.pro;
     a.flags0 = f.flags[0];
     a.flags1 = f.flags[1];
+    a.ccount = f.ccount;
     a.far0 = use_far ? f.far[0] : nullptr;
     a.far1 = use_far ? f.far[1] : nullptr;
     a.threshold = threshold;
@@ -1143,7 +1493,7 @@ hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int
     const int64_t E = c.Esum();
     if (E <= 0) return hipSuccess;
     int64_t target = (E + (int64_t)num_cu * 8 - 1) / ((int64_t)num_cu * 8);
-    if (target < 2048) target = 2048;
+    if (target < kMinChunk) target = kMinChunk;
     int64_t emax = 0;
     for (int k = 0; k < g.np; ++k) emax = c.E[k] > emax ? c.E[k] : emax;
     const int64_t B = (emax + target - 1) / target;
@@ -1230,7 +1580,8 @@ hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uin
     a.far_cur = use_far ? f.far[p] : nullptr;
     a.far_next = use_far ? f.far[p ^ 1] : nullptr;
     a.threshold = threshold;
-    hipLaunchKernelGGL(k_filter, dim3(f.ngroups * g.np), dim3(kBlk), 0, st, a);
+    if (g.np == 1) hipLaunchKernelGGL(k_filter<1>, dim3(f.ngroups), dim3(kBlk), 0, st, a);
+    else hipLaunchKernelGGL(k_filter<kMaxParts>, dim3(f.ngroups), dim3(kBlk), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1407,6 +1758,15 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     a.adj_in = g.adj_in;
     a.flags[0] = f.flags[0];
     a.flags[1] = f.flags[1];
+    a.ro = g.ro;
+    a.adj = g.adj;
+    a.cand[0] = f.cand[0];
+    a.cand[1] = f.cand[1];
+    a.ccount = f.ccount;
+    a.cand_region = f.cand_cap / kCandRegions;
+    a.small = cfg.small && f.cand[0] != nullptr ? 1 : 0;
+    a.phase_log = nullptr;
+    a.phase_log_cap = 0;
     a.far[0] = cfg.delta ? f.far[0] : nullptr;
     a.far[1] = cfg.delta ? f.far[1] : nullptr;
     a.delta = cfg.delta;
@@ -1430,22 +1790,23 @@ hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &
     return g.wt == 1 ? coop_launch<1, kMaxParts>(a, cfg.grid, st) : coop_launch<0, kMaxParts>(a, cfg.grid, st);
 }
 
-hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg, int64_t iter,
-                       hipEvent_t ev_adv_begin, hipEvent_t ev_adv_end, hipStream_t st) {
+hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg, int64_t launch,
+                       int8_t *phase_log, int64_t phase_log_cap, hipEvent_t ev_begin, hipEvent_t ev_end,
+                       hipStream_t st) {
     PersistArgs a;
     persist_args(g, dist, f, cfg, a);
+    a.phase_log = phase_log;
+    a.phase_log_cap = phase_log_cap;
     const dim3 grid((unsigned)cfg.grid), blk(kBlk);
-    if (ev_adv_begin) (void)hipEventRecord(ev_adv_begin, st);
+    if (ev_begin) (void)hipEventRecord(ev_begin, st);
     if (g.np == 1) {
-        if (g.wt == 1) hipLaunchKernelGGL((k_step_advance<1, 1>), grid, blk, 0, st, a, iter);
-        else hipLaunchKernelGGL((k_step_advance<0, 1>), grid, blk, 0, st, a, iter);
+        if (g.wt == 1) hipLaunchKernelGGL((k_step<1, 1>), grid, blk, 0, st, a, launch);
+        else hipLaunchKernelGGL((k_step<0, 1>), grid, blk, 0, st, a, launch);
     } else {
-        if (g.wt == 1) hipLaunchKernelGGL((k_step_advance<1, kMaxParts>), grid, blk, 0, st, a, iter);
-        else hipLaunchKernelGGL((k_step_advance<0, kMaxParts>), grid, blk, 0, st, a, iter);
+        if (g.wt == 1) hipLaunchKernelGGL((k_step<1, kMaxParts>), grid, blk, 0, st, a, launch);
+        else hipLaunchKernelGGL((k_step<0, kMaxParts>), grid, blk, 0, st, a, launch);
     }
-    if (ev_adv_end) (void)hipEventRecord(ev_adv_end, st);
-    if (g.np == 1) hipLaunchKernelGGL((k_step_filter<1>), grid, blk, 0, st, a, iter);
-    else hipLaunchKernelGGL((k_step_filter<kMaxParts>), grid, blk, 0, st, a, iter);
+    if (ev_end) (void)hipEventRecord(ev_end, st);
     return hipGetLastError();
 }
 
@@ -1454,10 +1815,18 @@ hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, con
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Candidate-list capacity: a multiple of kCandRegions, up to 2^18 vertices
+// (1 MiB per list).
+static inline int32_t cand_capacity(int32_t n) {
+    return kCandRegions * std::max(1, std::min(n, 1 << 18) / kCandRegions);
+}
+
 size_t frontier_bytes(const DevGraph &g) {
     const int64_t ng = groups_for(g.n);
     size_t b = 0;
     b += 4 * align256((size_t)ng * kGroupVerts);  // flags, held-back flags
+    b += 2 * align256(sizeof(int32_t) * (size_t)cand_capacity(g.n));
+    b += align256(sizeof(unsigned long long) * 3 * kCandRegions);
     for (int k = 0; k < g.np; ++k) {
         const size_t c = (size_t)(g.cap[k] > 0 ? g.cap[k] : 1);
         b += align256(c * 8) + align256(c * 4);
@@ -1480,6 +1849,13 @@ void frontier_carve(Frontier &f, void *base, const DevGraph &g) {
         f.far[i] = reinterpret_cast<uint8_t *>(p);
         p += align256((size_t)f.nflag);
     }
+    f.cand_cap = cand_capacity(g.n);
+    for (int i = 0; i < 2; ++i) {
+        f.cand[i] = reinterpret_cast<int32_t *>(p);
+        p += align256(sizeof(int32_t) * (size_t)f.cand_cap);
+    }
+    f.ccount = reinterpret_cast<unsigned long long *>(p);
+    p += align256(sizeof(unsigned long long) * 3 * kCandRegions);
     for (int k = 0; k < kMaxParts; ++k) {
         f.qse[k] = nullptr;
         f.qs[k] = nullptr;

@@ -162,12 +162,15 @@ def test_persistent_loop_stats_match_host_loop():
     G = gr.Graph.from_csr(g)
     try:
         a = run(G, 0, DIRS["push"], loop=LOOPS["host"])[1]
-        for lp in ("persistent", "queued", "queued"):  # queued twice: the second starts from a predicted chunk
-            b = run(G, 0, DIRS["push"], loop=LOOPS[lp])[1]
+        for lp, filt in (("persistent", 0), ("queued", 0), ("queued", 3), ("queued", 3)):
+            # queued twice with small rounds: the second starts from a predicted chunk
+            b = run(G, 0, DIRS["push"], loop=LOOPS[lp], filt=filt)[1]
             assert a["iterations"] == b["iterations"] == L, lp
             assert a["edges_pushed"] == b["edges_pushed"] == L, lp
             assert a["frontier_sum"] == b["frontier_sum"] == L, lp
             assert a["push_frontier_sum"] == b["push_frontier_sum"] == L, lp
+            if filt == 3:  # one improved vertex per round: rounds after the first skip the filter
+                assert b["small_rounds"] >= L - 2
         dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
         for lp in ("host", "persistent", "queued"):
             st = gr.gr_sssp_ex(G.handle, 0, dist, loop=LOOPS[lp], timing=1)
@@ -366,5 +369,58 @@ def test_near_far_configs():
             say("near-far rmat20 loop=%s" % lp)
             got, _ = run(G, srcs[0], DIRS["push"], loop=LOOPS[lp], delta=gr.delta_bits(0.25, gg.W_F32))
             assert_same(got, want, "rmat20 near-far loop %s" % lp)
+    finally:
+        G.close()
+
+
+# ------------------------------------------------- queued loop: small rounds
+
+def test_small_rounds_thread_and_block_mapped():
+    # grids: every vertex thread-mapped; R-MAT: hubs go to the block-mapped
+    # path; filter 1 / 2 turn small rounds off and must agree
+    cases = [("grid300", gg.grid(300, wseed=21)), ("rmat14", gg.rmat(14, 16, gseed=22, pseed=23, wseed=24)),
+             ("rmat13f", gg.rmat(13, 16, gseed=25, pseed=26, wseed=27, wtype=gg.W_F32)),
+             ("road", gg.grid(200, wseed=29, whi=1000, shortcuts=40, sseed=28))]
+    for tag, g in cases:
+        G = gr.Graph.from_csr(g, flags=gr.GR_FORCE_PARTITION)
+        try:
+            for s in gg.pick_sources(g, 30, 2):
+                want = oracle.dijkstra(g, int(s))
+                for filt in (3, 0, 1, 2):
+                    say("small rounds %s src=%d filter=%d" % (tag, s, filt))
+                    got, st = run(G, s, DIRS["push"], loop=LOOPS["queued"], filt=filt)
+                    assert_same(got, want, "%s src %d filter %d" % (tag, s, filt))
+                    if filt != 3:
+                        assert st["small_rounds"] == 0
+                    elif tag.startswith("grid"):
+                        assert st["small_rounds"] > st["iterations"] // 2
+        finally:
+            G.close()
+
+
+def test_small_rounds_candidate_overflow():
+    # a tree with fan-out 64, then 2: its last round improves 524,288 vertices,
+    # more than a candidate list holds (2^18), so that round's next frontier
+    # comes from the flag scan; earlier rounds run as small rounds
+    rng = np.random.default_rng(7)
+    src, dst = [], []
+    level, nxt = [0], 1
+    for fan in (64, 64, 64, 2):
+        for u in level:
+            src.extend([u] * fan)
+            dst.extend(range(nxt, nxt + fan))
+            nxt += fan
+        level = list(range(nxt - len(level) * fan, nxt))
+    n = nxt
+    w = rng.integers(1, 50, size=len(src))
+    g = gg.from_arcs(n, list(zip(src, dst, w.tolist())))
+    G = gr.Graph.from_csr(g)
+    try:
+        want = oracle.dijkstra(g, 0)
+        got, st = run(G, 0, DIRS["push"], loop=LOOPS["queued"], filt=3)
+        assert_same(got, want, "tree overflow")
+        ref = run(G, 0, DIRS["push"], loop=LOOPS["host"])[1]
+        assert st["iterations"] == ref["iterations"] and st["edges_pushed"] == ref["edges_pushed"]
+        assert st["small_rounds"] >= 1
     finally:
         G.close()

@@ -47,7 +47,7 @@ def test_tune_then_query(flags, tmp_path, monkeypatch):
     with gr.Graph.from_csr(g, flags=flags) as G2:
         r2 = G2.tune(srcs, reps=2)
         assert r2["from_cache"] == 1
-        for k in ("layout", "loop", "dense_ratio", "alpha_x16", "delta"):
+        for k in ("layout", "loop", "dense_ratio", "alpha_x16", "delta", "small"):
             assert r2[k] == r[k]
         assert np.array_equal(run(G2, srcs[0], g.n), oracle.dijkstra(g, int(srcs[0])))
     lines = open(tmp_path / "tune.jsonl").read().splitlines()
