@@ -128,6 +128,8 @@ static constexpr int32_t kPartitionMinN = 1 << 17;
 // An arc is "near" when |u - v| < n / 64: true for nearly all arcs of grids and
 // meshes, and for about 3% of the arcs of a graph with random vertex ids.
 static inline int32_t locality_span(int32_t n) { return std::max(n / 64, 64); }
+// Small rounds of the queued loop apply to graphs of at most this degree.
+static constexpr int32_t kSmallMaxDegree = 64;
 
 struct gr_graph {
     int device = 0;
@@ -324,6 +326,9 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
         g->max_degree = std::max(g->max_degree, d);
         nonempty += d > 0;
     }
+    // Small rounds by default where they apply (bounded degree): measured
+    // faster on grids and road-like graphs, whose many rounds are small.
+    g->auto_small = g->max_degree <= kSmallMaxDegree;
     BUILD_TRY(launch_locality(n, g->d_ro, g->d_adj, locality_span(n), near, st), "locality");
     unsigned long long hnear = 0;
     BUILD_TRY(hipMemcpyAsync(&hnear, near, sizeof hnear, hipMemcpyDeviceToHost, st), "locality");
@@ -678,7 +683,6 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
 // last chunk so that its state copy has landed before the pinned slot is
 // reused.
 static constexpr int64_t kPhaseLogCap = 1 << 16;
-static constexpr int32_t kSmallMaxDegree = 64;
 
 static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
                             gr_sssp_stats *stats) {
@@ -725,7 +729,13 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     int64_t K = std::clamp<int64_t>(g->last_iters.load(std::memory_order_relaxed) + 1, 4, 512);
     LoopState fin{};
     bool done = false;
+    const int grid_full = cfg.grid;
+    bool small_seen = false;  // the last state read back was in small rounds
     while (e == hipSuccess && !done) {
+        // Small rounds touch few vertices: a chunk that is expected to run
+        // them launches a quarter of the grid (every phase is correct at any
+        // grid size), which shortens the launch of the mostly idle blocks.
+        cfg.grid = small_seen ? std::max(kMaxParts, grid_full / 4) : grid_full;
         for (int64_t i = 0; i < K && e == hipSuccess; ++i) {
             hipEvent_t b = nullptr, en = nullptr;
             if (rc.timing && issued + i < kPhaseLogCap) {
@@ -748,6 +758,7 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
                 fin = ls;
                 done = true;
             }
+            small_seen = cfg.small && ls.st_phase[0] == 2 && ls.st_phase[1] == 2;
         }
         ++c;
         K = std::min<int64_t>(64, 4ll << std::min(c - 1, 4));
@@ -834,6 +845,18 @@ struct BatchStats {
 // per iteration to read the frontier size.
 static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, uint32_t *const *out_rows,
                            hipStream_t st, int64_t max_iters, BatchStats *bs) {
+    if (k == 1 && !bs) {
+        // one source: the single-source path with the graph's AUTO schedule
+        // (its loop needs no host round trip per round)
+        RunCfg rc;
+        gr_status s = check_opts(g, nullptr, &rc);
+        if (s != GR_OK) return s;
+        rc.max_iters = max_iters;
+        const int loop = g->auto_loop;
+        if (loop == GR_LOOP_QUEUED) return run_queued(g, srcs[0], out_rows[0], st, rc, nullptr);
+        if (loop == GR_LOOP_PERSISTENT) return run_persistent(g, srcs[0], out_rows[0], st, rc, nullptr);
+        return run_host_loop(g, srcs[0], out_rows[0], st, rc, nullptr);
+    }
     DeviceInfo di;
     gr_status s = device_info(g->device, &di);
     if (s != GR_OK) return s;

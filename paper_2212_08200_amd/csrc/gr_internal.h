@@ -73,6 +73,7 @@ struct Frontier {
     uint8_t *far[2];
     int32_t *cand[2];  // candidate lists of the small rounds (queued loop)
     unsigned long long *ccount;  // their counters: 3 rounds x kCandRegions
+    unsigned long long *rstat;   // small-round statistics (kStatWords)
     int32_t cand_cap;
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
@@ -108,9 +109,13 @@ struct LoopState {
     unsigned long long st_phase[2];  // ... and phase the launch runs
     unsigned long long small_rounds;
 };
-constexpr int kActiveWord = 72;  // 3 counters (rounds mod 3): small-round vertices that had arcs
-static_assert(kLoopStateWord + sizeof(LoopState) / 8 <= kActiveWord, "loop state fits the control block");
-static_assert(kActiveWord + 3 <= kCtlWords, "round counters fit the control block");
+static_assert(kLoopStateWord + sizeof(LoopState) / 8 <= kCtlWords, "loop state fits the control block");
+// Small-round statistics by candidate region: expanded vertices with arcs in
+// rounds r mod 3 (3 x kCandRegions), then running totals of expanded vertices
+// and of their arcs (kCandRegions each).
+constexpr int kStatFrontier = 3 * kCandRegions;
+constexpr int kStatEdges = 4 * kCandRegions;
+constexpr int kStatWords = 5 * kCandRegions;
 static_assert(kCtlSlots * kSlotWords <= kLoopStateWord, "counter slots fit below the loop state");
 
 size_t frontier_bytes(const DevGraph &g);

@@ -70,6 +70,7 @@ struct InitArgs {
     uint8_t *flags0, *flags1;
     uint8_t *far0, *far1;  // NULL when the near-far split is off
     unsigned long long *ccount;  // candidate-list counters (queued loop), NULL if absent
+    unsigned long long *rstat;   // small-round statistics, NULL if absent
     int64_t nflag;  // bytes per flag array (multiple of 16)
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
@@ -98,6 +99,8 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
         __syncthreads();
         if (threadIdx.x == 0) reinterpret_cast<LoopState *>(a.ctl + kLoopStateWord)->threshold = a.threshold;
         if (a.ccount && threadIdx.x < 3 * kCandRegions) a.ccount[threadIdx.x] = 0ull;
+        if (a.rstat)
+            for (int t = threadIdx.x; t < kStatWords; t += kBlk) a.rstat[t] = 0ull;
         if (threadIdx.x < a.np) {
             const int k = threadIdx.x;
             const int32_t st = a.pro[(int64_t)src * a.np + k];
@@ -147,26 +150,35 @@ struct CandOut {
     int32_t cap;
 };
 
-// All lanes of the wave call this (convergent); lane l appends its c values
-// vals[0..c).  Returns nothing; values past cap are dropped.
+// All threads of the block call this (convergent); thread t appends the
+// values vals[i] with take[i] set.  One atomic add per block reserves the
+// room; values past cap are dropped (the count still grows).
 template <int N>
-__device__ __forceinline__ void wave_append(const CandOut &o, const uint32_t (&vals)[N], const bool (&take)[N]) {
+__device__ __forceinline__ void block_append(const CandOut &o, const uint32_t (&vals)[N], const bool (&take)[N]) {
+    __shared__ int32_t sWave[kBlk / 64];
+    __shared__ unsigned long long sBase;
     int32_t c = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) c += take[i] ? 1 : 0;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int32_t inc = c;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const int32_t t = __shfl_up(inc, off, 64);
         if (lane >= off) inc += t;
     }
-    const int32_t total = __shfl(inc, 63, 64);
+    if (lane == 63) sWave[wid] = inc;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlk / 64; ++w) {
+        before += w < wid ? sWave[w] : 0;
+        total += sWave[w];
+    }
+    if (threadIdx.x == 0 && total > 0) sBase = atomicAdd(o.count, (unsigned long long)total);
+    __syncthreads();
     if (total == 0) return;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(o.count, (unsigned long long)total);
-    base = __shfl(base, 0, 64);
-    int64_t pos = (int64_t)base + (inc - c);
+    int64_t pos = (int64_t)sBase + before + (inc - c);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         if (take[i]) {
@@ -254,7 +266,7 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
                 vv[it] = arc[it].x;
                 if (take[it]) relax_commit(dist, nflags, arc[it].x, nd[it]);
             }
-            if (cand.list) wave_append<kPushItems>(cand, vv, take);
+            if (cand.list) block_append<kPushItems>(cand, vv, take);
         }
         i0 += cnt;
         e = wend;
@@ -542,7 +554,7 @@ __global__ __launch_bounds__(kBlk) void k_filter(FilterArgs a) {
 // in vertex order).  Each member whose frontier flag is set becomes an entry
 // (first arc, u); one atomic per block reserves the slice.  Every block also
 // clears its share of the current frontier's flags.
-constexpr int kDenseItems = 4;
+constexpr int kDenseItems = 8;
 constexpr int kDenseChunk = kBlk * kDenseItems;
 
 struct DenseFilterArgs {
@@ -724,6 +736,7 @@ struct PersistArgs {
     const uint2 *adj;
     int32_t *cand[2];
     unsigned long long *ccount;  // 3 rounds x kCandRegions
+    unsigned long long *rstat;   // small-round statistics by region (see kStat*)
     int32_t cand_region;
     int32_t small;
     int8_t *phase_log;  // timing: phase each launch ran (NULL: off)
@@ -969,7 +982,7 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
                 vv[it] = arc[it].x;
                 if (take[it]) relax_commit(a.dist, nf, arc[it].x, nd[it]);
             }
-            wave_append<kLight>(co, vv, take);
+            block_append<kLight>(co, vv, take);
         }
         __syncthreads();
         const int hc = hCount;
@@ -1012,19 +1025,37 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
                     vv[it] = arc[it].x;
                     if (take[it]) relax_commit(a.dist, nf, arc[it].x, nd[it]);
                 }
-                wave_append<kPushItems>(co, vv, take);
+                block_append<kPushItems>(co, vv, take);
             }
         }
         __syncthreads();  // LDS reuse
     }
+    // statistics per region (so that blocks rarely share an address): the
+    // round's expanded vertices, and running totals folded in at the end
     int32_t x[2] = {st_win, st_arcs}, tot[2];
     block_scan<2>(x, tot);
     if (threadIdx.x == 0 && tot[0] > 0) {
-        atomicAdd(a.ctl + kActiveWord + r % 3, (unsigned long long)tot[0]);
-        atomicAdd(&ls->frontier_sum, (unsigned long long)tot[0]);
-        atomicAdd(&ls->push_frontier_sum, (unsigned long long)tot[0]);
-        atomicAdd(&ls->edges_pushed, (unsigned long long)tot[1]);
+        atomicAdd(a.rstat + (r % 3) * kCandRegions + region, (unsigned long long)tot[0]);
+        atomicAdd(a.rstat + kStatFrontier + region, (unsigned long long)tot[0]);
+        atomicAdd(a.rstat + kStatEdges + region, (unsigned long long)tot[1]);
     }
+}
+
+// Query end (lead thread): fold the small rounds' regional totals into the
+// loop state, then publish the status.
+__device__ __forceinline__ void end_query(const PersistArgs &a, LoopState *ls, int64_t iter, unsigned long long st) {
+    if (a.rstat) {
+        unsigned long long f = 0, e = 0;
+        for (int q = 0; q < kCandRegions; ++q) {
+            f += a.rstat[kStatFrontier + q];
+            e += a.rstat[kStatEdges + q];
+        }
+        ls->frontier_sum += f;
+        ls->push_frontier_sum += f;
+        ls->edges_pushed += e;
+    }
+    ls->iter = (unsigned long long)iter;
+    __hip_atomic_store(&ls->status, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Normal filter of round r (flag scan), shared by the filter phase and the
@@ -1069,11 +1100,13 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
             // round r - 1 improved nothing: the query ends; round r - 1 counts
             // if some vertex it claimed had arcs
             if (lead) {
-                ls->iter = (unsigned long long)(a.ctl[kActiveWord + (r - 1) % 3] ? r : r - 1);
-                __hip_atomic_store(&ls->status, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                unsigned long long act = 0;
+                for (int q = 0; q < kCandRegions; ++q) act += a.rstat[((r - 1) % 3) * kCandRegions + q];
+                end_query(a, ls, act ? r : r - 1, 1ull);
             }
         } else if (!sOvf && r < a.max_iters) {
-            if (lead) a.ctl[kActiveWord + (r + 1) % 3] = 0ull;  // counter of round r + 1
+            if (b == 0 && threadIdx.x < kCandRegions)  // expanded-vertex counters of round r + 1
+                a.rstat[((r + 1) % 3) * kCandRegions + threadIdx.x] = 0ull;
             if (b == 0 && threadIdx.x < kCandRegions) a.ccount[((r + 2) % 3) * kCandRegions + threadIdx.x] = 0ull;
             // the queue counter slot a filter of round r would clear (a filter of
             // round r + 1 may run later and add into it)
@@ -1085,10 +1118,7 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
             next_r = r + 1;
             next_phase = kPhaseAfterSmall;
         } else if (r >= a.max_iters) {
-            if (lead) {
-                ls->iter = (unsigned long long)r;
-                __hip_atomic_store(&ls->status, 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            if (lead) end_query(a, ls, r, 2ull);
         } else {
             // too many candidates: round r - 1's filter, then a normal round r
             step_filter<NP>(a, r - 1, ls, total);
@@ -1100,11 +1130,7 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
         const int64_t jb = b / NP, B = G / NP;
         const SlotTotals t = slot_totals<NP>(a.ctl + (r % kCtlSlots) * kSlotWords, kb);
         if ((t.Fs == 0 && t.far_cnt == 0) || r >= a.max_iters) {
-            if (lead) {
-                ls->iter = (unsigned long long)r;
-                __hip_atomic_store(&ls->status, t.Fs == 0 && t.far_cnt == 0 ? 1ull : 2ull, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
+            if (lead) end_query(a, ls, r, t.Fs == 0 && t.far_cnt == 0 ? 1ull : 2ull);
         } else {
             next_phase = kPhaseFilter;
             // counters of round r + 2's list (last read when round r - 1 began)
@@ -1157,11 +1183,10 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
             // and is not empty (block 0 reads the counters after its share of
             // the filter; the push that appended ended with the last launch)
             const int64_t total = cand_prefix(a.ccount + ((r + 1) % 3) * kCandRegions, R, sPre, &sOvf);
-            if (lead) {
-                if (!sOvf && total > 0) {
-                    next_phase = kPhaseAfterSmall;
-                    a.ctl[kActiveWord + (r + 1) % 3] = 0ull;
-                }
+            if (!sOvf && total > 0) {
+                next_phase = kPhaseAfterSmall;
+                if (threadIdx.x < kCandRegions)  // expanded-vertex counters of round r + 1
+                    a.rstat[((r + 1) % 3) * kCandRegions + threadIdx.x] = 0ull;
             }
         }
     }
@@ -1474,6 +1499,7 @@ hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Fro
     a.flags0 = f.flags[0];
     a.flags1 = f.flags[1];
     a.ccount = f.ccount;
+    a.rstat = f.rstat;
     a.far0 = use_far ? f.far[0] : nullptr;
     a.far1 = use_far ? f.far[1] : nullptr;
     a.threshold = threshold;
@@ -1763,6 +1789,7 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     a.cand[0] = f.cand[0];
     a.cand[1] = f.cand[1];
     a.ccount = f.ccount;
+    a.rstat = f.rstat;
     a.cand_region = f.cand_cap / kCandRegions;
     a.small = cfg.small && f.cand[0] != nullptr ? 1 : 0;
     a.phase_log = nullptr;
@@ -1827,6 +1854,7 @@ size_t frontier_bytes(const DevGraph &g) {
     b += 4 * align256((size_t)ng * kGroupVerts);  // flags, held-back flags
     b += 2 * align256(sizeof(int32_t) * (size_t)cand_capacity(g.n));
     b += align256(sizeof(unsigned long long) * 3 * kCandRegions);
+    b += align256(sizeof(unsigned long long) * kStatWords);
     for (int k = 0; k < g.np; ++k) {
         const size_t c = (size_t)(g.cap[k] > 0 ? g.cap[k] : 1);
         b += align256(c * 8) + align256(c * 4);
@@ -1856,6 +1884,8 @@ void frontier_carve(Frontier &f, void *base, const DevGraph &g) {
     }
     f.ccount = reinterpret_cast<unsigned long long *>(p);
     p += align256(sizeof(unsigned long long) * 3 * kCandRegions);
+    f.rstat = reinterpret_cast<unsigned long long *>(p);
+    p += align256(sizeof(unsigned long long) * kStatWords);
     for (int k = 0; k < kMaxParts; ++k) {
         f.qse[k] = nullptr;
         f.qs[k] = nullptr;
