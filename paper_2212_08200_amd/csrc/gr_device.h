@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "gr_internal.h"
 
 namespace gr {
@@ -30,6 +32,20 @@ __device__ __forceinline__ uint32_t plus(uint32_t d, uint32_t w) {
 __device__ __forceinline__ uint2 load_arc(const uint2 *p) {
     const unsigned long long x = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
     return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+}
+
+// Element idx of base.  With O32 the address is formed as a uniform base plus
+// a 32-bit byte offset, so each lane holds one offset register instead of a
+// 64-bit address (a large share of the registers of the gather-heavy loops);
+// the caller guarantees idx * sizeof(T) < 2^32.
+template <bool O32, typename T>
+__device__ __forceinline__ T *elem(T *base, uint32_t idx) {
+    if constexpr (O32) {
+        using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+        return reinterpret_cast<T *>(reinterpret_cast<C *>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
+    } else {
+        return base + idx;
+    }
 }
 
 // Exclusive block-wide scan of V values per thread; tot receives the totals.

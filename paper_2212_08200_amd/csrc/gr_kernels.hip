@@ -40,7 +40,8 @@ namespace gr {
 // stores the same value, so concurrent marks need no atomics (distinct bytes
 // are distinct memory locations, so marks of neighbouring vertices by other
 // blocks are never lost).
-__device__ __forceinline__ void mark(uint8_t *flags, uint32_t v) { flags[v] = 1; }
+template <bool O32 = false>
+__device__ __forceinline__ void mark(uint8_t *flags, uint32_t v) { *elem<O32>(flags, v) = 1; }
 
 // Relaxation of one edge (Listing 4) is split in two so that a thread can
 // issue the loads of several edges before any of their atomics:
@@ -52,9 +53,10 @@ __device__ __forceinline__ void mark(uint8_t *flags, uint32_t v) { flags[v] = 1;
 // then either the atomic lowers dist[v] or dist[v] was already lowered since
 // the read was cached, during this advance -- either way v improved in this
 // round, so the marked set is exactly the set of improved vertices.
+template <bool O32 = false>
 __device__ __forceinline__ void relax_commit(uint32_t *dist, uint8_t *nflags, uint32_t v, uint32_t nd) {
-    __hip_atomic_fetch_min(dist + v, nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    mark(nflags, v);
+    __hip_atomic_fetch_min(elem<O32>(dist, v), nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mark<O32>(nflags, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -191,8 +193,9 @@ __device__ __forceinline__ void block_append(const CandOut &o, const uint32_t (&
 // Arc ranks [j*per, min(E, (j+1)*per)) of one partition's frontier
 // (F entries (first arc, u) with arc-count prefix sums s), by one block.
 // With cand.list set, improved vertices are also appended to the candidate
-// list (small rounds follow when it stays short).
-template <int WT>
+// list (small rounds follow when it stays short).  O32: 32-bit offsets for
+// the arc and distance accesses (arcs * 8 and n * 4 below 2^32).
+template <int WT, bool O32>
 __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint32_t *__restrict__ dist,
                                            const uint2 *__restrict__ qse, const int32_t *__restrict__ s,
                                            int32_t F, int32_t E, int32_t per, int64_t j,
@@ -217,7 +220,7 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
             const uint2 q = qse[i0 + t];
             sS[t] = s[i0 + t];
             sRow[t] = q.x;
-            sDu[t] = dist[q.y];
+            sDu[t] = *elem<O32>(dist, q.y);
         }
         // sS[cnt] bounds the window's ranks; entries past it are padded with
         // INT32_MAX so that the search below needs no bounds test.
@@ -249,14 +252,17 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
                 }
             }
             uint2 arc[kPushItems];
+            uint32_t du[kPushItems];
 #pragma unroll
-            for (int it = 0; it < kPushItems; ++it)
-                arc[it] = load_arc(padj + sRow[pos[it]] + (uint32_t)(xr[it] - sS[pos[it]]));
+            for (int it = 0; it < kPushItems; ++it) {
+                du[it] = sDu[pos[it]];
+                arc[it] = load_arc(elem<O32>(padj, sRow[pos[it]] + (uint32_t)(xr[it] - sS[pos[it]])));
+            }
             uint32_t nd[kPushItems], cur[kPushItems];
 #pragma unroll
             for (int it = 0; it < kPushItems; ++it) {
-                nd[it] = plus<WT>(sDu[pos[it]], arc[it].y);
-                cur[it] = dist[arc[it].x];
+                nd[it] = plus<WT>(du[it], arc[it].y);
+                cur[it] = *elem<O32>(dist, arc[it].x);
             }
             bool take[kPushItems];
             uint32_t vv[kPushItems];
@@ -264,7 +270,7 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
             for (int it = 0; it < kPushItems; ++it) {
                 take[it] = x0 + it * kBlk < wend && nd[it] < cur[it];
                 vv[it] = arc[it].x;
-                if (take[it]) relax_commit(dist, nflags, arc[it].x, nd[it]);
+                if (take[it]) relax_commit<O32>(dist, nflags, arc[it].x, nd[it]);
             }
             if (cand.list) block_append<kPushItems>(cand, vv, take);
         }
@@ -274,11 +280,11 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
     }
 }
 
-template <int WT, int NP>
+template <int WT, int NP, bool O32>
 __global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
     const int k = (NP == 1) ? 0 : (int)(blockIdx.x % NP);
     const int64_t j = (NP == 1) ? blockIdx.x : blockIdx.x / NP;
-    push_range<WT>(a.padj, a.dist, a.qse[k], a.qs[k], a.F[k], a.E[k], a.per[k], j, a.nflags,
+    push_range<WT, O32>(a.padj, a.dist, a.qse[k], a.qs[k], a.F[k], a.E[k], a.per[k], j, a.nflags,
                    CandOut{nullptr, nullptr, 0});
 }
 
@@ -814,8 +820,8 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
             for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
         } else {
             const int32_t per = (int32_t)max<int64_t>(kMinChunk, ((int64_t)t.Ek + B - 1) / B);
-            push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf,
-                           CandOut{nullptr, nullptr, 0});
+            push_range<WT, false>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf,
+                                  CandOut{nullptr, nullptr, 0});
         }
         if (!grid_sync(ls, (unsigned)G, a.spin_ticks)) break;
         unsigned long long *cn = a.ctl + ((iter + 1) % kCtlSlots) * kSlotWords;
@@ -917,7 +923,7 @@ __device__ __forceinline__ int64_t cand_prefix(const unsigned long long *cnt, in
 // (see run_queued), so one block's share stays bounded.
 constexpr int kLight = 8;
 
-template <int WT>
+template <int WT, bool O32>
 __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, LoopState *ls, const int32_t *sPre) {
     __shared__ int32_t hS[kBlk + 1];
     __shared__ int32_t hStart[kBlk];
@@ -970,17 +976,17 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
             bool take[kLight];
 #pragma unroll
             for (int it = 0; it < kLight; ++it)
-                arc[it] = (light && it < deg) ? load_arc(a.adj + st + it) : make_uint2(0u, 0u);
+                arc[it] = (light && it < deg) ? load_arc(elem<O32>(a.adj, (uint32_t)(st + it))) : make_uint2(0u, 0u);
 #pragma unroll
             for (int it = 0; it < kLight; ++it) {
                 nd[it] = plus<WT>(du, arc[it].y);
-                cur[it] = (light && it < deg) ? a.dist[arc[it].x] : 0u;
+                cur[it] = (light && it < deg) ? *elem<O32>(a.dist, arc[it].x) : 0u;
             }
 #pragma unroll
             for (int it = 0; it < kLight; ++it) {
                 take[it] = light && it < deg && nd[it] < cur[it];
                 vv[it] = arc[it].x;
-                if (take[it]) relax_commit(a.dist, nf, arc[it].x, nd[it]);
+                if (take[it]) relax_commit<O32>(a.dist, nf, arc[it].x, nd[it]);
             }
             block_append<kLight>(co, vv, take);
         }
@@ -1011,19 +1017,19 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
                 uint2 arc[kPushItems];
 #pragma unroll
                 for (int it = 0; it < kPushItems; ++it)
-                    arc[it] = load_arc(a.adj + hStart[pos[it]] + (xr[it] - hS[pos[it]]));
+                    arc[it] = load_arc(elem<O32>(a.adj, (uint32_t)(hStart[pos[it]] + (xr[it] - hS[pos[it]]))));
                 uint32_t nd[kPushItems], cur[kPushItems], vv[kPushItems];
                 bool take[kPushItems];
 #pragma unroll
                 for (int it = 0; it < kPushItems; ++it) {
                     nd[it] = plus<WT>(hDu[pos[it]], arc[it].y);
-                    cur[it] = a.dist[arc[it].x];
+                    cur[it] = *elem<O32>(a.dist, arc[it].x);
                 }
 #pragma unroll
                 for (int it = 0; it < kPushItems; ++it) {
                     take[it] = x0b + (int32_t)threadIdx.x + it * kBlk < H && nd[it] < cur[it];
                     vv[it] = arc[it].x;
-                    if (take[it]) relax_commit(a.dist, nf, arc[it].x, nd[it]);
+                    if (take[it]) relax_commit<O32>(a.dist, nf, arc[it].x, nd[it]);
                 }
                 block_append<kPushItems>(co, vv, take);
             }
@@ -1079,7 +1085,7 @@ __device__ __forceinline__ void step_filter(const PersistArgs &a, int64_t r, con
     }
 }
 
-template <int WT, int NP>
+template <int WT, int NP, bool O32>
 __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
     __shared__ int32_t sPre[kCandRegions + 1];
     __shared__ int sOvf;
@@ -1113,7 +1119,7 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
             if (b == 0 && threadIdx.x < kSlotWords)
                 a.ctl[((r + 2) % kCtlSlots) * kSlotWords + threadIdx.x] = 0ull;
             if (lead) ls->small_rounds += 1ull;
-            small_round<WT>(a, r, ls, sPre);
+            small_round<WT, O32>(a, r, ls, sPre);
             ran = kRanSmall;
             next_r = r + 1;
             next_phase = kPhaseAfterSmall;
@@ -1166,7 +1172,7 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
                                      a.ccount + ((r + 1) % 3) * kCandRegions + region, R};
                     // at least kMinChunk arcs per block: small frontiers use few blocks
                     const int32_t per = (int32_t)max<int64_t>(kMinChunk, ((int64_t)t.Ek + B - 1) / B);
-                    push_range<WT>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf, co);
+                    push_range<WT, O32>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf, co);
                     if (a.small && !app && lead) a.ccount[((r + 1) % 3) * kCandRegions] = (unsigned long long)R + 1ull;
                 }
             }
@@ -1446,6 +1452,11 @@ static inline int grid_for(int64_t items, int per_block, int cap) {
 
 static hipError_t scan_exclusive(const int32_t *in, int64_t len, int32_t *out, int32_t *tmp, hipStream_t st);
 
+// 32-bit byte offsets reach every arc, distance and flag of the graph.
+static inline bool offsets32(const DevGraph &g) {
+    return (uint64_t)std::max(g.m, 1) * sizeof(uint2) < (1ull << 32) && (uint64_t)g.n * sizeof(uint32_t) < (1ull << 32);
+}
+
 static inline int slot_of(int64_t i) { return (int)(((i % kCtlSlots) + kCtlSlots) % kCtlSlots); }
 
 unsigned long long *counters_after(const Frontier &f, int64_t iter) { return f.ctl + slot_of(iter + 1) * kSlotWords; }
@@ -1536,12 +1547,23 @@ hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int
     }
     a.nflags = f.flags[(iter + 1) & 1];
     const int grid = (int)(B * g.np);
-    if (g.np == 1) {
-        if (g.wt == 1) hipLaunchKernelGGL((k_push<1, 1>), dim3(grid), dim3(kBlk), 0, st, a);
-        else hipLaunchKernelGGL((k_push<0, 1>), dim3(grid), dim3(kBlk), 0, st, a);
+    const dim3 gd((unsigned)grid), bd(kBlk);
+    if (offsets32(g)) {
+        if (g.np == 1) {
+            if (g.wt == 1) hipLaunchKernelGGL((k_push<1, 1, true>), gd, bd, 0, st, a);
+            else hipLaunchKernelGGL((k_push<0, 1, true>), gd, bd, 0, st, a);
+        } else {
+            if (g.wt == 1) hipLaunchKernelGGL((k_push<1, kMaxParts, true>), gd, bd, 0, st, a);
+            else hipLaunchKernelGGL((k_push<0, kMaxParts, true>), gd, bd, 0, st, a);
+        }
     } else {
-        if (g.wt == 1) hipLaunchKernelGGL((k_push<1, kMaxParts>), dim3(grid), dim3(kBlk), 0, st, a);
-        else hipLaunchKernelGGL((k_push<0, kMaxParts>), dim3(grid), dim3(kBlk), 0, st, a);
+        if (g.np == 1) {
+            if (g.wt == 1) hipLaunchKernelGGL((k_push<1, 1, false>), gd, bd, 0, st, a);
+            else hipLaunchKernelGGL((k_push<0, 1, false>), gd, bd, 0, st, a);
+        } else {
+            if (g.wt == 1) hipLaunchKernelGGL((k_push<1, kMaxParts, false>), gd, bd, 0, st, a);
+            else hipLaunchKernelGGL((k_push<0, kMaxParts, false>), gd, bd, 0, st, a);
+        }
     }
     return hipGetLastError();
 }
@@ -1826,12 +1848,22 @@ hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, con
     a.phase_log_cap = phase_log_cap;
     const dim3 grid((unsigned)cfg.grid), blk(kBlk);
     if (ev_begin) (void)hipEventRecord(ev_begin, st);
-    if (g.np == 1) {
-        if (g.wt == 1) hipLaunchKernelGGL((k_step<1, 1>), grid, blk, 0, st, a, launch);
-        else hipLaunchKernelGGL((k_step<0, 1>), grid, blk, 0, st, a, launch);
+    if (offsets32(g)) {
+        if (g.np == 1) {
+            if (g.wt == 1) hipLaunchKernelGGL((k_step<1, 1, true>), grid, blk, 0, st, a, launch);
+            else hipLaunchKernelGGL((k_step<0, 1, true>), grid, blk, 0, st, a, launch);
+        } else {
+            if (g.wt == 1) hipLaunchKernelGGL((k_step<1, kMaxParts, true>), grid, blk, 0, st, a, launch);
+            else hipLaunchKernelGGL((k_step<0, kMaxParts, true>), grid, blk, 0, st, a, launch);
+        }
     } else {
-        if (g.wt == 1) hipLaunchKernelGGL((k_step<1, kMaxParts>), grid, blk, 0, st, a, launch);
-        else hipLaunchKernelGGL((k_step<0, kMaxParts>), grid, blk, 0, st, a, launch);
+        if (g.np == 1) {
+            if (g.wt == 1) hipLaunchKernelGGL((k_step<1, 1, false>), grid, blk, 0, st, a, launch);
+            else hipLaunchKernelGGL((k_step<0, 1, false>), grid, blk, 0, st, a, launch);
+        } else {
+            if (g.wt == 1) hipLaunchKernelGGL((k_step<1, kMaxParts, false>), grid, blk, 0, st, a, launch);
+            else hipLaunchKernelGGL((k_step<0, kMaxParts, false>), grid, blk, 0, st, a, launch);
+        }
     }
     if (ev_end) (void)hipEventRecord(ev_end, st);
     return hipGetLastError();
