@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-source batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-queries", type=int, default=1500, help="open-loop queries per load level")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip gr_graph_tune (the graph's untuned AUTO schedule is timed)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one elementwise copy (b = a + 1) of this many MiB and exit: a kernel of "
                          "known traffic, for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -121,6 +123,14 @@ def main():
     stream = torch.cuda.current_stream()
     opts = dict(loop=args.loop, direction=args.direction, layout=args.layout, filter=args.filter, alpha_x16=args.alpha,
                 delta=gr.delta_bits(args.delta, g.wtype) if args.delta > 0 else 0)
+
+    tuned = None
+    explicit = args.loop or args.direction or args.layout or args.filter or args.alpha or args.delta
+    if not args.no_tune and not explicit:
+        # the autotuner picks the AUTO schedule from a few of the workload's sources
+        t0 = time.time()
+        tuned = G.tune(srcs[:4], reps=2, stream=torch.cuda.current_stream())
+        log("tuned schedule: %s (%.1fs)" % (tuned, time.time() - t0))
 
     # m_reached per source (from the GPU result of its first run)
     reached = {}
@@ -183,7 +193,8 @@ def main():
         achieved = alg_bytes / (push_us * 1e-6) / 1e9
         kern = {2: "k_persistent", 3: "k_step"}.get(stats_last["loop"], "k_push")
         loop_name = {1: "host", 2: "persistent", 3: "queued"}.get(stats_last["loop"], "?")
-        traffic = counter_traffic(kern, args.workload, loop_name)
+        layout_name = {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?")
+        traffic = counter_traffic(kern, args.workload, loop_name, layout_name)
         roof = {"kernel": kern, "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -242,7 +253,9 @@ def main():
                    "layout": {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?") if stats_last else None,
                    "loop": {1: "host", 2: "persistent", 3: "queued"}.get(stats_last["loop"], "?") if stats_last else None,
                    "delta": args.delta or None,
-                   "iterations_per_query": iters / max(args.steps, 1)},
+                   "iterations_per_query": iters / max(args.steps, 1),
+                   "tuned": ({k: tuned[k] for k in ("layout", "loop", "dense_ratio", "alpha_x16", "delta", "small",
+                                                   "best_ms", "default_ms", "trials")} if tuned else None)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,
@@ -251,7 +264,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def counter_traffic(kernel, workload, loop):
+def counter_traffic(kernel, workload, loop, layout):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when that summary is for another kernel / workload or the kernel
     sources have changed since the counters were taken."""
@@ -268,7 +281,7 @@ def counter_traffic(kernel, workload, loop):
                   for f in ("gr_kernels.hip", "gr_device.h", "gr_internal.h"))
     if fields.get("kernel_sources_sha256") != hashlib.sha256(src.encode()).hexdigest():
         return None
-    if fields.get("loop") not in (None, loop):
+    if fields.get("loop") not in (None, loop) or fields.get("layout") not in (None, layout):
         return None
     try:
         return int(fields["traffic_bytes_per_launch"])
