@@ -222,6 +222,21 @@ gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsrcs, int32_t
                         gr_tune_result *out);
 
 /*
+ * Breadth-first search from src (Section III-C: the same advance / filter
+ * operators and convergence loop as SSSP, with every arc counting one hop).
+ *   depth_out  device memory for n uint32: the fewest arcs on a path from src,
+ *              GR_DIST_INF_U32 for unreachable vertices, 0 at src.  The stored
+ *              weights are not read (any weight type).
+ * The default direction policy switches to pull when the frontier's out-edges
+ * reach m / 14; pull then scans only the in-arcs of vertices without a depth.
+ * opts as for gr_sssp_ex, except: delta must be 0 / GR_DELTA_OFF, and the
+ * persistent loop is GR_ERR_INVALID_ARG (AUTO runs the queued loop).
+ */
+gr_status gr_bfs(const gr_graph *g, int32_t src, void *depth_out, void *stream);
+gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, void *stream, const gr_sssp_opts *opts,
+                    gr_sssp_stats *stats);
+
+/*
  * k independent SSSP queries on one graph in one batched launch.
  *   srcs      host int32[k], each in [0, n); duplicates allowed
  *   k         1 <= k <= 64

@@ -13,6 +13,7 @@ Exports
 ``certify(g, src, dist)``   O(n+m) certificate that ``dist`` is the
                             shortest-path vector (conditions in ``oracle.c``)
 ``reached_edges(g, dist)``  out-degree sum of reached vertices (TEPS numerator)
+``bfs(g, src)``             textbook FIFO breadth-first search depths (C)
 ``brute``                   tiny-input references written independently in
                             Python: Bellman-Ford, Floyd-Warshall and exhaustive
                             simple-path enumeration
@@ -78,6 +79,7 @@ def _load():
             lib.oracle_certify.argtypes = [i32, vp, vp, vp, ctypes.c_int, i32, vp, vp]
             lib.oracle_reached_edges.argtypes = [i32, vp, ctypes.c_int, vp]
             lib.oracle_reached_edges.restype = ctypes.c_int64
+            lib.oracle_bfs.argtypes = [i32, vp, vp, i32, vp]
             _lib = lib
     return _lib
 
@@ -104,6 +106,16 @@ def dijkstra(g, src: int) -> np.ndarray:
                              out.ctypes.data)
     if rc != 0:
         raise ValueError("oracle_dijkstra failed (%d)" % rc)
+    return out[: g.n]
+
+
+def bfs(g, src: int) -> np.ndarray:
+    """Hop depths from src (uint32; INF_U32 when unreachable); weights are ignored."""
+    lib = _load()
+    ro, col, _ = _arrays(g)
+    out = np.empty(max(g.n, 1), dtype=np.uint32)
+    if lib.oracle_bfs(g.n, ro.ctypes.data, col.ctypes.data, int(src), out.ctypes.data) != 0:
+        raise MemoryError("oracle_bfs allocation failed")
     return out[: g.n]
 
 

@@ -316,3 +316,29 @@ int64_t oracle_reached_edges(int32_t n, const int32_t *ro, int wtype, const uint
         if (dist[v] != INF) s += ro[v + 1] - ro[v];
     return s;
 }
+
+/* Breadth-first search from src (Section III-C names BFS as the other vertex
+ * program on the same operators): depth[v] = fewest arcs on a path src -> v,
+ * 0xFFFFFFFF when v is unreachable.  Textbook FIFO-queue BFS; arc weights are
+ * not read.  Returns 0, or -1 on allocation failure. */
+int oracle_bfs(int32_t n, const int32_t *ro, const int32_t *col, int32_t src, uint32_t *depth) {
+    for (int32_t v = 0; v < n; ++v) depth[v] = INF_U32;
+    if (n == 0) return 0;
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!q) return -1;
+    int32_t head = 0, tail = 0;
+    depth[src] = 0;
+    q[tail++] = src;
+    while (head < tail) {
+        const int32_t u = q[head++];
+        for (int32_t e = ro[u]; e < ro[u + 1]; ++e) {
+            const int32_t v = col[e];
+            if (depth[v] == INF_U32) {
+                depth[v] = depth[u] + 1u;
+                q[tail++] = v;
+            }
+        }
+    }
+    free(q);
+    return 0;
+}

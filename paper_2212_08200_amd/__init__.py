@@ -69,7 +69,7 @@ GR_DIR_ALTERNATE = 3
 
 EXPORTED = [
     "gr_graph_create_csr", "gr_graph_destroy", "gr_graph_info", "gr_graph_tune", "gr_sssp", "gr_sssp_ex",
-    "gr_sssp_batch",
+    "gr_bfs", "gr_bfs_ex", "gr_sssp_batch",
     "gr_server_create", "gr_server_add_graph", "gr_serve_submit", "gr_serve_poll", "gr_server_destroy",
     "gr_status_string", "gr_last_error", "gr_version",
 ]
@@ -149,6 +149,8 @@ def lib():
                 "gr_graph_tune": [vp, vp, i32, i32, vp, P(gr_tune_result)],
                 "gr_sssp": [vp, i32, vp, vp],
                 "gr_sssp_ex": [vp, i32, vp, vp, P(gr_sssp_opts), P(gr_sssp_stats)],
+                "gr_bfs": [vp, i32, vp, vp],
+                "gr_bfs_ex": [vp, i32, vp, vp, P(gr_sssp_opts), P(gr_sssp_stats)],
                 "gr_sssp_batch": [vp, vp, i32, vp, vp],
                 "gr_server_create": [P(vp), ctypes.c_size_t, P(gr_server_config)],
                 "gr_server_add_graph": [vp, vp, P(i32)],
@@ -267,6 +269,19 @@ def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direc
                      timing=timing, filter=filter, barrier_timeout_us=barrier_timeout_us, delta=delta)
     st = gr_sssp_stats()
     _check(lib().gr_sssp_ex(g, int(src), _ptr(dist_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def gr_bfs(g: int, src: int, depth_out, stream=None) -> None:
+    _check(lib().gr_bfs(g, int(src), _ptr(depth_out), _stream(stream)))
+
+
+def gr_bfs_ex(g: int, src: int, depth_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
+              max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0) -> dict:
+    o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
+                     timing=timing, filter=filter)
+    st = gr_sssp_stats()
+    _check(lib().gr_bfs_ex(g, int(src), _ptr(depth_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()
 
 

@@ -832,6 +832,45 @@ extern "C" gr_status gr_sssp(const gr_graph *g, int32_t src, void *dist_out, voi
     return gr_sssp_ex(g, src, dist_out, stream, nullptr, nullptr);
 }
 
+// Breadth-first search: the same operators and loops over a unit-weight view
+// of the graph (weight mode 2: every arc adds one hop, its stored weight is
+// not read).  The default direction rule pulls when the frontier's out-edges
+// reach m / 14 (the ratio of Beamer et al.), where the pull scans only the
+// in-arcs of vertices without a depth yet.
+static constexpr int32_t kBfsAlphaX16 = 16 * 14;
+
+extern "C" gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, void *stream,
+                               const gr_sssp_opts *opts, gr_sssp_stats *stats) {
+    if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
+    if (!depth_out) return fail(GR_ERR_INVALID_ARG, "depth_out is NULL");
+    if (src < 0 || src >= g->plain.n) return fail(GR_ERR_SOURCE_RANGE, "src = %d outside [0, %d)", src, g->plain.n);
+    if (opts && opts->delta && opts->delta != GR_DELTA_OFF)
+        return fail(GR_ERR_INVALID_ARG, "the near-far split does not apply to breadth-first search");
+    gr_sssp_opts o = opts ? *opts : gr_sssp_opts{};
+    o.delta = GR_DELTA_OFF;
+    RunCfg rc;
+    gr_status s = check_opts(g, &o, &rc);
+    if (s != GR_OK) return s;
+    // default: direction-optimising on skewed graphs; bounded-degree graphs
+    // (grids, meshes) never build frontiers large enough to pull and run
+    // push-only, which lets the queued loop use small rounds
+    if (!(opts && opts->alpha_x16 > 0))
+        rc.alpha_x16 = (g->pull && g->max_degree > kSmallMaxDegree) ? kBfsAlphaX16 : 0;
+    int loop = rc.loop == GR_LOOP_AUTO ? GR_LOOP_QUEUED : rc.loop;
+    if (loop == GR_LOOP_PERSISTENT)
+        return fail(GR_ERR_INVALID_ARG, "the device-driven persistent loop runs weighted queries only");
+    DevGraph unit = *rc.dg;
+    unit.wt = 2;
+    rc.dg = &unit;
+    uint32_t *d = static_cast<uint32_t *>(depth_out);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return loop == GR_LOOP_QUEUED ? run_queued(g, src, d, st, rc, stats) : run_host_loop(g, src, d, st, rc, stats);
+}
+
+extern "C" gr_status gr_bfs(const gr_graph *g, int32_t src, void *depth_out, void *stream) {
+    return gr_bfs_ex(g, src, depth_out, stream, nullptr, nullptr);
+}
+
 // ---------------------------------------------------------------------------
 // batched multi-source queries
 

@@ -14,10 +14,14 @@ constexpr int kWin = 256;  // frontier entries staged in LDS per window
 
 // ---------------------------------------------------------------------------
 // (+): uint32 add saturating at INF, or binary32 add (round to nearest even)
-// clamped at FLT_MAX.  A clamped value equals INF and never wins a min.
+// clamped at FLT_MAX, or (WT = 2) one hop.  A clamped value equals INF and
+// never wins a min.
 template <int WT>
 __device__ __forceinline__ uint32_t plus(uint32_t d, uint32_t w) {
-    if constexpr (WT == 0) {
+    if constexpr (WT == 2) {  // unit weights (breadth-first search): the arc weight is not used
+        (void)w;
+        return d == kInfU32 ? kInfU32 : d + 1u;
+    } else if constexpr (WT == 0) {
         uint32_t s = d + w;
         return s < d ? kInfU32 : s;
     } else {

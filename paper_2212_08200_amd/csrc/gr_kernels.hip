@@ -360,11 +360,79 @@ __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict_
     }
 }
 
+// Breadth-first pull (unit weights): a vertex that already has a depth keeps
+// it (depths only shrink from INF once), so only the in-arcs of the block's
+// unreached vertices are scanned -- the saving that makes pull pay in the
+// middle levels.  Their arcs are laid out by an LDS prefix sum over the
+// unreached owners and searched like the push's windows.
+__device__ __forceinline__ void pull_block_bfs(int32_t n, const int32_t *__restrict__ ro_in,
+                                               const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
+                                               const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags,
+                                               int64_t vb) {
+    __shared__ int32_t sPre[kBlk + 1];
+    __shared__ int32_t sStart[kBlk];
+    __shared__ uint32_t sMin[kBlk];
+    const int32_t v0 = (int32_t)(vb * kBlk);
+    const int32_t nv = min(kBlk, n - v0);
+    const int t = threadIdx.x;
+    int32_t deg = 0;
+    if (t < nv && dist[v0 + t] == kInfU32) {
+        sStart[t] = ro_in[v0 + t];
+        deg = ro_in[v0 + t + 1] - sStart[t];
+    }
+    int32_t x[1] = {deg}, tot[1];
+    block_scan<1>(x, tot);
+    sPre[t] = x[0];
+    if (t == 0) sPre[kBlk] = INT32_MAX;
+    sMin[t] = kInfU32;
+    __syncthreads();
+    const int32_t H = tot[0];
+    for (int32_t x0b = 0; x0b < H; x0b += kBlk * kPullItems) {
+        int32_t xr[kPullItems], pos[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) {
+            xr[it] = min(x0b + t + it * kBlk, H - 1);
+            pos[it] = 0;
+        }
+        // owner of each rank: largest p with sPre[p] <= rank (owners without
+        // arcs to scan repeat the next prefix and are never chosen)
+#pragma unroll
+        for (int b = kBlk / 2; b >= 1; b >>= 1) {
+#pragma unroll
+            for (int it = 0; it < kPullItems; ++it) {
+                const int32_t p = pos[it] + b;
+                pos[it] = (sPre[p] <= xr[it]) ? p : pos[it];
+            }
+        }
+        uint2 arc[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) arc[it] = load_arc(adj_in + sStart[pos[it]] + (xr[it] - sPre[pos[it]]));
+        uint8_t fl[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) fl[it] = cflags[arc[it].x];
+        uint32_t du[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) du[it] = fl[it] ? dist[arc[it].x] : kInfU32;
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it)
+            if (x0b + t + it * kBlk < H && du[it] != kInfU32) atomicMin(&sMin[pos[it]], du[it] + 1u);
+    }
+    __syncthreads();
+    if (t < nv) {
+        const uint32_t cand = sMin[t];
+        if (cand < dist[v0 + t]) {
+            dist[v0 + t] = cand;
+            mark(nflags, (uint32_t)(v0 + t));
+        }
+    }
+}
+
 template <int WT>
 __global__ __launch_bounds__(kBlk) void k_pull(int32_t n, const int32_t *__restrict__ ro_in,
                                                const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
                                                const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags) {
-    pull_block<WT>(n, ro_in, adj_in, dist, cflags, nflags, blockIdx.x);
+    if constexpr (WT == 2) pull_block_bfs(n, ro_in, adj_in, dist, cflags, nflags, blockIdx.x);
+    else pull_block<WT>(n, ro_in, adj_in, dist, cflags, nflags, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1160,8 +1228,10 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
                 uint8_t *nf = a.flags[(r + 1) & 1];
                 if (pull) {
                     const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
-                    for (int64_t vb = b; vb < nvb; vb += G)
-                        pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
+                    for (int64_t vb = b; vb < nvb; vb += G) {
+                        if constexpr (WT == 2) pull_block_bfs(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
+                        else pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
+                    }
                 } else {
                     // Candidate appends only when this round cannot improve many
                     // more vertices than the list holds (a too-long list just
@@ -1525,6 +1595,17 @@ hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Fro
     return hipGetLastError();
 }
 
+template <int WT>
+static void push_dispatch(const DevGraph &g, dim3 gd, dim3 bd, hipStream_t st, const PushArgs &a) {
+    if (offsets32(g)) {
+        if (g.np == 1) hipLaunchKernelGGL((k_push<WT, 1, true>), gd, bd, 0, st, a);
+        else hipLaunchKernelGGL((k_push<WT, kMaxParts, true>), gd, bd, 0, st, a);
+    } else {
+        if (g.np == 1) hipLaunchKernelGGL((k_push<WT, 1, false>), gd, bd, 0, st, a);
+        else hipLaunchKernelGGL((k_push<WT, kMaxParts, false>), gd, bd, 0, st, a);
+    }
+}
+
 hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, const FrontierCounts &c,
                        int num_cu, hipStream_t st) {
     const int64_t E = c.Esum();
@@ -1548,22 +1629,10 @@ hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int
     a.nflags = f.flags[(iter + 1) & 1];
     const int grid = (int)(B * g.np);
     const dim3 gd((unsigned)grid), bd(kBlk);
-    if (offsets32(g)) {
-        if (g.np == 1) {
-            if (g.wt == 1) hipLaunchKernelGGL((k_push<1, 1, true>), gd, bd, 0, st, a);
-            else hipLaunchKernelGGL((k_push<0, 1, true>), gd, bd, 0, st, a);
-        } else {
-            if (g.wt == 1) hipLaunchKernelGGL((k_push<1, kMaxParts, true>), gd, bd, 0, st, a);
-            else hipLaunchKernelGGL((k_push<0, kMaxParts, true>), gd, bd, 0, st, a);
-        }
-    } else {
-        if (g.np == 1) {
-            if (g.wt == 1) hipLaunchKernelGGL((k_push<1, 1, false>), gd, bd, 0, st, a);
-            else hipLaunchKernelGGL((k_push<0, 1, false>), gd, bd, 0, st, a);
-        } else {
-            if (g.wt == 1) hipLaunchKernelGGL((k_push<1, kMaxParts, false>), gd, bd, 0, st, a);
-            else hipLaunchKernelGGL((k_push<0, kMaxParts, false>), gd, bd, 0, st, a);
-        }
+    switch (g.wt) {
+        case 1: push_dispatch<1>(g, gd, bd, st, a); break;
+        case 2: push_dispatch<2>(g, gd, bd, st, a); break;
+        default: push_dispatch<0>(g, gd, bd, st, a);
     }
     return hipGetLastError();
 }
@@ -1573,6 +1642,9 @@ hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int
     const int p = (int)(iter & 1), np1 = p ^ 1;
     if (g.wt == 1)
         hipLaunchKernelGGL(k_pull<1>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
+                           f.flags[np1]);
+    else if (g.wt == 2)
+        hipLaunchKernelGGL(k_pull<2>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
                            f.flags[np1]);
     else
         hipLaunchKernelGGL(k_pull<0>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
@@ -1839,6 +1911,17 @@ hipError_t launch_persistent(const DevGraph &g, uint32_t *dist, const Frontier &
     return g.wt == 1 ? coop_launch<1, kMaxParts>(a, cfg.grid, st) : coop_launch<0, kMaxParts>(a, cfg.grid, st);
 }
 
+template <int WT>
+static void step_dispatch(const DevGraph &g, dim3 grid, dim3 blk, hipStream_t st, const PersistArgs &a, int64_t launch) {
+    if (offsets32(g)) {
+        if (g.np == 1) hipLaunchKernelGGL((k_step<WT, 1, true>), grid, blk, 0, st, a, launch);
+        else hipLaunchKernelGGL((k_step<WT, kMaxParts, true>), grid, blk, 0, st, a, launch);
+    } else {
+        if (g.np == 1) hipLaunchKernelGGL((k_step<WT, 1, false>), grid, blk, 0, st, a, launch);
+        else hipLaunchKernelGGL((k_step<WT, kMaxParts, false>), grid, blk, 0, st, a, launch);
+    }
+}
+
 hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, const PersistentCfg &cfg, int64_t launch,
                        int8_t *phase_log, int64_t phase_log_cap, hipEvent_t ev_begin, hipEvent_t ev_end,
                        hipStream_t st) {
@@ -1848,22 +1931,10 @@ hipError_t launch_step(const DevGraph &g, uint32_t *dist, const Frontier &f, con
     a.phase_log_cap = phase_log_cap;
     const dim3 grid((unsigned)cfg.grid), blk(kBlk);
     if (ev_begin) (void)hipEventRecord(ev_begin, st);
-    if (offsets32(g)) {
-        if (g.np == 1) {
-            if (g.wt == 1) hipLaunchKernelGGL((k_step<1, 1, true>), grid, blk, 0, st, a, launch);
-            else hipLaunchKernelGGL((k_step<0, 1, true>), grid, blk, 0, st, a, launch);
-        } else {
-            if (g.wt == 1) hipLaunchKernelGGL((k_step<1, kMaxParts, true>), grid, blk, 0, st, a, launch);
-            else hipLaunchKernelGGL((k_step<0, kMaxParts, true>), grid, blk, 0, st, a, launch);
-        }
-    } else {
-        if (g.np == 1) {
-            if (g.wt == 1) hipLaunchKernelGGL((k_step<1, 1, false>), grid, blk, 0, st, a, launch);
-            else hipLaunchKernelGGL((k_step<0, 1, false>), grid, blk, 0, st, a, launch);
-        } else {
-            if (g.wt == 1) hipLaunchKernelGGL((k_step<1, kMaxParts, false>), grid, blk, 0, st, a, launch);
-            else hipLaunchKernelGGL((k_step<0, kMaxParts, false>), grid, blk, 0, st, a, launch);
-        }
+    switch (g.wt) {
+        case 1: step_dispatch<1>(g, grid, blk, st, a, launch); break;
+        case 2: step_dispatch<2>(g, grid, blk, st, a, launch); break;
+        default: step_dispatch<0>(g, grid, blk, st, a, launch);
     }
     if (ev_end) (void)hipEventRecord(ev_end, st);
     return hipGetLastError();

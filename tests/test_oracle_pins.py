@@ -304,3 +304,47 @@ def test_rmat16_f32_oracle_certified():
     d = oracle.dijkstra(g, s)
     assert oracle.certify(g, s, d)[0] == 0
     np.testing.assert_array_equal(oracle.bsp(g, s)[0], d)
+
+
+# ------------------------------------------------------------------ BFS pins
+
+def _unit(g):
+    """The same arcs with every weight 1 (uint32)."""
+    return gg.CSR(n=g.n, ro=g.ro.copy(), col=g.col.copy(), w=np.ones(g.m, dtype=np.uint32), wtype=gg.W_U32,
+                  name=g.name + "_unit")
+
+
+@pytest.mark.parametrize("side,src", [(7, 0), (12, 5 * 12 + 7), (1, 0)])
+def test_bfs_grid_is_manhattan(side, src):
+    g = gg.grid(side, wseed=3)
+    d = oracle.bfs(g, src)
+    r0, c0 = divmod(src, side)
+    want = np.array([abs(r - r0) + abs(c - c0) for r in range(side) for c in range(side)], dtype=np.uint32)
+    assert np.array_equal(d, want)
+
+
+def test_bfs_directed_path_and_unreachable():
+    g = gg.from_arcs(6, [(0, 1, 7), (1, 2, 7), (2, 3, 7), (5, 4, 1)])
+    d = oracle.bfs(g, 0)
+    assert d.tolist() == [0, 1, 2, 3, oracle.INF_U32, oracle.INF_U32]
+    assert oracle.bfs(g, 3).tolist() == [oracle.INF_U32] * 3 + [0] + [oracle.INF_U32] * 2
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(st.integers(min_value=1, max_value=12), st.integers(min_value=0, max_value=10 ** 6))
+def test_bfs_equals_floyd_warshall_on_unit_weights(n, seed):
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(0, 3 * n + 1))
+    arcs = [(int(rng.integers(0, n)), int(rng.integers(0, n)), int(rng.integers(1, 9))) for _ in range(k)]
+    g = gg.from_arcs(n, arcs)
+    fw = brute.floyd_warshall(_unit(g))
+    for s in range(n):
+        assert np.array_equal(oracle.bfs(g, s), fw[s].astype(np.uint32)), (arcs, s)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_bfs_equals_unit_weight_dijkstra(seed):
+    g = gg.rmat(12, 8, gseed=seed, pseed=seed + 10, wseed=seed + 20)
+    u = _unit(g)
+    for s in gg.pick_sources(g, seed, 3):
+        assert np.array_equal(oracle.bfs(g, int(s)), oracle.dijkstra(u, int(s)))
