@@ -53,6 +53,16 @@ CERTIFY_MUTANTS = {
 }
 
 
+BFS_MUTANTS = {
+    "two_hops_per_arc": ("depth[v] = depth[u] + 1u;", "depth[v] = depth[u] + 2u;"),
+    "revisit_allowed": ("if (depth[v] == INF_U32) {\n                depth[v] = depth[u] + 1u;",
+                        "if (depth[v] >= depth[u]) {\n                depth[v] = depth[u] + 1u;"),
+    "skip_last_arc": ("for (int32_t e = ro[u]; e < ro[u + 1]; ++e) {\n            const int32_t v = col[e];\n            if (depth[v]",
+                      "for (int32_t e = ro[u]; e < ro[u + 1] - 1; ++e) {\n            const int32_t v = col[e];\n            if (depth[v]"),
+    "lifo_order": ("const int32_t u = q[head++];", "const int32_t u = q[--tail];"),
+}
+
+
 def _mutate(text, spec, name):
     pairs = spec if isinstance(spec, list) else [spec]
     for old, new in pairs:
@@ -71,6 +81,7 @@ def _compile(tmp_path, text, tag):
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     lib.oracle_dijkstra.argtypes = [i32, vp, vp, vp, ctypes.c_int, i32, vp]
     lib.oracle_certify.argtypes = [i32, vp, vp, vp, ctypes.c_int, i32, vp, vp]
+    lib.oracle_bfs.argtypes = [i32, vp, vp, i32, vp]
     return lib
 
 
@@ -136,6 +147,29 @@ def dijkstra_pins_fail(lib):
     return failed
 
 
+def _bfs(lib, g, s):
+    ro = np.ascontiguousarray(g.ro, np.int32)
+    col = np.ascontiguousarray(g.col if g.m else np.zeros(1, np.int32), np.int32)
+    out = np.empty(max(g.n, 1), np.uint32)
+    lib.oracle_bfs(g.n, ro.ctypes.data, col.ctypes.data, s, out.ctypes.data)
+    return out[:g.n]
+
+
+def bfs_pins_fail(lib):
+    """BFS pins: grid closed form, Floyd-Warshall on unit weights for tiny graphs."""
+    failed = []
+    g = gg.grid(9, wseed=0)
+    r, c = np.divmod(np.arange(81), 9)
+    if not np.array_equal(_bfs(lib, g, 0), r + c):
+        failed.append("manhattan")
+    for g, s in _tiny_cases()[:150]:
+        unit = gg.CSR(n=g.n, ro=g.ro, col=g.col, w=np.ones(g.m, np.uint32), wtype=gg.W_U32)
+        if not np.array_equal(_bfs(lib, g, s), brute.floyd_warshall(unit)[s].astype(np.uint32)):
+            failed.append("floyd_warshall")
+            break
+    return failed
+
+
 def certify_pins_fail(lib):
     failed = []
     g = gg.from_arcs(4, [(0, 1, 5), (2, 3, 0), (3, 2, 0)])
@@ -179,6 +213,8 @@ def test_unmodified_oracle_passes_battery(tmp_path):
     # the same child-process route the mutants take reports no failure either
     assert _run_battery(tmp_path, open(SRC).read(), "orig_child", "dijkstra") == []
     assert _run_battery(tmp_path, open(SRC).read(), "orig_child2", "certify") == []
+    assert bfs_pins_fail(lib) == []
+    assert _run_battery(tmp_path, open(SRC).read(), "orig_child3", "bfs") == []
 
 
 @pytest.mark.parametrize("name", sorted(DIJKSTRA_MUTANTS))
@@ -193,12 +229,19 @@ def test_certify_mutant_is_caught(tmp_path, name):
     assert _run_battery(tmp_path, text, name, "certify"), "mutant %s survived the pins" % name
 
 
-if __name__ == "__main__":  # child process: python test_oracle_mutants.py <lib.so> <dijkstra|certify>
+@pytest.mark.parametrize("name", sorted(BFS_MUTANTS))
+def test_bfs_mutant_is_caught(tmp_path, name):
+    text = _mutate(open(SRC).read(), BFS_MUTANTS[name], name)
+    assert _run_battery(tmp_path, text, name, "bfs"), "mutant %s survived the pins" % name
+
+
+if __name__ == "__main__":  # child process: python test_oracle_mutants.py <lib.so> <dijkstra|certify|bfs>
     sys.path.insert(0, ROOT)
     _lib = ctypes.CDLL(sys.argv[1])
     _vp, _i32 = ctypes.c_void_p, ctypes.c_int32
     _lib.oracle_dijkstra.argtypes = [_i32, _vp, _vp, _vp, ctypes.c_int, _i32, _vp]
     _lib.oracle_certify.argtypes = [_i32, _vp, _vp, _vp, ctypes.c_int, _i32, _vp, _vp]
-    _failed = dijkstra_pins_fail(_lib) if sys.argv[2] == "dijkstra" else certify_pins_fail(_lib)
+    _lib.oracle_bfs.argtypes = [_i32, _vp, _vp, _i32, _vp]
+    _failed = {"dijkstra": dijkstra_pins_fail, "certify": certify_pins_fail, "bfs": bfs_pins_fail}[sys.argv[2]](_lib)
     print(" ".join(_failed))
     sys.exit(3 if _failed else 0)
