@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--filter", type=int, default=0, help="filter (0 auto, 1 group, 2 streaming member lists)")
     ap.add_argument("--delta", type=float, default=0.0,
                     help="near-far split width in weight units (0: the graph's default)")
+    ap.add_argument("--relax", type=int, default=0,
+                    help="push relaxation filter (0 graph default, 1 pre-read dist, 2 upper-bound array)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-source batched comparison")
@@ -124,10 +126,10 @@ def main():
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
     opts = dict(loop=args.loop, direction=args.direction, layout=args.layout, filter=args.filter, alpha_x16=args.alpha,
-                delta=gr.delta_bits(args.delta, g.wtype) if args.delta > 0 else 0)
+                delta=gr.delta_bits(args.delta, g.wtype) if args.delta > 0 else 0, relax_filter=args.relax)
 
     tuned = None
-    explicit = args.loop or args.direction or args.layout or args.filter or args.alpha or args.delta
+    explicit = args.loop or args.direction or args.layout or args.filter or args.alpha or args.delta or args.relax
     if not args.no_tune and not explicit and not args.bfs:
         # the autotuner picks the AUTO schedule from a few of the workload's sources
         t0 = time.time()
@@ -201,7 +203,8 @@ def main():
         kern = {2: "k_persistent", 3: "k_step"}.get(stats_last["loop"], "k_push")
         loop_name = {1: "host", 2: "persistent", 3: "queued"}.get(stats_last["loop"], "?")
         layout_name = {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?")
-        traffic = counter_traffic(kern, args.workload, loop_name, layout_name)
+        relax_name = {1: "dist", 2: "bound"}.get(stats_last["relax_filter"], "?")
+        traffic = counter_traffic(kern, args.workload, loop_name, layout_name, relax_name)
         roof = {"kernel": kern, "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -261,9 +264,10 @@ def main():
                    "layout": {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?") if stats_last else None,
                    "loop": {1: "host", 2: "persistent", 3: "queued"}.get(stats_last["loop"], "?") if stats_last else None,
                    "delta": args.delta or None,
+                   "relax_filter": {1: "dist", 2: "bound"}.get(stats_last["relax_filter"]) if stats_last else None,
                    "iterations_per_query": iters / max(args.steps, 1),
                    "tuned": ({k: tuned[k] for k in ("layout", "loop", "dense_ratio", "alpha_x16", "delta", "small",
-                                                   "best_ms", "default_ms", "trials")} if tuned else None)},
+                                                   "relax_filter", "best_ms", "default_ms", "trials")} if tuned else None)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,
@@ -272,7 +276,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def counter_traffic(kernel, workload, loop, layout):
+def counter_traffic(kernel, workload, loop, layout, relax):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when that summary is for another kernel / workload or the kernel
     sources have changed since the counters were taken."""
@@ -289,7 +293,7 @@ def counter_traffic(kernel, workload, loop, layout):
                   for f in ("gr_kernels.hip", "gr_device.h", "gr_internal.h"))
     if fields.get("kernel_sources_sha256") != hashlib.sha256(src.encode()).hexdigest():
         return None
-    if fields.get("loop") not in (None, loop) or fields.get("layout") not in (None, layout):
+    if fields.get("loop") != loop or fields.get("layout") != layout or fields.get("relax_filter") != relax:
         return None
     try:
         return int(fields["traffic_bytes_per_launch"])

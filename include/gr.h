@@ -165,7 +165,21 @@ typedef struct {
                            held-back distance (+) delta.  0 = the graph's default (off
                            unless gr_graph_tune chose one); GR_DELTA_OFF = off.  Needs
                            push: GR_DIR_PULL / GR_DIR_ALTERNATE are GR_ERR_INVALID_ARG. */
+    int32_t relax_filter; /* what push compares a candidate distance with before its atomic
+                             min: GR_RELAX_* below.  0 = the graph's default (the bound
+                             array on graphs of maximum out-degree > 64, unless
+                             gr_graph_tune chose otherwise; breadth-first search: dist). */
 } gr_sssp_opts;
+
+/* Relaxation filters of push (gr_sssp_opts.relax_filter).  Either way the
+ * result is the same; only the number of atomic operations differs. */
+#define GR_RELAX_DIST 1  /* read dist[v]; the atomic min's result is not used */
+#define GR_RELAX_BOUND 2 /* read a per-vertex upper bound on dist[v] that push lowers with
+                            plain stores; the atomic returns the old distance, which
+                            decides whether v improved.  The bound stays in the cache of
+                            the die that relaxes v, where dist's own line goes stale as
+                            atomics complete beyond it, so fewer atomics are issued on
+                            graphs where many arcs reach the same vertices. */
 
 #define GR_DELTA_OFF 0xFFFFFFFFu
 
@@ -186,6 +200,7 @@ typedef struct {
     int32_t small_rounds;      /* queued loop: rounds expanded from a candidate list */
     int32_t launches;          /* kernel launches of the loop (queued: including the ones
                                   enqueued past the end, which return at once) */
+    int32_t relax_filter;      /* the GR_RELAX_* push ran with */
 } gr_sssp_stats;
 
 /* gr_sssp with an explicit schedule; opts and stats may be NULL.  stats are
@@ -206,11 +221,12 @@ typedef struct {
     int32_t from_cache;   /* 1 when read from the tuning cache file */
     uint32_t delta;       /* chosen near-far split width (weight-type bits; 0 = off) */
     int32_t small;        /* 1: small rounds (filter 3) in the queued loop */
+    int32_t relax_filter; /* GR_RELAX_DIST or GR_RELAX_BOUND */
 } gr_tune_result;
 
 /*
  * Autotuner: times candidate schedules -- push layout, loop driver, filter
- * threshold, pull threshold, near-far split width -- with a greedy search (one knob at a time, each
+ * threshold, pull threshold, near-far split width, small rounds, relaxation filter -- with a greedy search (one knob at a time, each
  * candidate timed as the median of `reps` queries from srcs[0..nsrcs)), and
  * keeps the fastest as the graph's AUTO configuration.  Every candidate
  * computes the same distances.  When the environment variable GR_TUNE_CACHE

@@ -53,6 +53,8 @@ GR_LOOP_HOST = 1
 GR_LOOP_PERSISTENT = 2
 GR_LOOP_QUEUED = 3
 GR_DELTA_OFF = 0xFFFFFFFF
+GR_RELAX_DIST = 1
+GR_RELAX_BOUND = 2
 
 
 def delta_bits(value, wt) -> int:
@@ -89,7 +91,8 @@ class GrError(RuntimeError):
 class gr_sssp_opts(ctypes.Structure):
     _fields_ = [("loop", ctypes.c_int32), ("direction", ctypes.c_int32), ("alpha_x16", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("layout", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("filter", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32), ("delta", ctypes.c_uint32)]
+                ("filter", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32), ("delta", ctypes.c_uint32),
+                ("relax_filter", ctypes.c_int32)]
 
 
 class gr_sssp_stats(ctypes.Structure):
@@ -98,7 +101,8 @@ class gr_sssp_stats(ctypes.Structure):
                 ("frontier_sum", ctypes.c_int64), ("push_frontier_sum", ctypes.c_int64),
                 ("frontier_max", ctypes.c_int32), ("loop", ctypes.c_int32), ("push_launches", ctypes.c_int32),
                 ("layout", ctypes.c_int32), ("push_us", ctypes.c_double), ("pull_us", ctypes.c_double),
-                ("filter_us", ctypes.c_double), ("small_rounds", ctypes.c_int32), ("launches", ctypes.c_int32)]
+                ("filter_us", ctypes.c_double), ("small_rounds", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("relax_filter", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,7 +112,7 @@ class gr_tune_result(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("loop", ctypes.c_int32), ("dense_ratio", ctypes.c_int32),
                 ("alpha_x16", ctypes.c_int32), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
                 ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("delta", ctypes.c_uint32),
-                ("small", ctypes.c_int32)]
+                ("small", ctypes.c_int32), ("relax_filter", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -263,10 +267,13 @@ def gr_sssp(g: int, src: int, dist_out, stream=None) -> None:
 
 
 def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
-               max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, barrier_timeout_us=0, delta=0) -> dict:
-    """delta: near-far split width as weight-type bits (see delta_bits), 0 = graph default, GR_DELTA_OFF = off."""
+               max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, barrier_timeout_us=0, delta=0,
+               relax_filter=0) -> dict:
+    """delta: near-far split width as weight-type bits (see delta_bits), 0 = graph default, GR_DELTA_OFF = off.
+    relax_filter: GR_RELAX_DIST / GR_RELAX_BOUND, 0 = graph default."""
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
-                     timing=timing, filter=filter, barrier_timeout_us=barrier_timeout_us, delta=delta)
+                     timing=timing, filter=filter, barrier_timeout_us=barrier_timeout_us, delta=delta,
+                     relax_filter=relax_filter)
     st = gr_sssp_stats()
     _check(lib().gr_sssp_ex(g, int(src), _ptr(dist_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()
@@ -277,9 +284,9 @@ def gr_bfs(g: int, src: int, depth_out, stream=None) -> None:
 
 
 def gr_bfs_ex(g: int, src: int, depth_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
-              max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0) -> dict:
+              max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, relax_filter=0) -> dict:
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
-                     timing=timing, filter=filter)
+                     timing=timing, filter=filter, relax_filter=relax_filter)
     st = gr_sssp_stats()
     _check(lib().gr_bfs_ex(g, int(src), _ptr(depth_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()

@@ -156,6 +156,7 @@ struct gr_graph {
     int32_t auto_alpha_x16 = 0;
     uint32_t auto_delta = 0;  // near-far split width (0: off)
     bool auto_small = false;  // queued loop: small rounds
+    int32_t auto_relax = GR_RELAX_DIST;  // push's relaxation filter
     // iterations of the last completed queued-loop query (first chunk size)
     mutable std::atomic<int32_t> last_iters{0};
     double locality = 1.0;  // fraction of arcs with |u - v| < locality_span(n)
@@ -329,6 +330,10 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
     // Small rounds by default where they apply (bounded degree): measured
     // faster on grids and road-like graphs, whose many rounds are small.
     g->auto_small = g->max_degree <= kSmallMaxDegree;
+    // The bound array pays where many arcs reach the same vertices within a
+    // round (skewed degrees: measured faster on R-MAT, slower on road-like
+    // graphs, whose relaxations are mostly first improvements).
+    g->auto_relax = g->max_degree > kSmallMaxDegree ? GR_RELAX_BOUND : GR_RELAX_DIST;
     BUILD_TRY(launch_locality(n, g->d_ro, g->d_adj, locality_span(n), near, st), "locality");
     unsigned long long hnear = 0;
     BUILD_TRY(hipMemcpyAsync(&hnear, near, sizeof hnear, hipMemcpyDeviceToHost, st), "locality");
@@ -453,6 +458,7 @@ struct RunCfg {
     int filter;
     int32_t dense_ratio;
     bool small;      // queued loop: small rounds from candidate lists
+    bool bound;      // push filters relaxations with the upper-bound array
     uint32_t delta;  // near-far split width (weight-type bits); 0 = off
     int64_t barrier_timeout_us;
     const DevGraph *dg;
@@ -485,6 +491,10 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
     if (rc->filter < 0 || rc->filter > 3) return fail(GR_ERR_INVALID_ARG, "unknown filter mode %d", rc->filter);
     rc->small = rc->filter == 3 || (rc->filter == 0 && g->auto_small);
     if (rc->filter == 3) rc->filter = 0;
+    const int32_t relax = (o && o->relax_filter) ? o->relax_filter : g->auto_relax;
+    if (relax != GR_RELAX_DIST && relax != GR_RELAX_BOUND)
+        return fail(GR_ERR_INVALID_ARG, "unknown relax_filter %d", relax);
+    rc->bound = relax == GR_RELAX_BOUND;
     uint32_t d = (o && o->delta) ? o->delta : g->auto_delta;
     if (d == GR_DELTA_OFF) d = 0;
     if (d && g->plain.wt == GR_W_F32) {
@@ -526,9 +536,11 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
     HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
     Frontier f;
     frontier_carve(f, ws, dg);
+    if (!rc.bound) f.bound = nullptr;
     gr_sssp_stats local{};
     local.loop = GR_LOOP_HOST;
     local.layout = rc.layout;
+    local.relax_filter = rc.bound ? GR_RELAX_BOUND : GR_RELAX_DIST;
     gr_status status = GR_OK;
     // Optional per-launch timing: events around the advance and the filter.
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -633,6 +645,7 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
     Frontier f;
     frontier_carve(f, ws, dg);
+    if (!rc.bound) f.bound = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     const bool timed = rc.timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
     hipError_t e = launch_init(dg, dist, src, f, rc.delta ? next_threshold(0u, rc.delta, dg.wt) : kInfU32,
@@ -648,6 +661,7 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     gr_sssp_stats local{};
     local.loop = GR_LOOP_PERSISTENT;
     local.layout = rc.layout;
+    local.relax_filter = rc.bound ? GR_RELAX_BOUND : GR_RELAX_DIST;
     local.iterations = (int32_t)ls.iter;
     local.pull_iterations = (int32_t)ls.pull_iters;
     local.edges_pushed = (int64_t)ls.edges_pushed;
@@ -711,6 +725,7 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
     Frontier f;
     frontier_carve(f, ws, dg);
+    if (!rc.bound) f.bound = nullptr;
     int8_t *plog = nullptr;
     hipEvent_t evc[2] = {nullptr, nullptr};
     hipError_t e = hipSuccess;
@@ -768,6 +783,7 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     gr_sssp_stats local{};
     local.loop = GR_LOOP_QUEUED;
     local.layout = rc.layout;
+    local.relax_filter = rc.bound ? GR_RELAX_BOUND : GR_RELAX_DIST;
     local.iterations = (int32_t)fin.iter;
     local.pull_iterations = (int32_t)fin.pull_iters;
     local.edges_pushed = (int64_t)fin.edges_pushed;
@@ -856,6 +872,8 @@ extern "C" gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, 
     // push-only, which lets the queued loop use small rounds
     if (!(opts && opts->alpha_x16 > 0))
         rc.alpha_x16 = (g->pull && g->max_degree > kSmallMaxDegree) ? kBfsAlphaX16 : 0;
+    // hop counts leave few redundant relaxations: dist unless asked otherwise
+    if (!(opts && opts->relax_filter)) rc.bound = false;
     int loop = rc.loop == GR_LOOP_AUTO ? GR_LOOP_QUEUED : rc.loop;
     if (loop == GR_LOOP_PERSISTENT)
         return fail(GR_ERR_INVALID_ARG, "the device-driven persistent loop runs weighted queries only");
@@ -1159,11 +1177,11 @@ static bool cache_lookup(const std::string &sig, gr_tune_result *r) {
         char s[300];
         int lay, loop, dr, al;
         unsigned dl;
-        int sm;
+        int sm, rf;
         double ms;
         if (sscanf(line, "{\"sig\": \"%299[^\"]\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
-                         "\"delta\": %u, \"small\": %d, \"best_ms\": %lf}",
-                   s, &lay, &loop, &dr, &al, &dl, &sm, &ms) == 8 &&
+                         "\"delta\": %u, \"small\": %d, \"relax_filter\": %d, \"best_ms\": %lf}",
+                   s, &lay, &loop, &dr, &al, &dl, &sm, &rf, &ms) == 9 &&
             sig == s) {
             r->layout = lay;
             r->loop = loop;
@@ -1171,6 +1189,7 @@ static bool cache_lookup(const std::string &sig, gr_tune_result *r) {
             r->alpha_x16 = al;
             r->delta = dl;
             r->small = sm;
+            r->relax_filter = rf;
             r->best_ms = ms;
             found = true;  // the last matching line wins
         }
@@ -1185,8 +1204,8 @@ static void cache_store(const std::string &sig, const gr_tune_result &r) {
     FILE *f = fopen(path, "a");
     if (!f) return;
     fprintf(f, "{\"sig\": \"%s\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
-               "\"delta\": %u, \"small\": %d, \"best_ms\": %.6f}\n",
-            sig.c_str(), r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small, r.best_ms);
+               "\"delta\": %u, \"small\": %d, \"relax_filter\": %d, \"best_ms\": %.6f}\n",
+            sig.c_str(), r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small, r.relax_filter, r.best_ms);
     fclose(f);
 }
 
@@ -1194,6 +1213,7 @@ struct TuneCfg {
     int32_t layout, loop, dense_ratio, alpha_x16;
     uint32_t delta;
     int32_t small;
+    int32_t relax;
 };
 
 static void apply_auto(gr_graph *g, const TuneCfg &c) {
@@ -1203,6 +1223,7 @@ static void apply_auto(gr_graph *g, const TuneCfg &c) {
     g->auto_alpha_x16 = c.alpha_x16;
     g->auto_delta = c.delta;
     g->auto_small = c.small != 0;
+    g->auto_relax = c.relax;
 }
 
 // Near-far split widths to try: multiples of the mean weight of a sample of
@@ -1255,7 +1276,8 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         if (r.layout == GR_LAYOUT_PARTITIONED && !g->has_part) r.layout = GR_LAYOUT_PLAIN;
         if (r.alpha_x16 > 0 && !g->pull) r.alpha_x16 = 0;
         if (r.delta) r.alpha_x16 = 0;
-        apply_auto(g, TuneCfg{r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small});
+        if (r.relax_filter != GR_RELAX_BOUND) r.relax_filter = GR_RELAX_DIST;
+        apply_auto(g, TuneCfg{r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small, r.relax_filter});
         r.from_cache = 1;
         if (out) *out = r;
         return GR_OK;
@@ -1273,6 +1295,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         o.direction = c.alpha_x16 > 0 ? GR_DIR_AUTO : GR_DIR_PUSH;
         o.delta = c.delta ? c.delta : GR_DELTA_OFF;
         o.filter = c.small ? 3 : 0;
+        o.relax_filter = c.relax;
         const int32_t saved = g->auto_dense_ratio;
         g->auto_dense_ratio = c.dense_ratio;
         std::vector<double> t;
@@ -1295,7 +1318,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         return GR_OK;
     };
     TuneCfg best{g->auto_layout, g->auto_loop, g->auto_dense_ratio, g->auto_alpha_x16, g->auto_delta,
-                 g->auto_small ? 1 : 0};
+                 g->auto_small ? 1 : 0, g->auto_relax};
     double best_ms = 0;
     status = measure(best, &best_ms);
     const double default_ms = best_ms;
@@ -1318,6 +1341,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         knobs.push_back({4, ds});
     }
     if (g->max_degree <= kSmallMaxDegree) knobs.push_back({5, {0, 1}});
+    knobs.push_back({6, {GR_RELAX_DIST, GR_RELAX_BOUND}});
     for (const auto &kv : knobs) {
         for (int32_t v : kv.second) {
             if (status != GR_OK) break;
@@ -1329,6 +1353,9 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
             } else if (kv.first == 5) {
                 if (c.small == v || c.loop != GR_LOOP_QUEUED || c.delta) continue;
                 c.small = v;
+            } else if (kv.first == 6) {
+                if (c.relax == v) continue;
+                c.relax = v;
             } else if (kv.first == 3 && c.delta) {
                 continue;
             } else {
@@ -1355,6 +1382,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
     r.alpha_x16 = best.alpha_x16;
     r.delta = best.delta;
     r.small = best.small;
+    r.relax_filter = best.relax;
     r.best_ms = best_ms;
     r.default_ms = default_ms;
     r.trials = trials;

@@ -206,6 +206,7 @@ void batch_carve(BatchWs &w, void *base, const DevGraph &g) {
     f.cand_cap = 0;
     f.ccount = nullptr;
     f.rstat = nullptr;
+    f.bound = nullptr;
     for (int i = 0; i < 2; ++i) {
         f.flags[i] = reinterpret_cast<uint8_t *>(p);
         p += align256((size_t)nv);

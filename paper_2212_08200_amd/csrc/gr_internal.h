@@ -74,6 +74,7 @@ struct Frontier {
     int32_t *cand[2];  // candidate lists of the small rounds (queued loop)
     unsigned long long *ccount;  // their counters: 3 rounds x kCandRegions
     unsigned long long *rstat;   // small-round statistics (kStatWords)
+    uint32_t *bound;             // per-vertex upper bound on dist that filters relaxations (see relax_bound)
     int32_t cand_cap;
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];

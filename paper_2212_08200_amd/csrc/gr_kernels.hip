@@ -59,6 +59,29 @@ __device__ __forceinline__ void relax_commit(uint32_t *dist, uint8_t *nflags, ui
     mark<O32>(nflags, v);
 }
 
+// Relaxation filter with the bound array: the pre-read comes from `bound`, a
+// per-vertex upper bound on dist lowered by plain stores.  Every value stored
+// there was the new minimum of an atomic that returned a larger old value, and
+// dist never rises within a query, so dist <= bound holds throughout and a
+// candidate not below the bound is safely dropped.  The atomic returns the old
+// distance, so a vertex is marked (and its bound lowered) exactly when this
+// relaxation lowered it.  Within a round a vertex's bound line stays in the L2
+// of the die that relaxes it (the partitioned layout sends all arcs into one
+// destination range to one XCD), while dist's line there goes stale as the
+// atomics complete beyond the L2: the bound filters out most of the atomics
+// that a stale dist pre-read lets through.  Stale bound values are larger,
+// never wrong.
+template <bool O32>
+__device__ __forceinline__ bool relax_bound(uint32_t *dist, uint32_t *bound, uint8_t *nflags, uint32_t v, uint32_t nd,
+                                           uint32_t old) {
+    if (nd < old) {
+        *elem<O32>(bound, v) = nd;
+        mark<O32>(nflags, v);
+        return true;
+    }
+    return false;
+}
+
 // ---------------------------------------------------------------------------
 // init: dist, bitmaps, summaries, counters and the one-vertex frontier.
 
@@ -72,6 +95,7 @@ struct InitArgs {
     uint8_t *flags0, *flags1;
     uint8_t *far0, *far1;  // NULL when the near-far split is off
     unsigned long long *ccount;  // candidate-list counters (queued loop), NULL if absent
+    uint32_t *bound;             // relaxation filter (see relax_bound), NULL if off
     unsigned long long *rstat;   // small-round statistics, NULL if absent
     int64_t nflag;  // bytes per flag array (multiple of 16)
     uint2 *qse[kMaxParts];
@@ -84,7 +108,10 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int32_t src = a.src;
-    for (int64_t v = tid; v < a.n; v += stride) a.dist[v] = (v == src) ? 0u : a.inf;
+    for (int64_t v = tid; v < a.n; v += stride) {
+        a.dist[v] = (v == src) ? 0u : a.inf;
+        if (a.bound) a.bound[v] = (v == src) ? 0u : a.inf;
+    }
     const int64_t sw = src >> 4;
     for (int64_t w = tid; w < a.nflag / 16; w += stride) {
         uint4 z = make_uint4(0u, 0u, 0u, 0u);
@@ -139,6 +166,7 @@ struct PushArgs {
     int32_t E[kMaxParts];
     int32_t per[kMaxParts];
     uint8_t *nflags;
+    uint32_t *bound;  // relaxation filter (NULL: pre-read dist)
 };
 
 // Candidate list of the small-frontier rounds: the vertices a round
@@ -199,7 +227,7 @@ template <int WT, bool O32>
 __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint32_t *__restrict__ dist,
                                            const uint2 *__restrict__ qse, const int32_t *__restrict__ s,
                                            int32_t F, int32_t E, int32_t per, int64_t j,
-                                           uint8_t *__restrict__ nflags, const CandOut &cand) {
+                                           uint8_t *__restrict__ nflags, const CandOut &cand, uint32_t *bound) {
     __shared__ int32_t sS[kWin + 1];
     __shared__ uint32_t sRow[kWin];
     __shared__ uint32_t sDu[kWin];
@@ -262,15 +290,30 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
 #pragma unroll
             for (int it = 0; it < kPushItems; ++it) {
                 nd[it] = plus<WT>(du[it], arc[it].y);
-                cur[it] = *elem<O32>(dist, arc[it].x);
+                cur[it] = *elem<O32>(bound ? bound : dist, arc[it].x);
             }
             bool take[kPushItems];
             uint32_t vv[kPushItems];
+            if (bound) {
+                uint32_t old[kPushItems];
 #pragma unroll
-            for (int it = 0; it < kPushItems; ++it) {
-                take[it] = x0 + it * kBlk < wend && nd[it] < cur[it];
-                vv[it] = arc[it].x;
-                if (take[it]) relax_commit<O32>(dist, nflags, arc[it].x, nd[it]);
+                for (int it = 0; it < kPushItems; ++it) {
+                    take[it] = x0 + it * kBlk < wend && nd[it] < cur[it];
+                    vv[it] = arc[it].x;
+                    old[it] = take[it] ? __hip_atomic_fetch_min(elem<O32>(dist, arc[it].x), nd[it], __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT)
+                                       : 0u;
+                }
+#pragma unroll
+                for (int it = 0; it < kPushItems; ++it)
+                    take[it] = take[it] && relax_bound<O32>(dist, bound, nflags, arc[it].x, nd[it], old[it]);
+            } else {
+#pragma unroll
+                for (int it = 0; it < kPushItems; ++it) {
+                    take[it] = x0 + it * kBlk < wend && nd[it] < cur[it];
+                    vv[it] = arc[it].x;
+                    if (take[it]) relax_commit<O32>(dist, nflags, arc[it].x, nd[it]);
+                }
             }
             if (cand.list) block_append<kPushItems>(cand, vv, take);
         }
@@ -285,7 +328,7 @@ __global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
     const int k = (NP == 1) ? 0 : (int)(blockIdx.x % NP);
     const int64_t j = (NP == 1) ? blockIdx.x : blockIdx.x / NP;
     push_range<WT, O32>(a.padj, a.dist, a.qse[k], a.qs[k], a.F[k], a.E[k], a.per[k], j, a.nflags,
-                   CandOut{nullptr, nullptr, 0});
+                        CandOut{nullptr, nullptr, 0}, a.bound);
 }
 
 // ---------------------------------------------------------------------------
@@ -811,6 +854,7 @@ struct PersistArgs {
     int32_t *cand[2];
     unsigned long long *ccount;  // 3 rounds x kCandRegions
     unsigned long long *rstat;   // small-round statistics by region (see kStat*)
+    uint32_t *bound;             // relaxation filter (NULL: pre-read dist)
     int32_t cand_region;
     int32_t small;
     int8_t *phase_log;  // timing: phase each launch ran (NULL: off)
@@ -889,7 +933,7 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
         } else {
             const int32_t per = (int32_t)max<int64_t>(kMinChunk, ((int64_t)t.Ek + B - 1) / B);
             push_range<WT, false>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf,
-                                  CandOut{nullptr, nullptr, 0});
+                                  CandOut{nullptr, nullptr, 0}, a.bound);
         }
         if (!grid_sync(ls, (unsigned)G, a.spin_ticks)) break;
         unsigned long long *cn = a.ctl + ((iter + 1) % kCtlSlots) * kSlotWords;
@@ -1242,7 +1286,8 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
                                      a.ccount + ((r + 1) % 3) * kCandRegions + region, R};
                     // at least kMinChunk arcs per block: small frontiers use few blocks
                     const int32_t per = (int32_t)max<int64_t>(kMinChunk, ((int64_t)t.Ek + B - 1) / B);
-                    push_range<WT, O32>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf, co);
+                    push_range<WT, O32>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf, co,
+                                        a.bound);
                     if (a.small && !app && lead) a.ccount[((r + 1) % 3) * kCandRegions] = (unsigned long long)R + 1ull;
                 }
             }
@@ -1581,6 +1626,7 @@ hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Fro
     a.flags1 = f.flags[1];
     a.ccount = f.ccount;
     a.rstat = f.rstat;
+    a.bound = f.bound;
     a.far0 = use_far ? f.far[0] : nullptr;
     a.far1 = use_far ? f.far[1] : nullptr;
     a.threshold = threshold;
@@ -1627,6 +1673,7 @@ hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int
         if (a.per[k] < 1) a.per[k] = 1;
     }
     a.nflags = f.flags[(iter + 1) & 1];
+    a.bound = f.bound;
     const int grid = (int)(B * g.np);
     const dim3 gd((unsigned)grid), bd(kBlk);
     switch (g.wt) {
@@ -1884,6 +1931,7 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     a.cand[1] = f.cand[1];
     a.ccount = f.ccount;
     a.rstat = f.rstat;
+    a.bound = f.bound;
     a.cand_region = f.cand_cap / kCandRegions;
     a.small = cfg.small && f.cand[0] != nullptr ? 1 : 0;
     a.phase_log = nullptr;
@@ -1958,6 +2006,7 @@ size_t frontier_bytes(const DevGraph &g) {
     b += 2 * align256(sizeof(int32_t) * (size_t)cand_capacity(g.n));
     b += align256(sizeof(unsigned long long) * 3 * kCandRegions);
     b += align256(sizeof(unsigned long long) * kStatWords);
+    b += align256(sizeof(uint32_t) * (size_t)std::max(g.n, 1));  // bound
     for (int k = 0; k < g.np; ++k) {
         const size_t c = (size_t)(g.cap[k] > 0 ? g.cap[k] : 1);
         b += align256(c * 8) + align256(c * 4);
@@ -1989,6 +2038,8 @@ void frontier_carve(Frontier &f, void *base, const DevGraph &g) {
     p += align256(sizeof(unsigned long long) * 3 * kCandRegions);
     f.rstat = reinterpret_cast<unsigned long long *>(p);
     p += align256(sizeof(unsigned long long) * kStatWords);
+    f.bound = reinterpret_cast<uint32_t *>(p);
+    p += align256(sizeof(uint32_t) * (size_t)std::max(g.n, 1));
     for (int k = 0; k < kMaxParts; ++k) {
         f.qse[k] = nullptr;
         f.qs[k] = nullptr;

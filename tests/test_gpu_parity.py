@@ -23,10 +23,10 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run(G, src, direction=0, loop=0, n=None, layout=0, filt=0, delta=0):
+def run(G, src, direction=0, loop=0, n=None, layout=0, filt=0, delta=0, relax=0):
     dist = torch.full((n or G.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
     st = gr.gr_sssp_ex(G.handle, int(src), dist, direction=direction, loop=loop, layout=layout, filter=filt,
-                       delta=delta)
+                       delta=delta, relax_filter=relax)
     torch.cuda.synchronize()
     return dist.cpu().numpy().view(np.uint32), st
 
@@ -40,12 +40,14 @@ def assert_same(got, want, tag):
 
 
 LOOPS = {"host": 1, "persistent": 2, "queued": 3}
+RELAX = (gr.GR_RELAX_DIST, gr.GR_RELAX_BOUND)
 
 
 def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate"), flags=gr.GR_FORCE_PARTITION,
                    loops=("host", "persistent", "queued")):
-    """Every direction policy, with both push layouts (plain CSR and partitioned)
-    and every loop driver (host-driven, device-driven persistent, queued)."""
+    """Every direction policy, with both push layouts (plain CSR and partitioned),
+    every loop driver (host-driven, device-driven persistent, queued) and both
+    relaxation filters of push."""
     G = gr.Graph.from_csr(g, flags=flags)
     info = G.info()
     layouts = [gr.GR_LAYOUT_PLAIN] + ([gr.GR_LAYOUT_PARTITIONED] if info["partitions"] > 1 else [])
@@ -59,10 +61,13 @@ def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate"), fla
                     if d == "pull" and lay != layouts[0]:
                         continue  # pull does not use the push layout
                     for lp in loops:
-                        say("case %s src=%d dir=%s layout=%d loop=%s n=%d m=%d" % (tag, s, d, lay, lp, g.n, g.m))
-                        got, st = run(G, s, DIRS[d], layout=lay, loop=LOOPS[lp])
-                        assert_same(got, want, "%s src %d dir %s layout %d loop %s" % (tag, s, d, lay, lp))
-                        assert st["loop"] == LOOPS[lp]
+                        for rf in RELAX if d != "pull" else RELAX[:1]:
+                            say("case %s src=%d dir=%s layout=%d loop=%s relax=%d n=%d m=%d" % (
+                                tag, s, d, lay, lp, rf, g.n, g.m))
+                            got, st = run(G, s, DIRS[d], layout=lay, loop=LOOPS[lp], relax=rf)
+                            assert_same(got, want, "%s src %d dir %s layout %d loop %s relax %d" % (
+                                tag, s, d, lay, lp, rf))
+                            assert st["loop"] == LOOPS[lp]
     finally:
         G.close()
 
@@ -212,6 +217,10 @@ def test_errors_on_gpu():
         with pytest.raises(gr.GrError) as ei:
             gr.gr_sssp_ex(G.handle, 0, dist, loop=4)
         assert ei.value.status == gr.GR_ERR_INVALID_ARG
+        for rf in (-1, 3):
+            with pytest.raises(gr.GrError) as ei:
+                gr.gr_sssp_ex(G.handle, 0, dist, relax_filter=rf)
+            assert ei.value.status == gr.GR_ERR_INVALID_ARG
     finally:
         G.close()
     Gp = gr.Graph.from_csr(g, flags=gr.GR_NO_PULL)
@@ -313,9 +322,11 @@ def test_near_far_split_all_loops_filters(wtype):
                     for lay in layouts:
                         for lp in ("host", "persistent", "queued"):
                             for filt in (0, 1, 2):
-                                say("near-far %s w%d src=%d delta=%#x layout=%d loop=%s filter=%d" % (
-                                    tag, wtype, s, d, lay, lp, filt))
-                                got, st = run(G, s, DIRS["push"], layout=lay, loop=LOOPS[lp], filt=filt, delta=d)
+                                rf = RELAX[filt % 2]
+                                say("near-far %s w%d src=%d delta=%#x layout=%d loop=%s filter=%d relax=%d" % (
+                                    tag, wtype, s, d, lay, lp, filt, rf))
+                                got, st = run(G, s, DIRS["push"], layout=lay, loop=LOOPS[lp], filt=filt, delta=d,
+                                              relax=rf)
                                 assert_same(got, want, "near-far %s delta %#x layout %d loop %s filter %d" % (
                                     tag, d, lay, lp, filt))
         finally:
@@ -386,10 +397,10 @@ def test_small_rounds_thread_and_block_mapped():
         try:
             for s in gg.pick_sources(g, 30, 2):
                 want = oracle.dijkstra(g, int(s))
-                for filt in (3, 0, 1, 2):
-                    say("small rounds %s src=%d filter=%d" % (tag, s, filt))
-                    got, st = run(G, s, DIRS["push"], loop=LOOPS["queued"], filt=filt)
-                    assert_same(got, want, "%s src %d filter %d" % (tag, s, filt))
+                for filt, rf in ((3, 1), (3, 2), (0, 0), (1, 2), (2, 1)):
+                    say("small rounds %s src=%d filter=%d relax=%d" % (tag, s, filt, rf))
+                    got, st = run(G, s, DIRS["push"], loop=LOOPS["queued"], filt=filt, relax=rf)
+                    assert_same(got, want, "%s src %d filter %d relax %d" % (tag, s, filt, rf))
                     if filt in (1, 2):
                         assert st["small_rounds"] == 0
                     elif tag.startswith("grid"):  # bounded degree: small rounds by default too
