@@ -174,12 +174,12 @@ typedef struct {
 /* Relaxation filters of push (gr_sssp_opts.relax_filter).  Either way the
  * result is the same; only the number of atomic operations differs. */
 #define GR_RELAX_DIST 1  /* read dist[v]; the atomic min's result is not used */
-#define GR_RELAX_BOUND 2 /* read a per-vertex upper bound on dist[v] that push lowers with
-                            plain stores; the atomic returns the old distance, which
-                            decides whether v improved.  The bound stays in the cache of
-                            the die that relaxes v, where dist's own line goes stale as
-                            atomics complete beyond it, so fewer atomics are issued on
-                            graphs where many arcs reach the same vertices. */
+#define GR_RELAX_BOUND 2 /* read a per-vertex upper bound on dist[v] that push keeps with
+                            plain stores of the candidates it sends to the atomic min.
+                            The bound stays current in the cache of the die that relaxes
+                            v, and the pre-reads stay off the lines that the atomics are
+                            updating; faster on skewed graphs, slower on road-like ones.
+                            Costs 4 bytes per vertex of query workspace. */
 
 #define GR_DELTA_OFF 0xFFFFFFFFu
 

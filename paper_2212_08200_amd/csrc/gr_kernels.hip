@@ -60,26 +60,25 @@ __device__ __forceinline__ void relax_commit(uint32_t *dist, uint8_t *nflags, ui
 }
 
 // Relaxation filter with the bound array: the pre-read comes from `bound`, a
-// per-vertex upper bound on dist lowered by plain stores.  Every value stored
-// there was the new minimum of an atomic that returned a larger old value, and
-// dist never rises within a query, so dist <= bound holds throughout and a
-// candidate not below the bound is safely dropped.  The atomic returns the old
-// distance, so a vertex is marked (and its bound lowered) exactly when this
-// relaxation lowered it.  Within a round a vertex's bound line stays in the L2
-// of the die that relaxes it (the partitioned layout sends all arcs into one
-// destination range to one XCD), while dist's line there goes stale as the
-// atomics complete beyond the L2: the bound filters out most of the atomics
-// that a stale dist pre-read lets through.  Stale bound values are larger,
-// never wrong.
+// per-vertex upper bound on dist kept with plain stores.  A relaxation that
+// passes it issues its atomic min and then stores its candidate into the
+// bound: once that atomic has executed (at the latest when the launch ends)
+// dist <= candidate, and dist never rises within a query, so every value the
+// bound has held is an upper bound on dist by the end of the launch that
+// wrote it, and a candidate not below the value read can be dropped.  Racing
+// stores may leave a larger candidate than another one that passed: still an
+// upper bound.  Every issuer marks its vertex, so every decrease of dist is
+// marked.  Within a round a vertex's bound line stays in the L2 of the die
+// that relaxes it (the partitioned layout sends all arcs into one destination
+// range to one XCD) and is kept current there by the stores, and the
+// pre-reads no longer touch the lines that the atomics (executed beyond the
+// L2) are working on.  Measured on R-MAT graphs: the same number of atomics
+// and L2 hits, 10-25% less time per query; slower on road-like graphs.
 template <bool O32>
-__device__ __forceinline__ bool relax_bound(uint32_t *dist, uint32_t *bound, uint8_t *nflags, uint32_t v, uint32_t nd,
-                                           uint32_t old) {
-    if (nd < old) {
-        *elem<O32>(bound, v) = nd;
-        mark<O32>(nflags, v);
-        return true;
-    }
-    return false;
+__device__ __forceinline__ void relax_bound(uint32_t *dist, uint32_t *bound, uint8_t *nflags, uint32_t v,
+                                            uint32_t nd) {
+    relax_commit<O32>(dist, nflags, v, nd);
+    *elem<O32>(bound, v) = nd;
 }
 
 // ---------------------------------------------------------------------------
@@ -294,19 +293,13 @@ __device__ __forceinline__ void push_range(const uint2 *__restrict__ padj, uint3
             }
             bool take[kPushItems];
             uint32_t vv[kPushItems];
-            if (bound) {
-                uint32_t old[kPushItems];
+            if (bound) {  // two loops: a branch inside the unrolled one measured 5% slower
 #pragma unroll
                 for (int it = 0; it < kPushItems; ++it) {
                     take[it] = x0 + it * kBlk < wend && nd[it] < cur[it];
                     vv[it] = arc[it].x;
-                    old[it] = take[it] ? __hip_atomic_fetch_min(elem<O32>(dist, arc[it].x), nd[it], __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT)
-                                       : 0u;
+                    if (take[it]) relax_bound<O32>(dist, bound, nflags, arc[it].x, nd[it]);
                 }
-#pragma unroll
-                for (int it = 0; it < kPushItems; ++it)
-                    take[it] = take[it] && relax_bound<O32>(dist, bound, nflags, arc[it].x, nd[it], old[it]);
             } else {
 #pragma unroll
                 for (int it = 0; it < kPushItems; ++it) {
@@ -344,7 +337,7 @@ template <int WT>
 __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict__ ro_in,
                                            const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
                                            const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags,
-                                           int64_t vb) {
+                                           uint32_t *__restrict__ bound, int64_t vb) {
     __shared__ int32_t sOff[kBlk + 1];
     __shared__ uint32_t sMin[kBlk];
     const int32_t v0 = (int32_t)(vb * kBlk);
@@ -398,6 +391,7 @@ __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict_
         const uint32_t cur = dist[v];
         if (cand < cur) {
             dist[v] = cand;
+            if (bound) bound[v] = cand;  // keeps push's relaxation filter tight
             mark(nflags, (uint32_t)v);
         }
     }
@@ -411,7 +405,7 @@ __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict_
 __device__ __forceinline__ void pull_block_bfs(int32_t n, const int32_t *__restrict__ ro_in,
                                                const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
                                                const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags,
-                                               int64_t vb) {
+                                               uint32_t *__restrict__ bound, int64_t vb) {
     __shared__ int32_t sPre[kBlk + 1];
     __shared__ int32_t sStart[kBlk];
     __shared__ uint32_t sMin[kBlk];
@@ -465,6 +459,7 @@ __device__ __forceinline__ void pull_block_bfs(int32_t n, const int32_t *__restr
         const uint32_t cand = sMin[t];
         if (cand < dist[v0 + t]) {
             dist[v0 + t] = cand;
+            if (bound) bound[v0 + t] = cand;
             mark(nflags, (uint32_t)(v0 + t));
         }
     }
@@ -473,9 +468,10 @@ __device__ __forceinline__ void pull_block_bfs(int32_t n, const int32_t *__restr
 template <int WT>
 __global__ __launch_bounds__(kBlk) void k_pull(int32_t n, const int32_t *__restrict__ ro_in,
                                                const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
-                                               const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags) {
-    if constexpr (WT == 2) pull_block_bfs(n, ro_in, adj_in, dist, cflags, nflags, blockIdx.x);
-    else pull_block<WT>(n, ro_in, adj_in, dist, cflags, nflags, blockIdx.x);
+                                               const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags,
+                                               uint32_t *__restrict__ bound) {
+    if constexpr (WT == 2) pull_block_bfs(n, ro_in, adj_in, dist, cflags, nflags, bound, blockIdx.x);
+    else pull_block<WT>(n, ro_in, adj_in, dist, cflags, nflags, bound, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -929,7 +925,7 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (pull) {
             const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
-            for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
+            for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, a.bound, vb);
         } else {
             const int32_t per = (int32_t)max<int64_t>(kMinChunk, ((int64_t)t.Ek + B - 1) / B);
             push_range<WT, false>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf,
@@ -1092,13 +1088,18 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
 #pragma unroll
             for (int it = 0; it < kLight; ++it) {
                 nd[it] = plus<WT>(du, arc[it].y);
-                cur[it] = (light && it < deg) ? *elem<O32>(a.dist, arc[it].x) : 0u;
+                cur[it] = (light && it < deg) ? *elem<O32>(a.bound ? a.bound : a.dist, arc[it].x) : 0u;
             }
 #pragma unroll
             for (int it = 0; it < kLight; ++it) {
                 take[it] = light && it < deg && nd[it] < cur[it];
                 vv[it] = arc[it].x;
-                if (take[it]) relax_commit<O32>(a.dist, nf, arc[it].x, nd[it]);
+                if (take[it]) {
+                    if (a.bound)
+                        relax_bound<O32>(a.dist, a.bound, nf, arc[it].x, nd[it]);
+                    else
+                        relax_commit<O32>(a.dist, nf, arc[it].x, nd[it]);
+                }
             }
             block_append<kLight>(co, vv, take);
         }
@@ -1135,13 +1136,18 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
 #pragma unroll
                 for (int it = 0; it < kPushItems; ++it) {
                     nd[it] = plus<WT>(hDu[pos[it]], arc[it].y);
-                    cur[it] = *elem<O32>(a.dist, arc[it].x);
+                    cur[it] = *elem<O32>(a.bound ? a.bound : a.dist, arc[it].x);
                 }
 #pragma unroll
                 for (int it = 0; it < kPushItems; ++it) {
                     take[it] = x0b + (int32_t)threadIdx.x + it * kBlk < H && nd[it] < cur[it];
                     vv[it] = arc[it].x;
-                    if (take[it]) relax_commit<O32>(a.dist, nf, arc[it].x, nd[it]);
+                    if (take[it]) {
+                        if (a.bound)
+                            relax_bound<O32>(a.dist, a.bound, nf, arc[it].x, nd[it]);
+                        else
+                            relax_commit<O32>(a.dist, nf, arc[it].x, nd[it]);
+                    }
                 }
                 block_append<kPushItems>(co, vv, take);
             }
@@ -1273,8 +1279,8 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
                 if (pull) {
                     const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
                     for (int64_t vb = b; vb < nvb; vb += G) {
-                        if constexpr (WT == 2) pull_block_bfs(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
-                        else pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, vb);
+                        if constexpr (WT == 2) pull_block_bfs(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, a.bound, vb);
+                        else pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, a.bound, vb);
                     }
                 } else {
                     // Candidate appends only when this round cannot improve many
@@ -1689,13 +1695,13 @@ hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int
     const int p = (int)(iter & 1), np1 = p ^ 1;
     if (g.wt == 1)
         hipLaunchKernelGGL(k_pull<1>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
-                           f.flags[np1]);
+                           f.flags[np1], f.bound);
     else if (g.wt == 2)
         hipLaunchKernelGGL(k_pull<2>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
-                           f.flags[np1]);
+                           f.flags[np1], f.bound);
     else
         hipLaunchKernelGGL(k_pull<0>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
-                           f.flags[np1]);
+                           f.flags[np1], f.bound);
     return hipGetLastError();
 }
 
