@@ -63,7 +63,8 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--layout", type=int, default=0, help="gr_layout (0 auto, 1 plain, 2 partitioned)")
     ap.add_argument("--direction", type=int, default=0, help="gr_direction (0 auto, 1 push, 2 pull)")
-    ap.add_argument("--loop", type=int, default=0, help="gr_loop_mode (0 auto, 1 host, 2 persistent, 3 queued)")
+    ap.add_argument("--loop", type=int, default=0,
+                    help="gr_loop_mode (0 auto, 1 host, 2 persistent, 3 queued, 4 asynchronous)")
     ap.add_argument("--alpha", type=int, default=0,
                     help="direction switch: pull when frontier out-edges * alpha / 16 >= m (0: graph default)")
     ap.add_argument("--filter", type=int, default=0, help="filter (0 auto, 1 group, 2 streaming member lists)")
@@ -200,8 +201,8 @@ def main():
     roof = None
     if launches and push_us > 0:
         achieved = alg_bytes / (push_us * 1e-6) / 1e9
-        kern = {2: "k_persistent", 3: "k_step"}.get(stats_last["loop"], "k_push")
-        loop_name = {1: "host", 2: "persistent", 3: "queued"}.get(stats_last["loop"], "?")
+        kern = {2: "k_persistent", 3: "k_step", 4: "k_async"}.get(stats_last["loop"], "k_push")
+        loop_name = {1: "host", 2: "persistent", 3: "queued", 4: "async"}.get(stats_last["loop"], "?")
         layout_name = {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?")
         relax_name = {1: "dist", 2: "bound"}.get(stats_last["relax_filter"], "?")
         traffic = counter_traffic(kern, args.workload, loop_name, layout_name, relax_name)
@@ -262,7 +263,8 @@ def main():
         "data": "synthetic (seeded generator)",
         "config": {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m,
                    "layout": {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?") if stats_last else None,
-                   "loop": {1: "host", 2: "persistent", 3: "queued"}.get(stats_last["loop"], "?") if stats_last else None,
+                   "loop": {1: "host", 2: "persistent", 3: "queued", 4: "async"}.get(stats_last["loop"], "?")
+                   if stats_last else None,
                    "delta": args.delta or None,
                    "relax_filter": {1: "dist", 2: "bound"}.get(stats_last["relax_filter"]) if stats_last else None,
                    "iterations_per_query": iters / max(args.steps, 1),

@@ -125,8 +125,16 @@ typedef enum {
     GR_LOOP_AUTO = 0,       /* the library's choice (tuned per graph) */
     GR_LOOP_HOST = 1,       /* one launch per operator, host reads the frontier size */
     GR_LOOP_PERSISTENT = 2, /* one cooperative launch, device-side grid barrier */
-    GR_LOOP_QUEUED = 3      /* launches enqueued ahead in chunks; each reads the frontier
+    GR_LOOP_QUEUED = 3,     /* launches enqueued ahead in chunks; each reads the frontier
                                size from device memory; the host checks once per chunk */
+    GR_LOOP_ASYNC = 4       /* asynchronous (Section III-A without the per-advance barrier,
+                               III-B frontier as a message queue): one persistent kernel
+                               drains a device worklist of improved vertices; no rounds.
+                               Push only over the plain CSR (direction PULL / ALTERNATE and
+                               an explicit delta are GR_ERR_INVALID_ARG; layout, filter and
+                               relax_filter are ignored).  Extra workspace: 16 n bytes.
+                               stats: iterations = worklist phases (1 unless the list of
+                               4 n entries overflowed), frontier_sum = vertex expansions. */
 } gr_loop_mode;
 
 /* Traversal direction policy (Section III-C: push vs pull). */

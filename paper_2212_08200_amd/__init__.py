@@ -52,6 +52,7 @@ GR_LOOP_AUTO = 0
 GR_LOOP_HOST = 1
 GR_LOOP_PERSISTENT = 2
 GR_LOOP_QUEUED = 3
+GR_LOOP_ASYNC = 4
 GR_DELTA_OFF = 0xFFFFFFFF
 GR_RELAX_DIST = 1
 GR_RELAX_BOUND = 2
@@ -284,9 +285,9 @@ def gr_bfs(g: int, src: int, depth_out, stream=None) -> None:
 
 
 def gr_bfs_ex(g: int, src: int, depth_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
-              max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, relax_filter=0) -> dict:
+              max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, relax_filter=0, barrier_timeout_us=0) -> dict:
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
-                     timing=timing, filter=filter, relax_filter=relax_filter)
+                     timing=timing, filter=filter, relax_filter=relax_filter, barrier_timeout_us=barrier_timeout_us)
     st = gr_sssp_stats()
     _check(lib().gr_bfs_ex(g, int(src), _ptr(depth_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()

@@ -453,6 +453,7 @@ struct RunCfg {
     int direction;
     int32_t alpha_x16;
     int64_t max_iters;
+    bool max_iters_given;  // set by the caller (else the default cap)
     bool timing;
     int layout;
     int filter;
@@ -469,9 +470,10 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
     rc->direction = o ? o->direction : GR_DIR_AUTO;
     rc->alpha_x16 = (o && o->alpha_x16 > 0) ? o->alpha_x16 : g->auto_alpha_x16;
     rc->max_iters = (o && o->max_iters > 0) ? o->max_iters : (int64_t)g->plain.n + 1;
+    rc->max_iters_given = o && o->max_iters > 0;
     const int layout = o ? o->layout : GR_LAYOUT_AUTO;
     if (!g->pull) rc->alpha_x16 = 0;  // the device-side AUTO rule must never pick pull then
-    if (rc->loop < GR_LOOP_AUTO || rc->loop > GR_LOOP_QUEUED)
+    if (rc->loop < GR_LOOP_AUTO || rc->loop > GR_LOOP_ASYNC)
         return fail(GR_ERR_INVALID_ARG, "unknown loop mode %d", rc->loop);
     if (rc->direction < GR_DIR_AUTO || rc->direction > GR_DIR_ALTERNATE)
         return fail(GR_ERR_INVALID_ARG, "unknown direction %d", rc->direction);
@@ -501,6 +503,13 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
         float x;
         std::memcpy(&x, &d, 4);
         if (!(x > 0.f && x <= FLT_MAX)) return fail(GR_ERR_INVALID_ARG, "delta must be a positive finite binary32");
+    }
+    if (rc->loop == GR_LOOP_ASYNC) {
+        if (rc->direction == GR_DIR_PULL || rc->direction == GR_DIR_ALTERNATE)
+            return fail(GR_ERR_INVALID_ARG, "the asynchronous loop runs push only");
+        if (o && o->delta && o->delta != GR_DELTA_OFF)
+            return fail(GR_ERR_INVALID_ARG, "the asynchronous loop has no near-far split");
+        d = 0;
     }
     rc->delta = d;
     if (d) {
@@ -827,6 +836,94 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     return GR_OK;
 }
 
+// Asynchronous loop: one persistent kernel drains a device worklist (see
+// gr_async.hip) per phase; a phase ends early only when the list overflowed,
+// and the next one starts from the spilled vertices.  The host waits for
+// each phase (phases beyond the first are rare: the list holds 4 n entries).
+static gr_status run_async(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
+                           gr_sssp_stats *stats) {
+    DeviceInfo di;
+    gr_status s = device_info(g->device, &di);
+    if (s != GR_OK) return s;
+    const DevGraph &dg = *rc.dg;
+    const uint64_t spin = (uint64_t)rc.barrier_timeout_us * (uint64_t)di.wall_khz / 1000ull;
+    unsigned long long *hp = pinned_slot();
+    if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
+    void *ws = nullptr, *aws = nullptr;
+    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
+    // GR_ASYNC_LIST_CAP (entries, >= 1) lowers the list's capacity: a test
+    // hook for the overflow path
+    int64_t cap = async_capacity(dg.n);
+    if (const char *ev = getenv("GR_ASYNC_LIST_CAP")) {
+        const long long c = atoll(ev);
+        if (c >= 1) cap = std::min<int64_t>(cap, c);
+    }
+    hipError_t e = hipMallocAsync(&aws, async_bytes(cap), st);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(ws, st);
+        return hip_fail(e, "hipMallocAsync");
+    }
+    Frontier f;
+    frontier_carve(f, ws, dg);
+    unsigned long long *ctl = async_ctl(cap, aws);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool timed = rc.timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
+    gr_status status = GR_OK;
+    int64_t phases = 0;
+    double us = 0;
+    e = launch_async_init(dg, dist, src, f, aws, cap, st);
+    while (e == hipSuccess) {
+        if (timed) e = hipEventRecord(ev[0], st);
+        if (e == hipSuccess) e = launch_async(dg, dist, f, aws, cap, di.num_cu, spin, st);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[1], st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hp, ctl, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hp + 3, ctl + kAsyncTail, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
+        ++phases;
+        if (timed) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+            us += 1e3 * ms;
+        }
+        if (hp[0] == 3ull) {
+            status = fail(GR_ERR_HIP, "asynchronous loop: a worklist wait exceeded %lld us",
+                          (long long)rc.barrier_timeout_us);
+            break;
+        }
+        if (hp[3] <= (unsigned long long)cap) break;  // drained without spilling: done
+        // each phase expands at least one vertex, so phases end without a cap
+        // unless the caller set one
+        if (rc.max_iters_given && phases >= rc.max_iters) {
+            status = fail(GR_ERR_ITER_LIMIT, "phase cap %lld reached", (long long)rc.max_iters);
+            break;
+        }
+        e = launch_async_relist(dg, f, aws, cap, st);
+    }
+    gr_sssp_stats local{};
+    local.loop = GR_LOOP_ASYNC;
+    local.layout = GR_LAYOUT_PLAIN;
+    local.relax_filter = GR_RELAX_DIST;
+    local.iterations = (int32_t)phases;
+    local.edges_pushed = (int64_t)hp[2];
+    local.frontier_sum = (int64_t)hp[1];
+    local.push_frontier_sum = (int64_t)hp[1];
+    local.push_launches = (int32_t)phases;
+    local.launches = (int32_t)(2 * phases);  // init, then one phase (+ a relist before each later one)
+    local.push_us = us;
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    hipError_t e2 = hipFreeAsync(aws, st);
+    hipError_t e3 = hipFreeAsync(ws, st);
+    if (e != hipSuccess) return hip_fail(e, "asynchronous loop");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    if (e3 != hipSuccess) return hip_fail(e3, "hipFreeAsync");
+    if (status != GR_OK) return status;
+    if (stats) *stats = local;
+    return GR_OK;
+}
+
 extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, void *stream,
                                 const gr_sssp_opts *opts, gr_sssp_stats *stats) {
     if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
@@ -837,6 +934,8 @@ extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, 
     if (s != GR_OK) return s;
     int loop = rc.loop;
     if (loop == GR_LOOP_AUTO) loop = g->auto_loop;
+    if (loop == GR_LOOP_ASYNC)
+        return run_async(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
     if (loop == GR_LOOP_QUEUED)
         return run_queued(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
     if (loop == GR_LOOP_PERSISTENT)
@@ -882,6 +981,7 @@ extern "C" gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, 
     rc.dg = &unit;
     uint32_t *d = static_cast<uint32_t *>(depth_out);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (loop == GR_LOOP_ASYNC) return run_async(g, src, d, st, rc, stats);
     return loop == GR_LOOP_QUEUED ? run_queued(g, src, d, st, rc, stats) : run_host_loop(g, src, d, st, rc, stats);
 }
 
@@ -910,6 +1010,7 @@ static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, ui
         if (s != GR_OK) return s;
         rc.max_iters = max_iters;
         const int loop = g->auto_loop;
+        if (loop == GR_LOOP_ASYNC) return run_async(g, srcs[0], out_rows[0], st, rc, nullptr);
         if (loop == GR_LOOP_QUEUED) return run_queued(g, srcs[0], out_rows[0], st, rc, nullptr);
         if (loop == GR_LOOP_PERSISTENT) return run_persistent(g, srcs[0], out_rows[0], st, rc, nullptr);
         return run_host_loop(g, srcs[0], out_rows[0], st, rc, nullptr);
@@ -1293,7 +1394,8 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         o.layout = c.layout;
         o.alpha_x16 = c.alpha_x16 > 0 ? c.alpha_x16 : 0;
         o.direction = c.alpha_x16 > 0 ? GR_DIR_AUTO : GR_DIR_PUSH;
-        o.delta = c.delta ? c.delta : GR_DELTA_OFF;
+        o.delta = (c.delta && c.loop != GR_LOOP_ASYNC) ? c.delta : GR_DELTA_OFF;
+        if (c.loop == GR_LOOP_ASYNC) o.direction = GR_DIR_PUSH;
         o.filter = c.small ? 3 : 0;
         o.relax_filter = c.relax;
         const int32_t saved = g->auto_dense_ratio;
@@ -1330,8 +1432,8 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         DeviceInfo di;
         const bool coop = device_info(g->device, &di) == GR_OK && di.coop &&
                           persistent_grid(g->plain, di.num_cu) >= kMaxParts;
-        knobs.push_back({1, coop ? std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_PERSISTENT}
-                                 : std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED}});
+        knobs.push_back({1, coop ? std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_PERSISTENT, GR_LOOP_ASYNC}
+                                 : std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_ASYNC}});
     }
     knobs.push_back({2, {8, 64, 512}});
     if (g->pull) knobs.push_back({3, {0, 8, 32}});
@@ -1346,6 +1448,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         for (int32_t v : kv.second) {
             if (status != GR_OK) break;
             TuneCfg c = best;
+            if (c.loop == GR_LOOP_ASYNC && kv.first != 1) continue;  // no other knob applies to it
             if (kv.first == 4) {
                 if (c.delta == (uint32_t)v) continue;
                 c.delta = (uint32_t)v;

@@ -205,6 +205,31 @@ hipError_t launch_members(int32_t n, int32_t np, const int32_t *pro, int32_t *cn
 hipError_t launch_locality(int32_t n, const int32_t *ro, const uint2 *adj, int32_t span, unsigned long long *near,
                            hipStream_t st);
 
+// Asynchronous loop (gr_async.hip).  Its worklist and counters live in a
+// buffer of async_bytes(n) bytes; the frontier workspace's two flag arrays
+// serve as the in-queue and spill bytes.  Counter words (each hot one on its
+// own 256-byte line): status (0 running or done, 3 a wait timed out), the
+// expanded-vertex and arc totals, then the list's head, tail and done counts.
+constexpr int kAsyncStatus = 0;
+constexpr int kAsyncStatItems = 1;
+constexpr int kAsyncStatArcs = 2;
+constexpr int kAsyncHead = 32;
+constexpr int kAsyncTail = 64;
+constexpr int kAsyncDone = 96;
+constexpr int kAsyncCtlWords = 128;
+int64_t async_capacity(int32_t n);  // default list entries: 4 n + 1024
+size_t async_bytes(int64_t cap);    // list of cap entries + counters
+unsigned long long *async_ctl(int64_t cap, void *ws);
+// dist, flags, list {src} and counters for a new query.
+hipError_t launch_async_init(const DevGraph &g, uint32_t *dist, int32_t src, const Frontier &f, void *ws, int64_t cap,
+                             hipStream_t st);
+// One phase: runs until the list is drained or a wait exceeds spin_ticks.
+// Appends past the list's capacity are spilled: tail - cap of them.
+hipError_t launch_async(const DevGraph &g, uint32_t *dist, const Frontier &f, void *ws, int64_t cap, int num_cu,
+                        uint64_t spin_ticks, hipStream_t st);
+// Restarts the list with the spilled vertices (those past cap stay spilled).
+hipError_t launch_async_relist(const DevGraph &g, const Frontier &f, void *ws, int64_t cap, hipStream_t st);
+
 // Batched multi-source (gr_batch.hip): up to kBatchLanes sources, one per
 // wave lane, distances vertex-major D[v * kBatchLanes + s].
 constexpr int kBatchLanes = 64;
