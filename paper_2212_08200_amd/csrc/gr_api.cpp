@@ -112,7 +112,7 @@ static unsigned long long *pinned_slot() {
     static thread_local unsigned long long *p = nullptr;
     if (!p) {
         void *q = nullptr;
-        if (hipHostMalloc(&q, 256, hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (hipHostMalloc(&q, 8192, hipHostMallocDefault) != hipSuccess) return nullptr;
         p = static_cast<unsigned long long *>(q);
     }
     return p;

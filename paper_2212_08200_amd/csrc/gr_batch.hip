@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kBlk) void k_batch_fill(uint32_t *__restrict__ D, i
         reinterpret_cast<uint4 *>(f0)[i] = z;
         reinterpret_cast<uint4 *>(f1)[i] = z;
     }
-    if (tid < kCtlWords) ctl[tid] = 0ull;
+    for (int64_t i = tid; i < kCtlWords; i += stride) ctl[i] = 0ull;
 }
 
 // Sources: slot s starts at srcs[s] with distance 0 and is active there.

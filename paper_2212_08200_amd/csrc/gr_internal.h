@@ -64,9 +64,10 @@ struct DevGraph {
 //                    repeats) that let small rounds skip the flag scan
 //   ctl              3 slots of kSlotWords counters, rotated over three
 //                    iterations so that a slot is cleared one iteration after
-//                    its last use: word k < 8 packs F_k (low 32 bits) and E_k
-//                    (high 32 bits) of partition k, word 8 counts held-back
-//                    vertices and word 9 holds the max of ~dist over them;
+//                    its last use: word k * kCtrStride (k < 8) packs F_k (low
+//                    32 bits) and E_k (high 32 bits) of partition k, word
+//                    kFarCountWord counts held-back vertices and word
+//                    kFarMaxInvWord holds the max of ~dist over them;
 //                    then the device-driven loop state
 struct Frontier {
     uint8_t *flags[2];
@@ -86,11 +87,14 @@ struct Frontier {
 
 constexpr int kCandRegions = 64;  // regions of a small-round candidate list
 constexpr int kCtlSlots = 3;
-constexpr int kSlotWords = 16;
-constexpr int kFarCountWord = 8;    // within a slot
-constexpr int kFarMaxInvWord = 9;   // within a slot: max of ~dist[u] over held-back u
-constexpr int kCtlWords = 80;       // 3 slots of 16 words, LoopState, candidate counters
-constexpr int kLoopStateWord = 48;  // LoopState at ctl + 48
+// Counters that many blocks update at once each sit on a 256-byte line of
+// their own: memory-side atomics to one line are serialised.
+constexpr int kCtrStride = 32;                    // words from one counter to the next
+constexpr int kFarCountWord = 8 * kCtrStride;     // within a slot
+constexpr int kFarMaxInvWord = 9 * kCtrStride;    // within a slot: max of ~dist[u] over held-back u
+constexpr int kSlotWords = 10 * kCtrStride;       // partition k's counter at word k * kCtrStride
+constexpr int kLoopStateWord = 3 * kSlotWords;    // LoopState after the 3 slots
+constexpr int kCtlWords = kLoopStateWord + 32;
 constexpr int32_t kDenseRatio = 64;  // default: streaming filter when |frontier| >= n / 64
 
 // Device-driven loop state.

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
         reinterpret_cast<uint4 *>(a.flags0)[w] = z;
     }
     if (blockIdx.x == 0) {
-        if (threadIdx.x < kCtlWords) a.ctl[threadIdx.x] = 0ull;
+        for (int t = threadIdx.x; t < kCtlWords; t += kBlk) a.ctl[t] = 0ull;
         __syncthreads();
         if (threadIdx.x == 0) reinterpret_cast<LoopState *>(a.ctl + kLoopStateWord)->threshold = a.threshold;
         if (a.ccount && threadIdx.x < 3 * kCandRegions) a.ccount[threadIdx.x] = 0ull;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
             if (d > 0) {
                 a.qse[k][0] = make_uint2((uint32_t)st, (uint32_t)src);
                 a.qs[k][0] = 0;
-                a.ctl[k] = 1ull | ((unsigned long long)d << 32);
+                a.ctl[k * kCtrStride] = 1ull | ((unsigned long long)d << 32);
             }
         }
     }
@@ -579,7 +579,8 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t g, con
                                              uint8_t *__restrict__ far_next, uint32_t T) {
     __shared__ unsigned long long sh_base[NP];
     __shared__ uint32_t sh_far_cnt, sh_far_inv;
-    if (g == 0 && threadIdx.x < kSlotWords) ctl_zero[threadIdx.x] = 0ull;
+    if (g == 0)
+        for (int t = threadIdx.x; t < kSlotWords; t += kBlk) ctl_zero[t] = 0ull;
     if (a.zmask)
         for (int t = threadIdx.x; t < kGroupVerts; t += kBlk) a.zmask[g * kGroupVerts + t] = 0ull;
     const int64_t base = g * kGroupVerts + threadIdx.x * kVpt;
@@ -629,7 +630,7 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t g, con
     block_scan<2 * NP>(x, tot);
     if (threadIdx.x < NP) {
         const int k = threadIdx.x;
-        sh_base[k] = tot[k] ? atomicAdd(ctl_next + k, (unsigned long long)tot[k] |
+        sh_base[k] = tot[k] ? atomicAdd(ctl_next + k * kCtrStride, (unsigned long long)tot[k] |
                                                           ((unsigned long long)tot[NP + k] << 32))
                             : 0ull;
     }
@@ -701,7 +702,8 @@ __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t v
     const int np = a.np;
     const int k = (int)(vb % np);
     const int64_t j = vb / np;
-    if (vb == 0 && threadIdx.x < kSlotWords) ctl_zero[threadIdx.x] = 0ull;
+    if (vb == 0)
+        for (int t = threadIdx.x; t < kSlotWords; t += kBlk) ctl_zero[t] = 0ull;
     {
         // this block's share of the flags: clear the current ones and, with
         // the near-far split, write the next held-back flags of the share
@@ -765,7 +767,7 @@ __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t v
     }
     block_scan<2>(x, tot);
     if (threadIdx.x == 0)
-        sh_base = tot[0] ? atomicAdd(ctl_next + k, (unsigned long long)tot[0] | ((unsigned long long)tot[1] << 32))
+        sh_base = tot[0] ? atomicAdd(ctl_next + k * kCtrStride, (unsigned long long)tot[0] | ((unsigned long long)tot[1] << 32))
                          : 0ull;
     __syncthreads();
     int32_t pos = (int32_t)(sh_base & 0xFFFFFFFFull) + x[0];
@@ -869,7 +871,7 @@ __device__ __forceinline__ SlotTotals slot_totals(const unsigned long long *cur,
     SlotTotals t{0, 0, 0, 0, 0, 0u};
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const unsigned long long c = __hip_atomic_load(cur + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long c = __hip_atomic_load(cur + k * kCtrStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int32_t f = (int32_t)(c & 0xFFFFFFFFull), e = (int32_t)(c >> 32);
         t.Fs += f;
         t.Es += e;
@@ -1234,8 +1236,8 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
             if (b == 0 && threadIdx.x < kCandRegions) a.ccount[((r + 2) % 3) * kCandRegions + threadIdx.x] = 0ull;
             // the queue counter slot a filter of round r would clear (a filter of
             // round r + 1 may run later and add into it)
-            if (b == 0 && threadIdx.x < kSlotWords)
-                a.ctl[((r + 2) % kCtlSlots) * kSlotWords + threadIdx.x] = 0ull;
+            if (b == 0)
+                for (int t = threadIdx.x; t < kSlotWords; t += kBlk) a.ctl[((r + 2) % kCtlSlots) * kSlotWords + t] = 0ull;
             if (lead) ls->small_rounds += 1ull;
             small_round<WT, O32>(a, r, ls, sPre);
             ran = kRanSmall;
@@ -1584,8 +1586,8 @@ unsigned long long *counters_after(const Frontier &f, int64_t iter) { return f.c
 
 void read_counts(const unsigned long long *h, FrontierCounts *c) {
     for (int k = 0; k < kMaxParts; ++k) {
-        c->F[k] = (int32_t)(h[k] & 0xFFFFFFFFull);
-        c->E[k] = (int32_t)(h[k] >> 32);
+        c->F[k] = (int32_t)(h[k * kCtrStride] & 0xFFFFFFFFull);
+        c->E[k] = (int32_t)(h[k * kCtrStride] >> 32);
     }
     c->far_count = (int64_t)h[kFarCountWord];
     c->far_min = ~(uint32_t)h[kFarMaxInvWord];
