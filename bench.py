@@ -236,6 +236,11 @@ def main():
 
     batched = None
     if not args.no_batched and args.workload == "rmat22" and not args.bfs:
+        for s in srcs:  # every batched source needs its reached-arc count
+            if s not in reached:
+                gr.gr_sssp_ex(G.handle, s, dist, stream=stream, **opts)
+                d = dist.cpu().numpy().view(np.uint32)
+                reached[s] = int(deg[d != inf].sum())
         batched = measure_batched(G, g, srcs, reached, ms_per_step, torch, np, gr, dev)
         log("batched: %s" % batched)
     G.close()
