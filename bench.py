@@ -274,7 +274,8 @@ def main():
                    "relax_filter": {1: "dist", 2: "bound"}.get(stats_last["relax_filter"]) if stats_last else None,
                    "iterations_per_query": iters / max(args.steps, 1),
                    "tuned": ({k: tuned[k] for k in ("layout", "loop", "dense_ratio", "alpha_x16", "delta", "small",
-                                                   "relax_filter", "best_ms", "default_ms", "trials")} if tuned else None)},
+                                                   "relax_filter", "async_blocks", "best_ms", "default_ms", "trials")}
+                             if tuned else None)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,

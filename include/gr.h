@@ -230,11 +230,13 @@ typedef struct {
     uint32_t delta;       /* chosen near-far split width (weight-type bits; 0 = off) */
     int32_t small;        /* 1: small rounds (filter 3) in the queued loop */
     int32_t relax_filter; /* GR_RELAX_DIST or GR_RELAX_BOUND */
+    int32_t async_blocks; /* blocks of the asynchronous loop (0: the library's default) */
 } gr_tune_result;
 
 /*
  * Autotuner: times candidate schedules -- push layout, loop driver, filter
- * threshold, pull threshold, near-far split width, small rounds, relaxation filter -- with a greedy search (one knob at a time, each
+ * threshold, pull threshold, near-far split width, small rounds, relaxation filter,
+ * the asynchronous loop's block count -- with a greedy search (one knob at a time, each
  * candidate timed as the median of `reps` queries from srcs[0..nsrcs)), and
  * keeps the fastest as the graph's AUTO configuration.  Every candidate
  * computes the same distances.  When the environment variable GR_TUNE_CACHE

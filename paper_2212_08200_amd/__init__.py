@@ -113,7 +113,7 @@ class gr_tune_result(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("loop", ctypes.c_int32), ("dense_ratio", ctypes.c_int32),
                 ("alpha_x16", ctypes.c_int32), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
                 ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("delta", ctypes.c_uint32),
-                ("small", ctypes.c_int32), ("relax_filter", ctypes.c_int32)]
+                ("small", ctypes.c_int32), ("relax_filter", ctypes.c_int32), ("async_blocks", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

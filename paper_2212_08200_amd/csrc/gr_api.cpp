@@ -157,6 +157,7 @@ struct gr_graph {
     uint32_t auto_delta = 0;  // near-far split width (0: off)
     bool auto_small = false;  // queued loop: small rounds
     int32_t auto_relax = GR_RELAX_DIST;  // push's relaxation filter
+    int32_t auto_async_blocks = 0;       // asynchronous loop's block count (0: async_blocks())
     // iterations of the last completed queued-loop query (first chunk size)
     mutable std::atomic<int32_t> last_iters{0};
     double locality = 1.0;  // fraction of arcs with |u - v| < locality_span(n)
@@ -866,6 +867,7 @@ static gr_status run_async(const gr_graph *g, int32_t src, uint32_t *dist, hipSt
     Frontier f;
     frontier_carve(f, ws, dg);
     unsigned long long *ctl = async_ctl(cap, aws);
+    const int blocks = g->auto_async_blocks > 0 ? g->auto_async_blocks : async_blocks(dg, di.num_cu);
     hipEvent_t ev[2] = {nullptr, nullptr};
     const bool timed = rc.timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
     gr_status status = GR_OK;
@@ -874,7 +876,7 @@ static gr_status run_async(const gr_graph *g, int32_t src, uint32_t *dist, hipSt
     e = launch_async_init(dg, dist, src, f, aws, cap, st);
     while (e == hipSuccess) {
         if (timed) e = hipEventRecord(ev[0], st);
-        if (e == hipSuccess) e = launch_async(dg, dist, f, aws, cap, di.num_cu, spin, st);
+        if (e == hipSuccess) e = launch_async(dg, dist, f, aws, cap, blocks, spin, st);
         if (e == hipSuccess && timed) e = hipEventRecord(ev[1], st);
         if (e == hipSuccess) e = hipMemcpyAsync(hp, ctl, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
@@ -1278,11 +1280,11 @@ static bool cache_lookup(const std::string &sig, gr_tune_result *r) {
         char s[300];
         int lay, loop, dr, al;
         unsigned dl;
-        int sm, rf;
+        int sm, rf, ab;
         double ms;
         if (sscanf(line, "{\"sig\": \"%299[^\"]\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
-                         "\"delta\": %u, \"small\": %d, \"relax_filter\": %d, \"best_ms\": %lf}",
-                   s, &lay, &loop, &dr, &al, &dl, &sm, &rf, &ms) == 9 &&
+                         "\"delta\": %u, \"small\": %d, \"relax_filter\": %d, \"async_blocks\": %d, \"best_ms\": %lf}",
+                   s, &lay, &loop, &dr, &al, &dl, &sm, &rf, &ab, &ms) == 10 &&
             sig == s) {
             r->layout = lay;
             r->loop = loop;
@@ -1291,6 +1293,7 @@ static bool cache_lookup(const std::string &sig, gr_tune_result *r) {
             r->delta = dl;
             r->small = sm;
             r->relax_filter = rf;
+            r->async_blocks = ab;
             r->best_ms = ms;
             found = true;  // the last matching line wins
         }
@@ -1305,8 +1308,9 @@ static void cache_store(const std::string &sig, const gr_tune_result &r) {
     FILE *f = fopen(path, "a");
     if (!f) return;
     fprintf(f, "{\"sig\": \"%s\", \"layout\": %d, \"loop\": %d, \"dense_ratio\": %d, \"alpha_x16\": %d, "
-               "\"delta\": %u, \"small\": %d, \"relax_filter\": %d, \"best_ms\": %.6f}\n",
-            sig.c_str(), r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small, r.relax_filter, r.best_ms);
+               "\"delta\": %u, \"small\": %d, \"relax_filter\": %d, \"async_blocks\": %d, \"best_ms\": %.6f}\n",
+            sig.c_str(), r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small, r.relax_filter, r.async_blocks,
+            r.best_ms);
     fclose(f);
 }
 
@@ -1315,6 +1319,7 @@ struct TuneCfg {
     uint32_t delta;
     int32_t small;
     int32_t relax;
+    int32_t async_blocks;  // 0: the default
 };
 
 static void apply_auto(gr_graph *g, const TuneCfg &c) {
@@ -1325,6 +1330,7 @@ static void apply_auto(gr_graph *g, const TuneCfg &c) {
     g->auto_delta = c.delta;
     g->auto_small = c.small != 0;
     g->auto_relax = c.relax;
+    g->auto_async_blocks = c.async_blocks;
 }
 
 // Near-far split widths to try: multiples of the mean weight of a sample of
@@ -1378,7 +1384,9 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         if (r.alpha_x16 > 0 && !g->pull) r.alpha_x16 = 0;
         if (r.delta) r.alpha_x16 = 0;
         if (r.relax_filter != GR_RELAX_BOUND) r.relax_filter = GR_RELAX_DIST;
-        apply_auto(g, TuneCfg{r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small, r.relax_filter});
+        if (r.async_blocks < 0 || r.async_blocks > 65536) r.async_blocks = 0;
+        apply_auto(g, TuneCfg{r.layout, r.loop, r.dense_ratio, r.alpha_x16, r.delta, r.small, r.relax_filter,
+                              r.async_blocks});
         r.from_cache = 1;
         if (out) *out = r;
         return GR_OK;
@@ -1398,8 +1406,9 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         if (c.loop == GR_LOOP_ASYNC) o.direction = GR_DIR_PUSH;
         o.filter = c.small ? 3 : 0;
         o.relax_filter = c.relax;
-        const int32_t saved = g->auto_dense_ratio;
+        const int32_t saved = g->auto_dense_ratio, saved_ab = g->auto_async_blocks;
         g->auto_dense_ratio = c.dense_ratio;
+        g->auto_async_blocks = c.async_blocks;
         std::vector<double> t;
         gr_status s = GR_OK;
         for (int32_t rep = 0; rep <= reps && s == GR_OK; ++rep) {
@@ -1413,6 +1422,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
             }
         }
         g->auto_dense_ratio = saved;
+        g->auto_async_blocks = saved_ab;
         ++trials;
         if (s != GR_OK) return s;
         std::sort(t.begin(), t.end());
@@ -1420,7 +1430,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         return GR_OK;
     };
     TuneCfg best{g->auto_layout, g->auto_loop, g->auto_dense_ratio, g->auto_alpha_x16, g->auto_delta,
-                 g->auto_small ? 1 : 0, g->auto_relax};
+                 g->auto_small ? 1 : 0, g->auto_relax, g->auto_async_blocks};
     double best_ms = 0;
     status = measure(best, &best_ms);
     const double default_ms = best_ms;
@@ -1444,11 +1454,13 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
     }
     if (g->max_degree <= kSmallMaxDegree) knobs.push_back({5, {0, 1}});
     knobs.push_back({6, {GR_RELAX_DIST, GR_RELAX_BOUND}});
+    knobs.push_back({7, {64, 128, 256, 512, 1024}});  // asynchronous loop only
     for (const auto &kv : knobs) {
         for (int32_t v : kv.second) {
             if (status != GR_OK) break;
             TuneCfg c = best;
-            if (c.loop == GR_LOOP_ASYNC && kv.first != 1) continue;  // no other knob applies to it
+            if (c.loop == GR_LOOP_ASYNC && kv.first != 1 && kv.first != 7) continue;  // the others do not apply
+            if (kv.first == 7 && c.loop != GR_LOOP_ASYNC) continue;
             if (kv.first == 4) {
                 if (c.delta == (uint32_t)v) continue;
                 c.delta = (uint32_t)v;
@@ -1456,6 +1468,9 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
             } else if (kv.first == 5) {
                 if (c.small == v || c.loop != GR_LOOP_QUEUED || c.delta) continue;
                 c.small = v;
+            } else if (kv.first == 7) {
+                if (c.async_blocks == v) continue;
+                c.async_blocks = v;
             } else if (kv.first == 6) {
                 if (c.relax == v) continue;
                 c.relax = v;
@@ -1486,6 +1501,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
     r.delta = best.delta;
     r.small = best.small;
     r.relax_filter = best.relax;
+    r.async_blocks = best.async_blocks;
     r.best_ms = best_ms;
     r.default_ms = default_ms;
     r.trials = trials;

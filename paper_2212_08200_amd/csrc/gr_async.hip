@@ -446,7 +446,16 @@ hipError_t launch_async_init(const DevGraph &g, uint32_t *dist, int32_t src, con
     return hipGetLastError();
 }
 
-hipError_t launch_async(const DevGraph &g, uint32_t *dist, const Frontier &f, void *ws, int64_t cap, int num_cu,
+int async_blocks(const DevGraph &g, int num_cu) {
+    // one block per 64K arcs, between 64 and two per CU: measured best (R-MAT
+    // 22: 512 blocks, 8.5 ms, against 11.7 ms with 1024; road-like 2048^2:
+    // 256, 13.6 against 21.4 ms; grid 64^2: 128 or fewer, 1.2 against 4.3 ms)
+    // -- more blocks than the worklist keeps busy only add counter traffic
+    const int64_t b = std::min<int64_t>(std::max<int64_t>((int64_t)g.m >> 16, 64), 2 * (int64_t)std::max(num_cu, 1));
+    return (int)b;
+}
+
+hipError_t launch_async(const DevGraph &g, uint32_t *dist, const Frontier &f, void *ws, int64_t cap, int blocks,
                         uint64_t spin_ticks, hipStream_t st) {
     const AsyncArgs a = async_args(g, dist, 0, f, ws, cap, spin_ticks);
     const bool o32 = (uint64_t)g.m * 8ull < (1ull << 32) && (uint64_t)g.n * 4ull < (1ull << 32);
@@ -457,8 +466,9 @@ hipError_t launch_async(const DevGraph &g, uint32_t *dist, const Frontier &f, vo
         default: occ = o32 ? async_occupancy<0, true>() : async_occupancy<0, false>(); break;
     }
     // blocks need not be co-resident (no block waits for one that has not
-    // started), but a resident grid keeps every CU busy
-    const int grid = std::max(1, std::min(occ, 4)) * std::max(num_cu, 1);
+    // started); at most the resident count
+    if (occ < 1) return hipErrorInvalidConfiguration;
+    const int grid = std::max(1, blocks);
 #define GR_ASYNC_LAUNCH(W, O) hipLaunchKernelGGL((k_async<W, O>), dim3(grid), dim3(kBlk), 0, st, a)
     switch (g.wt) {
         case 1:

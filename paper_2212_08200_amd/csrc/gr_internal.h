@@ -227,9 +227,12 @@ unsigned long long *async_ctl(int64_t cap, void *ws);
 // dist, flags, list {src} and counters for a new query.
 hipError_t launch_async_init(const DevGraph &g, uint32_t *dist, int32_t src, const Frontier &f, void *ws, int64_t cap,
                              hipStream_t st);
-// One phase: runs until the list is drained or a wait exceeds spin_ticks.
-// Appends past the list's capacity are spilled: tail - cap of them.
-hipError_t launch_async(const DevGraph &g, uint32_t *dist, const Frontier &f, void *ws, int64_t cap, int num_cu,
+// Default block count of the asynchronous kernel for a graph.
+int async_blocks(const DevGraph &g, int num_cu);
+// One phase with `blocks` blocks: runs until the list is drained or a wait
+// exceeds spin_ticks.  Appends past the list's capacity are spilled: tail -
+// cap of them.
+hipError_t launch_async(const DevGraph &g, uint32_t *dist, const Frontier &f, void *ws, int64_t cap, int blocks,
                         uint64_t spin_ticks, hipStream_t st);
 // Restarts the list with the spilled vertices (those past cap stay spilled).
 hipError_t launch_async_relist(const DevGraph &g, const Frontier &f, void *ws, int64_t cap, hipStream_t st);

@@ -39,7 +39,7 @@ def test_tune_then_query(flags, tmp_path, monkeypatch):
         assert r["layout"] in (gr.GR_LAYOUT_PLAIN, gr.GR_LAYOUT_PARTITIONED)
         if not G.info()["partitions"] > 1:
             assert r["layout"] == gr.GR_LAYOUT_PLAIN
-        assert r["loop"] in (gr.GR_LOOP_HOST, gr.GR_LOOP_PERSISTENT, gr.GR_LOOP_QUEUED)
+        assert r["loop"] in (gr.GR_LOOP_HOST, gr.GR_LOOP_PERSISTENT, gr.GR_LOOP_QUEUED, gr.GR_LOOP_ASYNC)
         assert r["dense_ratio"] in (8, 64, 512) and r["alpha_x16"] in (0, 8, 32)
         assert r["relax_filter"] in (gr.GR_RELAX_DIST, gr.GR_RELAX_BOUND)
         assert 0 < r["best_ms"] <= r["default_ms"]
@@ -48,7 +48,7 @@ def test_tune_then_query(flags, tmp_path, monkeypatch):
     with gr.Graph.from_csr(g, flags=flags) as G2:
         r2 = G2.tune(srcs, reps=2)
         assert r2["from_cache"] == 1
-        for k in ("layout", "loop", "dense_ratio", "alpha_x16", "delta", "small", "relax_filter"):
+        for k in ("layout", "loop", "dense_ratio", "alpha_x16", "delta", "small", "relax_filter", "async_blocks"):
             assert r2[k] == r[k]
         assert np.array_equal(run(G2, srcs[0], g.n), oracle.dijkstra(g, int(srcs[0])))
     lines = open(tmp_path / "tune.jsonl").read().splitlines()
