@@ -155,3 +155,32 @@ def test_async_rejects_and_times_out():
         assert np.array_equal(got, oracle.dijkstra(g, 0))
     finally:
         G.close()
+
+
+def test_async_is_the_small_mesh_default():
+    # bounded degree and n <= 65,536: AUTO runs the asynchronous loop, except
+    # for requests it cannot serve (pull, near-far), which take the queued loop
+    g = gg.grid(64, wseed=2)
+    want = oracle.dijkstra(g, 0)
+    G = gr.Graph.from_csr(g)
+    try:
+        for kw, loop in ((dict(), gr.GR_LOOP_ASYNC), (dict(direction=gr.GR_DIR_ALTERNATE), gr.GR_LOOP_QUEUED),
+                         (dict(delta=50), gr.GR_LOOP_QUEUED)):
+            d = torch.full((g.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+            st = gr.gr_sssp_ex(G.handle, 0, d, **kw)
+            torch.cuda.synchronize()
+            assert st["loop"] == loop, kw
+            assert np.array_equal(d.cpu().numpy().view(np.uint32), want), kw
+    finally:
+        G.close()
+    g = gg.rmat(14, 16, gseed=31, pseed=32, wseed=33)  # skewed degrees: queued
+    G = gr.Graph.from_csr(g)
+    try:
+        s = int(gg.pick_sources(g, 3, 1)[0])
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        st = gr.gr_sssp_ex(G.handle, s, d)
+        torch.cuda.synchronize()
+        assert st["loop"] == gr.GR_LOOP_QUEUED
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), oracle.dijkstra(g, s))
+    finally:
+        G.close()
