@@ -749,13 +749,17 @@ __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t v
     for (int it = 0; it < kDenseItems; ++it) {
         const int64_t m = min(m0 + it, hi - 1);
         u[it] = a.mem_u[m];
-        sd[it] = a.mem_sd[m];
     }
     int32_t x[2] = {0, 0}, tot[2];
     uint32_t du[kDenseItems];
 #pragma unroll
-    for (int it = 0; it < kDenseItems; ++it) {
+    for (int it = 0; it < kDenseItems; ++it)
         on[it] = (m0 + it < hi) && (nflags[u[it]] != 0 || (far_cur && far_cur[u[it]] != 0));
+    // arc ranges only of the members in the frontier (R-MAT 20: 2.25 -> 2.17 ms)
+#pragma unroll
+    for (int it = 0; it < kDenseItems; ++it) sd[it] = on[it] ? a.mem_sd[min(m0 + it, hi - 1)] : make_uint2(0u, 0u);
+#pragma unroll
+    for (int it = 0; it < kDenseItems; ++it) {
         if (far_cur) {
             du[it] = on[it] ? a.dist[u[it]] : 0u;
             on[it] = on[it] && du[it] < T;
