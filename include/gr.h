@@ -122,7 +122,10 @@ gr_status gr_sssp(const gr_graph *g, int32_t src, void *dist_out, void *stream);
 
 /* Loop schedule of gr_sssp_ex (Section III-A: execution policies). */
 typedef enum {
-    GR_LOOP_AUTO = 0,       /* the library's choice (tuned per graph) */
+    GR_LOOP_AUTO = 0,       /* the library's choice: gr_graph_tune's if run, else the
+                               asynchronous loop for graphs of maximum out-degree <= 64
+                               and n <= 65,536, the queued loop otherwise (and whenever
+                               the request needs pull or a near-far split) */
     GR_LOOP_HOST = 1,       /* one launch per operator, host reads the frontier size */
     GR_LOOP_PERSISTENT = 2, /* one cooperative launch, device-side grid barrier */
     GR_LOOP_QUEUED = 3,     /* launches enqueued ahead in chunks; each reads the frontier
@@ -134,7 +137,10 @@ typedef enum {
                                an explicit delta are GR_ERR_INVALID_ARG; layout, filter and
                                relax_filter are ignored).  Extra workspace: 16 n bytes.
                                stats: iterations = worklist phases (1 unless the list of
-                               4 n entries overflowed), frontier_sum = vertex expansions. */
+                               4 n entries overflowed), frontier_sum = vertex expansions.
+                               The call waits for the stream after each phase.  The
+                               environment variable GR_ASYNC_LIST_CAP (entries, >= 1)
+                               lowers the list capacity, to test the overflow path. */
 } gr_loop_mode;
 
 /* Traversal direction policy (Section III-C: push vs pull). */
