@@ -1060,7 +1060,7 @@ static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, ui
         }
         e = launch_batch_push(dg, w, iter, F, E, di.num_cu, st);
         if (e == hipSuccess)
-            e = launch_filter(dg, w.f, iter, w.mask[iter & 1], (int64_t)F * kDenseRatio >= dg.n, nullptr, false,
+            e = launch_filter(dg, w.f, iter, w.mask[iter & 1], (int64_t)F * kBatchDenseRatio >= dg.n, nullptr, false,
                               kInfU32, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hp, counters_after(w.f, iter), sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
