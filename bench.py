@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-source batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-queries", type=int, default=1500, help="open-loop queries per load level")
+    ap.add_argument("--serve-streams", type=int, default=4, help="server: concurrent batches on the device")
+    ap.add_argument("--serve-wait-us", type=int, default=200, help="server: longest wait of a partial batch")
     ap.add_argument("--bfs", action="store_true",
                     help="time breadth-first search (gr_bfs_ex) instead of SSSP on the same workload")
     ap.add_argument("--no-tune", action="store_true",
@@ -353,7 +355,8 @@ def measure_serving(args, torch, np, gr, gg, dev):
     edges_of = {}
 
     def serve(queries, arrivals_ns, max_batch):
-        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=4, max_wait_us=200)
+        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_streams,
+                                  max_wait_us=args.serve_wait_us)
         try:
             gids = [gr.gr_server_add_graph(srv, G.handle) for G in Gs]
             tickets = []
@@ -402,7 +405,8 @@ def measure_serving(args, torch, np, gr, gg, dev):
 
     def serve_closed(queries, clients, max_batch):
         """Closed loop: `clients` queries outstanding; each completion submits the next."""
-        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=4, max_wait_us=200)
+        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_streams,
+                                  max_wait_us=args.serve_wait_us)
         try:
             gids = [gr.gr_server_add_graph(srv, G.handle) for G in Gs]
             use = [0] * len(graphs)
