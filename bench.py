@@ -167,12 +167,14 @@ def main():
     edges = 0
     iters = 0
     q_bytes = 0
+    relax = 0
     stats_last = None
     for i in range(args.steps):
         s, st = run(args.warmup + i)
         edges += reached[s]
         iters += st["iterations"]
         q_bytes += 12 * st["edges_pushed"] + 20 * st["push_frontier_sum"]
+        relax += st["edges_pushed"]
         stats_last = st
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
@@ -275,6 +277,9 @@ def main():
                    "delta": args.delta or None,
                    "relax_filter": {1: "dist", 2: "bound"}.get(stats_last["relax_filter"]) if stats_last else None,
                    "iterations_per_query": iters / max(args.steps, 1),
+                   # relaxations performed per query, and per reached arc (work inflation)
+                   "relaxations_per_query": round(relax / max(args.steps, 1)),
+                   "relaxation_inflation": round(relax / max(edges, 1), 3),
                    "tuned": ({k: tuned[k] for k in ("layout", "loop", "dense_ratio", "alpha_x16", "delta", "small",
                                                    "relax_filter", "async_blocks", "best_ms", "default_ms", "trials")}
                              if tuned else None)},
