@@ -57,9 +57,8 @@ struct DevGraph {
 //   far[2]           near-far split: one byte per vertex that was improved
 //                    but held back because its distance is not below the
 //                    current threshold (read / written by iteration parity)
-//   qse[k], qs[k]    sparse frontier of partition k: (first arc, dist[u]) --
-//                    (first arc, u) for batched queries -- and the exclusive
-//                    prefix sum of the arc counts
+//   qse[k], qs[k]    sparse frontier of partition k: entries (first arc, u)
+//                    and the exclusive prefix sum of their arc counts
 //   cand[2]          queued loop: candidate lists (improved vertices, with
 //                    repeats) that let small rounds skip the flag scan
 //   ctl              3 slots of kSlotWords counters, rotated over three

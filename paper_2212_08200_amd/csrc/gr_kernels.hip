@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
 // ---------------------------------------------------------------------------
 // push advance with load-balanced search.
 //
-// Partition k's frontier has F entries (first arc, du) with exclusive arc
+// Partition k's frontier has F entries (first arc, u) with exclusive arc
 // count prefix sums s[0..F) (strictly increasing: the filter drops entries
 // without arcs) and E arcs in total.  Block j of partition k relaxes arc ranks
 // [j*per, min(E, (j+1)*per)).  It finds the entry holding its first rank with
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
 // staged in LDS; each lane maps its rank to an entry by binary search in LDS.
 constexpr int kPushItems = 16;
 // Smallest arc range a block of the device-sized advance takes (one pass of
-// its 256 lanes x 8 items).
+// its 256 lanes x kPushItems items).
 constexpr int32_t kMinChunk = kBlk * kPushItems;
 
 struct PushArgs {
