@@ -261,8 +261,9 @@ gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsrcs, int32_t
  *              weights are not read (any weight type).
  * The default direction policy switches to pull when the frontier's out-edges
  * reach m / 14; pull then scans only the in-arcs of vertices without a depth.
- * opts as for gr_sssp_ex, except: delta must be 0 / GR_DELTA_OFF, and the
- * persistent loop is GR_ERR_INVALID_ARG (AUTO runs the queued loop).
+ * opts as for gr_sssp_ex, except: delta must be 0 / GR_DELTA_OFF, the
+ * persistent loop is GR_ERR_INVALID_ARG, and AUTO runs the host-driven loop
+ * on graphs of maximum out-degree > 64 and the queued loop otherwise.
  */
 gr_status gr_bfs(const gr_graph *g, int32_t src, void *depth_out, void *stream);
 gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, void *stream, const gr_sssp_opts *opts,

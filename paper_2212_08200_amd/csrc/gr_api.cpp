@@ -986,7 +986,11 @@ extern "C" gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, 
         rc.alpha_x16 = (g->pull && g->max_degree > kSmallMaxDegree) ? kBfsAlphaX16 : 0;
     // hop counts leave few redundant relaxations: dist unless asked otherwise
     if (!(opts && opts->relax_filter)) rc.bound = false;
-    int loop = rc.loop == GR_LOOP_AUTO ? GR_LOOP_QUEUED : rc.loop;
+    // AUTO: the host-driven loop on skewed graphs (few rounds, direction-
+    // optimising: R-MAT 22 1.23 ms against 1.34 queued), the queued loop on
+    // bounded-degree ones (thousands of rounds: grid 2048^2 39 ms against 172)
+    int loop = rc.loop;
+    if (loop == GR_LOOP_AUTO) loop = g->max_degree > kSmallMaxDegree ? GR_LOOP_HOST : GR_LOOP_QUEUED;
     if (loop == GR_LOOP_PERSISTENT)
         return fail(GR_ERR_INVALID_ARG, "the device-driven persistent loop runs weighted queries only");
     DevGraph unit = *rc.dg;

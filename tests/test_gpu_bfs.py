@@ -97,7 +97,19 @@ def test_bfs_rmat20_rmat22_configs():
                     say("bfs %s src=%d dir=%s" % (name, s, d))
                     got, st = bfs(G, g.n, s, direction=DIRS[d])
                     assert np.array_equal(got, want), (name, s, d)
+                    assert st["loop"] == gr.GR_LOOP_HOST  # AUTO on a skewed graph
                     if d == "auto":
                         assert st["pull_iterations"] > 0  # the middle levels pull
         finally:
             G.close()
+
+
+def test_bfs_default_loop_on_a_mesh():
+    g = gg.grid(48, wseed=3)
+    G = gr.Graph.from_csr(g)
+    try:
+        got, st = bfs(G, g.n, 0)
+        assert np.array_equal(got, oracle.bfs(g, 0))
+        assert st["loop"] == gr.GR_LOOP_QUEUED  # bounded degree: the queued loop
+    finally:
+        G.close()
