@@ -124,8 +124,10 @@ gr_status gr_sssp(const gr_graph *g, int32_t src, void *dist_out, void *stream);
 typedef enum {
     GR_LOOP_AUTO = 0,       /* the library's choice: gr_graph_tune's if run, else the
                                asynchronous loop for graphs of maximum out-degree <= 64
-                               and n <= 65,536, the queued loop otherwise (and whenever
-                               the request needs pull or a near-far split) */
+                               and n <= 65,536 (the queued loop when the request needs
+                               pull or a near-far split), the host-driven loop for graphs
+                               of maximum out-degree > 64 and m >= 2^26, the queued loop
+                               otherwise */
     GR_LOOP_HOST = 1,       /* one launch per operator, host reads the frontier size */
     GR_LOOP_PERSISTENT = 2, /* one cooperative launch, device-side grid barrier */
     GR_LOOP_QUEUED = 3,     /* launches enqueued ahead in chunks; each reads the frontier

@@ -341,6 +341,11 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
     // (grid 64^2: 0.9 ms against 2.0 ms queued; 128^2: 1.9 against 4.8 ms;
     // 256^2 even; larger grids and every R-MAT graph favour the queued loop).
     if (g->max_degree <= kSmallMaxDegree && n <= kAsyncDefaultMaxN) g->auto_loop = GR_LOOP_ASYNC;
+    // Large skewed graphs: few, heavy rounds, where the host-driven loop's
+    // push grid of 16 blocks per CU beats the step kernel (R-MAT 22: 3.48 ms
+    // against 3.63); smaller ones keep the queued loop (no host round trip
+    // per round).
+    if (g->max_degree > kSmallMaxDegree && m >= (1 << 26)) g->auto_loop = GR_LOOP_HOST;
     BUILD_TRY(launch_locality(n, g->d_ro, g->d_adj, locality_span(n), near, st), "locality");
     unsigned long long hnear = 0;
     BUILD_TRY(hipMemcpyAsync(&hnear, near, sizeof hnear, hipMemcpyDeviceToHost, st), "locality");
