@@ -1,0 +1,70 @@
+"""GPU results on the hand-derived fixtures of tests/golden/, compared with the
+values written in the files (not with the oracle): every direction policy,
+push layout, loop driver (the asynchronous one included) and relaxation
+filter for SSSP, the batched call over all of a fixture's sources, and BFS
+hop counts."""
+import sys
+
+import numpy as np
+import pytest
+
+import golden_fixtures
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+gr = pytest.importorskip("paper_2212_08200_amd")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fresh(n):
+    return torch.full((n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("name", golden_fixtures.names())
+def test_golden_fixture_on_gpu(name):
+    g, queries = golden_fixtures.load(name)
+    G = gr.Graph.from_csr(g, flags=gr.GR_FORCE_PARTITION)
+    try:
+        info = G.info()
+        layouts = [gr.GR_LAYOUT_PLAIN] + ([gr.GR_LAYOUT_PARTITIONED] if info["partitions"] > 1 else [])
+        dirs = [gr.GR_DIR_PUSH, gr.GR_DIR_AUTO] + (
+            [gr.GR_DIR_PULL, gr.GR_DIR_ALTERNATE] if info["pull_enabled"] else [])
+        loops = (gr.GR_LOOP_HOST, gr.GR_LOOP_PERSISTENT, gr.GR_LOOP_QUEUED, gr.GR_LOOP_ASYNC)
+        for src, dist, hops in queries:
+            for lay in layouts:
+                for d in dirs:
+                    for lp in loops:
+                        if lp == gr.GR_LOOP_ASYNC and d not in (gr.GR_DIR_PUSH, gr.GR_DIR_AUTO):
+                            continue  # the asynchronous loop is push-only
+                        for rf in (gr.GR_RELAX_DIST, gr.GR_RELAX_BOUND):
+                            tag = "%s src=%d layout=%d dir=%d loop=%d relax=%d" % (name, src, lay, d, lp, rf)
+                            say("golden " + tag)
+                            out = fresh(g.n)
+                            kw = dict(barrier_timeout_us=5_000_000) if lp != gr.GR_LOOP_HOST else {}
+                            gr.gr_sssp_ex(G.handle, src, out, loop=lp, direction=d, layout=lay, relax_filter=rf,
+                                          **kw)
+                            np.testing.assert_array_equal(host(out), dist, err_msg=tag)
+            for lp in (gr.GR_LOOP_HOST, gr.GR_LOOP_QUEUED, gr.GR_LOOP_ASYNC):
+                say("golden bfs %s src=%d loop=%d" % (name, src, lp))
+                out = fresh(g.n)
+                kw = dict(barrier_timeout_us=5_000_000) if lp != gr.GR_LOOP_HOST else {}
+                gr.gr_bfs_ex(G.handle, src, out, loop=lp, **kw)
+                np.testing.assert_array_equal(host(out), hops, err_msg="bfs %s src=%d loop=%d" % (name, src, lp))
+        srcs = [q[0] for q in queries]
+        say("golden batch %s sources=%s" % (name, srcs))
+        out = torch.full((len(srcs), g.n), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+        gr.gr_sssp_batch(G.handle, np.asarray(srcs, np.int32), out)
+        got = host(out)
+        for i, (src, dist, _) in enumerate(queries):
+            np.testing.assert_array_equal(got[i], dist, err_msg="batch %s src=%d" % (name, src))
+    finally:
+        G.close()

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 from hypothesis import given, settings, strategies as st, HealthCheck
 
+import golden_fixtures
 import graphgen as gg
 import oracle
 from oracle import brute
@@ -78,6 +79,23 @@ def test_fp32_rounding_order_hand_example():
     # (1 + 2^-23) + 2^-24 is a tie between 1 + 2^-23 (odd) and 1 + 2^-22 (even): rounds up
     g2 = gg.from_arcs(3, [(0, 1, 1.0 + 2 * e24), (1, 2, e24)], wtype=gg.W_F32)
     assert as_f32(oracle.dijkstra(g2, 0))[2] == np.float32(1.0 + 4 * e24)
+
+
+@pytest.mark.parametrize("name", golden_fixtures.names())
+def test_hand_derived_golden_fixtures(name):
+    # distances and hop counts worked out by hand in tests/golden/ (the paper
+    # prints no numeric example); the BSP loop must reach the same fixed point
+    g, queries = golden_fixtures.load(name)
+    assert queries
+    for src, dist, hops in queries:
+        np.testing.assert_array_equal(oracle.dijkstra(g, src), dist, err_msg="%s from %d" % (name, src))
+        np.testing.assert_array_equal(oracle.bsp(g, src)[0], dist, err_msg="bsp %s from %d" % (name, src))
+        np.testing.assert_array_equal(oracle.bfs(g, src), hops, err_msg="bfs %s from %d" % (name, src))
+
+
+def test_golden_fixture_inf_encodings_match_the_oracle():
+    assert golden_fixtures.INF_U32 == oracle.inf_bits(gg.W_U32)
+    assert golden_fixtures.INF_F32_BITS == oracle.inf_bits(gg.W_F32)
 
 
 def test_star_and_components_and_isolated_source():
