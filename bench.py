@@ -316,6 +316,29 @@ def counter_traffic(kernel, workload, loop, layout, relax):
         return None
 
 
+def batch_traffic(workload):
+    """HBM bytes of one whole 64-source gr_sssp_batch call (every kernel it
+    launches) from the committed counter summary, or None when the summary is
+    missing or the kernel sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_batch_push_%s_counters.md" % workload)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    src = "".join(open(os.path.join(ROOT, "paper_2212_08200_amd", "csrc", f)).read()
+                  for f in ("gr_kernels.hip", "gr_device.h", "gr_internal.h", "gr_batch.hip"))
+    if fields.get("batch_sources_sha256") != hashlib.sha256(src.encode()).hexdigest():
+        return None
+    try:
+        return int(fields["traffic_bytes_per_batch_call"])
+    except (KeyError, ValueError):
+        return None
+
+
 def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev):
     """64 sources in one gr_sssp_batch launch vs the same 64 as looped single queries."""
     k = len(srcs)
@@ -331,9 +354,16 @@ def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev):
     ms = 1e3 * (time.perf_counter() - t0) / reps
     edges = sum(reached[s] for s in srcs)
     looped_ms = single_ms * k
-    return {"k": k, "ms_per_launch": round(ms, 3), "gteps": round(edges / (ms * 1e-3) / 1e9, 3),
-            "looped_ms": round(looped_ms, 3), "looped_gteps": round(edges / (looped_ms * 1e-3) / 1e9, 3),
-            "speedup_vs_looped": round(looped_ms / ms, 3)}
+    res = {"k": k, "ms_per_launch": round(ms, 3), "gteps": round(edges / (ms * 1e-3) / 1e9, 3),
+           "looped_ms": round(looped_ms, 3), "looped_gteps": round(edges / (looped_ms * 1e-3) / 1e9, 3),
+           "speedup_vs_looped": round(looped_ms / ms, 3)}
+    traffic = batch_traffic("rmat22") if k == 64 else None
+    if traffic:
+        # counted HBM bytes of one call (rocprofv3, copy-calibrated) over this run's call time
+        res["hbm_bytes_per_launch"] = traffic
+        res["hbm_gbs"] = round(traffic / (ms * 1e-3) / 1e9, 1)
+        res["hbm_frac"] = round(traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return res
 
 
 def measure_serving(args, torch, np, gr, gg, dev):
