@@ -1,8 +1,8 @@
 """GPU results on the hand-derived fixtures of tests/golden/, compared with the
 values written in the files (not with the oracle): every direction policy,
 push layout, loop driver (the asynchronous one included) and relaxation
-filter for SSSP, the batched call over all of a fixture's sources, and BFS
-hop counts."""
+filter for SSSP, the batched call over all of a fixture's sources, BFS hop
+counts, and queries served together by one query server."""
 import sys
 
 import numpy as np
@@ -68,3 +68,39 @@ def test_golden_fixture_on_gpu(name):
             np.testing.assert_array_equal(got[i], dist, err_msg="batch %s src=%d" % (name, src))
     finally:
         G.close()
+
+
+def test_golden_fixtures_served():
+    # every fixture query, submitted four times over in an interleaved stream to
+    # one server holding all fixture graphs, so that queries share batches
+    import time
+    loaded = [golden_fixtures.load(nm) for nm in golden_fixtures.names()]
+    Gs = [gr.Graph.from_csr(g) for g, _ in loaded]
+    server = gr.gr_server_create(1 << 30, max_batch=8, num_streams=2, max_wait_us=500)
+    try:
+        gids = [gr.gr_server_add_graph(server, G.handle) for G in Gs]
+        reqs = []
+        for rep in range(4):
+            for gi, (g, queries) in enumerate(loaded):
+                for src, dist, _ in queries:
+                    out = fresh(g.n)
+                    reqs.append((gr.gr_serve_submit(server, gids[gi], src, out), gi, src, dist, out))
+        say("golden served: %d queries on %d graphs" % (len(reqs), len(Gs)))
+        pending = {r[0] for r in reqs}
+        res = {}
+        t0 = time.time()
+        while pending:
+            for t in list(pending):
+                r = gr.gr_serve_poll(server, t)
+                if r is not None:
+                    res[t] = r
+                    pending.discard(t)
+            assert time.time() - t0 < 60, "%d served queries pending" % len(pending)
+            time.sleep(0.0005)
+        for t, gi, src, dist, out in reqs:
+            assert res[t]["status"] == gr.GR_OK and res[t]["graph_id"] == gids[gi] and res[t]["src"] == src
+            np.testing.assert_array_equal(host(out), dist, err_msg="served %s src=%d" % (loaded[gi][0].name, src))
+    finally:
+        gr.gr_server_destroy(server)
+        for G in Gs:
+            G.close()
