@@ -72,7 +72,7 @@ def test_golden_fixture_on_gpu(name):
 
 def test_golden_fixtures_served():
     # every fixture query, submitted four times over in an interleaved stream to
-    # one server holding all fixture graphs, so that queries share batches
+    # one server holding all fixture graphs, so that queries can share batches
     import time
     loaded = [golden_fixtures.load(nm) for nm in golden_fixtures.names()]
     Gs = [gr.Graph.from_csr(g) for g, _ in loaded]
