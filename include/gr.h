@@ -277,7 +277,11 @@ gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, void *strea
  *   k         1 <= k <= 64
  *   dist_out  device memory, k x n row-major: row i holds the result of srcs[i]
  * Row i is bit-identical to gr_sssp(g, srcs[i], ...).  Ordered on `stream`;
- * complete after stream synchronisation.
+ * complete after stream synchronisation (the host also waits for the stream
+ * once per round, to size the next launch).  Workspace: 274 bytes per vertex
+ * (64 distance slots, two 64-bit source masks, two flag bytes) plus 12 per
+ * vertex with out-arcs (the frontier queue), whatever k is, taken
+ * stream-ordered from the device pool and returned before the call ends.
  */
 gr_status gr_sssp_batch(const gr_graph *g, const int32_t *srcs, int32_t k, void *dist_out, void *stream);
 
