@@ -101,11 +101,18 @@ gr_status gr_graph_create_csr(gr_graph **out, int32_t n, int32_t m, const int32_
 /* Frees the graph's device memory.  No query on it may still be running. */
 gr_status gr_graph_destroy(gr_graph *g);
 
-/* Any output pointer may be NULL.  has_csc: 1 when a separate transposed copy
- * is stored, 0 when the CSR serves pull too (symmetric) or pull is off.
- * partitions: 8 when the partitioned push layout exists, else 1. */
-gr_status gr_graph_info(const gr_graph *g, int32_t *n, int32_t *m, int32_t *wt, size_t *dev_bytes,
-                        int32_t *has_csc, int32_t *pull_enabled, int32_t *partitions);
+/* Size, weight type and device footprint of a graph (the dimensions of the
+ * csr_t of Section IV-A, Listing 1).  Any output pointer may be NULL.
+ * dev_bytes counts every device allocation the graph holds (CSR, transposed
+ * copy, partitioned push layout, membership lists). */
+gr_status gr_graph_info(const gr_graph *g, int32_t *n, int32_t *m, gr_weight_type *wt, size_t *dev_bytes);
+
+/* Which traversal structures were built (see gr_graph_create_csr).  Any output
+ * pointer may be NULL.  has_csc: 1 when a separate transposed copy is stored,
+ * 0 when the CSR serves pull too (symmetric) or pull is off.  pull_enabled:
+ * 1 unless the graph was built with GR_NO_PULL.  partitions: 8 when the
+ * partitioned push layout exists, else 1. */
+gr_status gr_graph_layout(const gr_graph *g, int32_t *has_csc, int32_t *pull_enabled, int32_t *partitions);
 
 /*
  * Single-source shortest paths from src (Section IV-D, Listing 4).
@@ -302,6 +309,9 @@ typedef struct {
     int64_t t_submit_ns; /* CLOCK_MONOTONIC times */
     int64_t t_start_ns;
     int64_t t_done_ns;
+    int32_t iterations;  /* advance/filter rounds of the launch that served the query (for the
+                            asynchronous loop: worklist phases) */
+    int32_t reserved;
 } gr_query_result;
 
 /* A query server: resident graphs, admission by device-memory footprint,

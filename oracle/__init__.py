@@ -12,7 +12,6 @@ Exports
                             with round / relaxation / frontier statistics
 ``certify(g, src, dist)``   O(n+m) certificate that ``dist`` is the
                             shortest-path vector (conditions in ``oracle.c``)
-``reached_edges(g, dist)``  out-degree sum of reached vertices (TEPS numerator)
 ``bfs(g, src)``             textbook FIFO breadth-first search depths (C)
 ``brute``                   tiny-input references written independently in
                             Python: Bellman-Ford, Floyd-Warshall and exhaustive
@@ -77,8 +76,6 @@ def _load():
             lib.oracle_dijkstra.argtypes = [i32, vp, vp, vp, ctypes.c_int, i32, vp]
             lib.oracle_bsp.argtypes = [i32, vp, vp, vp, ctypes.c_int, i32, ctypes.c_int64, vp, vp]
             lib.oracle_certify.argtypes = [i32, vp, vp, vp, ctypes.c_int, i32, vp, vp]
-            lib.oracle_reached_edges.argtypes = [i32, vp, ctypes.c_int, vp]
-            lib.oracle_reached_edges.restype = ctypes.c_int64
             lib.oracle_bfs.argtypes = [i32, vp, vp, i32, vp]
             _lib = lib
     return _lib
@@ -149,10 +146,3 @@ def certify(g, src: int, dist) -> tuple[int, int]:
     if rc < 0:
         raise MemoryError("oracle_certify allocation failed")
     return int(rc), int(bad.value)
-
-
-def reached_edges(g, dist) -> int:
-    lib = _load()
-    ro = np.ascontiguousarray(g.ro, dtype=np.int32)
-    d = np.ascontiguousarray(dist, dtype=np.uint32)
-    return int(lib.oracle_reached_edges(g.n, ro.ctypes.data, g.wtype, d.ctypes.data))

@@ -308,15 +308,6 @@ int oracle_certify(int32_t n, const int32_t *ro, const int32_t *col, const uint3
     return rc;
 }
 
-/* Out-degree sum over vertices with dist != INF (edges "traversed" for TEPS). */
-int64_t oracle_reached_edges(int32_t n, const int32_t *ro, int wtype, const uint32_t *dist) {
-    const uint32_t INF = wtype == 0 ? INF_U32 : f_to_bits(FLT_MAX);
-    int64_t s = 0;
-    for (int32_t v = 0; v < n; ++v)
-        if (dist[v] != INF) s += ro[v + 1] - ro[v];
-    return s;
-}
-
 /* Breadth-first search from src (Section III-C names BFS as the other vertex
  * program on the same operators): depth[v] = fewest arcs on a path src -> v,
  * 0xFFFFFFFF when v is unreachable.  Textbook FIFO-queue BFS; arc weights are

@@ -71,7 +71,8 @@ GR_DIR_PULL = 2
 GR_DIR_ALTERNATE = 3
 
 EXPORTED = [
-    "gr_graph_create_csr", "gr_graph_destroy", "gr_graph_info", "gr_graph_tune", "gr_sssp", "gr_sssp_ex",
+    "gr_graph_create_csr", "gr_graph_destroy", "gr_graph_info", "gr_graph_layout", "gr_graph_tune", "gr_sssp",
+    "gr_sssp_ex",
     "gr_bfs", "gr_bfs_ex", "gr_sssp_batch",
     "gr_server_create", "gr_server_add_graph", "gr_serve_submit", "gr_serve_poll", "gr_server_destroy",
     "gr_status_string", "gr_last_error", "gr_version",
@@ -127,7 +128,7 @@ class gr_server_config(ctypes.Structure):
 class gr_query_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("graph_id", ctypes.c_int32), ("src", ctypes.c_int32),
                 ("batch_size", ctypes.c_int32), ("t_submit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
-                ("t_done_ns", ctypes.c_int64)]
+                ("t_done_ns", ctypes.c_int64), ("iterations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -150,7 +151,8 @@ def lib():
             sigs = {
                 "gr_graph_create_csr": [P(vp), i32, i32, vp, vp, vp, ctypes.c_int, u32, vp],
                 "gr_graph_destroy": [vp],
-                "gr_graph_info": [vp, P(i32), P(i32), P(i32), P(ctypes.c_size_t), P(i32), P(i32), P(i32)],
+                "gr_graph_info": [vp, P(i32), P(i32), P(ctypes.c_int), P(ctypes.c_size_t)],
+                "gr_graph_layout": [vp, P(i32), P(i32), P(i32)],
                 "gr_graph_tune": [vp, vp, i32, i32, vp, P(gr_tune_result)],
                 "gr_sssp": [vp, i32, vp, vp],
                 "gr_sssp_ex": [vp, i32, vp, vp, P(gr_sssp_opts), P(gr_sssp_stats)],
@@ -244,12 +246,41 @@ def gr_graph_destroy(g: int) -> None:
 
 
 def gr_graph_info(g: int) -> dict:
-    n, m, wt, hc, pe, pa = (ctypes.c_int32() for _ in range(6))
+    """gr_graph_info and gr_graph_layout of one graph, as one dict."""
+    n, m, hc, pe, pa = (ctypes.c_int32() for _ in range(5))
+    wt = ctypes.c_int()
     db = ctypes.c_size_t()
-    _check(lib().gr_graph_info(g, ctypes.byref(n), ctypes.byref(m), ctypes.byref(wt), ctypes.byref(db),
-                               ctypes.byref(hc), ctypes.byref(pe), ctypes.byref(pa)))
+    _check(lib().gr_graph_info(g, ctypes.byref(n), ctypes.byref(m), ctypes.byref(wt), ctypes.byref(db)))
+    _check(lib().gr_graph_layout(g, ctypes.byref(hc), ctypes.byref(pe), ctypes.byref(pa)))
     return dict(n=n.value, m=m.value, wt=wt.value, dev_bytes=db.value, has_csc=bool(hc.value),
                 pull_enabled=bool(pe.value), partitions=pa.value)
+
+
+def gr_graph_layout(g: int) -> dict:
+    hc, pe, pa = (ctypes.c_int32() for _ in range(3))
+    _check(lib().gr_graph_layout(g, ctypes.byref(hc), ctypes.byref(pe), ctypes.byref(pa)))
+    return dict(has_csc=bool(hc.value), pull_enabled=bool(pe.value), partitions=pa.value)
+
+
+def _graph_n(g: int) -> int:
+    n = ctypes.c_int32()
+    _check(lib().gr_graph_info(g, ctypes.byref(n), None, None, None))
+    return n.value
+
+
+def _out_ptr(x, need: int, what: str) -> int | None:
+    """Address of an output buffer of `need` 32-bit values.  Torch tensors are
+    checked on the host (device memory, 4-byte elements, contiguous, large
+    enough) so that a wrong buffer is an error instead of an out-of-bounds
+    write on the device; raw integer addresses are the caller's promise."""
+    if hasattr(x, "data_ptr") and hasattr(x, "is_cuda"):
+        ok = (x.is_cuda and x.element_size() == 4 and x.is_contiguous() and x.numel() >= need)
+        if not ok:
+            raise GrError(GR_ERR_INVALID_ARG, "%s must be a contiguous device tensor of >= %d 4-byte elements "
+                          "(got device %s, dtype %s, %d elements, contiguous %s)" % (
+                              what, need, x.device, x.dtype, x.numel(), x.is_contiguous()))
+        return int(x.data_ptr())
+    return _ptr(x)
 
 
 def gr_graph_tune(g: int, srcs, reps=3, stream=None) -> dict:
@@ -264,7 +295,7 @@ def gr_graph_tune(g: int, srcs, reps=3, stream=None) -> dict:
 # ---- queries ----------------------------------------------------------------
 
 def gr_sssp(g: int, src: int, dist_out, stream=None) -> None:
-    _check(lib().gr_sssp(g, int(src), _ptr(dist_out), _stream(stream)))
+    _check(lib().gr_sssp(g, int(src), _out_ptr(dist_out, _graph_n(g), "dist_out"), _stream(stream)))
 
 
 def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
@@ -276,12 +307,13 @@ def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direc
                      timing=timing, filter=filter, barrier_timeout_us=barrier_timeout_us, delta=delta,
                      relax_filter=relax_filter)
     st = gr_sssp_stats()
-    _check(lib().gr_sssp_ex(g, int(src), _ptr(dist_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
+    _check(lib().gr_sssp_ex(g, int(src), _out_ptr(dist_out, _graph_n(g), "dist_out"), _stream(stream),
+                            ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()
 
 
 def gr_bfs(g: int, src: int, depth_out, stream=None) -> None:
-    _check(lib().gr_bfs(g, int(src), _ptr(depth_out), _stream(stream)))
+    _check(lib().gr_bfs(g, int(src), _out_ptr(depth_out, _graph_n(g), "depth_out"), _stream(stream)))
 
 
 def gr_bfs_ex(g: int, src: int, depth_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
@@ -289,13 +321,15 @@ def gr_bfs_ex(g: int, src: int, depth_out, stream=None, loop=GR_LOOP_AUTO, direc
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
                      timing=timing, filter=filter, relax_filter=relax_filter, barrier_timeout_us=barrier_timeout_us)
     st = gr_sssp_stats()
-    _check(lib().gr_bfs_ex(g, int(src), _ptr(depth_out), _stream(stream), ctypes.byref(o), ctypes.byref(st)))
+    _check(lib().gr_bfs_ex(g, int(src), _out_ptr(depth_out, _graph_n(g), "depth_out"), _stream(stream),
+                           ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()
 
 
 def gr_sssp_batch(g: int, srcs, dist_out, stream=None) -> None:
     s = np.ascontiguousarray(srcs, dtype=np.int32)
-    _check(lib().gr_sssp_batch(g, s.ctypes.data if s.size else None, int(s.size), _ptr(dist_out), _stream(stream)))
+    out = _out_ptr(dist_out, _graph_n(g) * max(int(s.size), 1), "dist_out")
+    _check(lib().gr_sssp_batch(g, s.ctypes.data if s.size else None, int(s.size), out, _stream(stream)))
 
 
 # ---- serving ----------------------------------------------------------------
@@ -307,15 +341,21 @@ def gr_server_create(hbm_budget_bytes: int, max_batch=0, num_streams=0, max_wait
     return h.value
 
 
+_server_n = {}  # (server, graph id) -> vertex count, for the output checks of gr_serve_submit
+
+
 def gr_server_add_graph(server: int, g: int) -> int:
     gid = ctypes.c_int32()
     _check(lib().gr_server_add_graph(server, g, ctypes.byref(gid)))
+    _server_n[(server, gid.value)] = _graph_n(g)
     return gid.value
 
 
 def gr_serve_submit(server: int, graph_id: int, src: int, dist_out) -> int:
     t = ctypes.c_uint64()
-    _check(lib().gr_serve_submit(server, int(graph_id), int(src), _ptr(dist_out), ctypes.byref(t)))
+    need = _server_n.get((server, int(graph_id)), 0)
+    _check(lib().gr_serve_submit(server, int(graph_id), int(src), _out_ptr(dist_out, need, "dist_out"),
+                                 ctypes.byref(t)))
     return t.value
 
 
@@ -328,6 +368,8 @@ def gr_serve_poll(server: int, ticket: int):
 
 def gr_server_destroy(server: int) -> None:
     _check(lib().gr_server_destroy(server))
+    for key in [k for k in _server_n if k[0] == server]:
+        del _server_n[key]
 
 
 def gr_status_string(s: int) -> str:

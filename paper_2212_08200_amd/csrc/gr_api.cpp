@@ -440,13 +440,19 @@ extern "C" gr_status gr_graph_destroy(gr_graph *g) {
     return GR_OK;
 }
 
-extern "C" gr_status gr_graph_info(const gr_graph *g, int32_t *n, int32_t *m, int32_t *wt, size_t *dev_bytes,
-                                   int32_t *has_csc, int32_t *pull_enabled, int32_t *partitions) {
+extern "C" gr_status gr_graph_info(const gr_graph *g, int32_t *n, int32_t *m, gr_weight_type *wt,
+                                   size_t *dev_bytes) {
     if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
     if (n) *n = g->plain.n;
     if (m) *m = g->plain.m;
-    if (wt) *wt = g->plain.wt;
+    if (wt) *wt = static_cast<gr_weight_type>(g->plain.wt);
     if (dev_bytes) *dev_bytes = g->dev_bytes;
+    return GR_OK;
+}
+
+extern "C" gr_status gr_graph_layout(const gr_graph *g, int32_t *has_csc, int32_t *pull_enabled,
+                                     int32_t *partitions) {
+    if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
     if (has_csc) *has_csc = g->csc_separate ? 1 : 0;
     if (pull_enabled) *pull_enabled = g->pull ? 1 : 0;
     if (partitions) *partitions = g->has_part ? kMaxParts : 1;
@@ -1024,7 +1030,7 @@ struct BatchStats {
 // per iteration to read the frontier size.
 static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, uint32_t *const *out_rows,
                            hipStream_t st, int64_t max_iters, BatchStats *bs) {
-    if (k == 1 && !bs) {
+    if (k == 1) {
         // one source: the single-source path with the graph's AUTO schedule
         // (its loop needs no host round trip per round)
         RunCfg rc;
@@ -1032,10 +1038,16 @@ static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, ui
         if (s != GR_OK) return s;
         rc.max_iters = max_iters;
         const int loop = g->auto_loop;
-        if (loop == GR_LOOP_ASYNC) return run_async(g, srcs[0], out_rows[0], st, rc, nullptr);
-        if (loop == GR_LOOP_QUEUED) return run_queued(g, srcs[0], out_rows[0], st, rc, nullptr);
-        if (loop == GR_LOOP_PERSISTENT) return run_persistent(g, srcs[0], out_rows[0], st, rc, nullptr);
-        return run_host_loop(g, srcs[0], out_rows[0], st, rc, nullptr);
+        gr_sssp_stats one{};
+        if (loop == GR_LOOP_ASYNC) s = run_async(g, srcs[0], out_rows[0], st, rc, &one);
+        else if (loop == GR_LOOP_QUEUED) s = run_queued(g, srcs[0], out_rows[0], st, rc, &one);
+        else if (loop == GR_LOOP_PERSISTENT) s = run_persistent(g, srcs[0], out_rows[0], st, rc, &one);
+        else s = run_host_loop(g, srcs[0], out_rows[0], st, rc, &one);
+        if (bs) {
+            bs->iterations = one.iterations;
+            bs->edges = one.edges_pushed;
+        }
+        return s;
     }
     DeviceInfo di;
     gr_status s = device_info(g->device, &di);
@@ -1165,7 +1177,8 @@ static void server_worker(gr_server *s, int slot) {
             t.res.batch_size = k;
         }
         lk.unlock();
-        const gr_status rc = run_batch(g, srcs.data(), k, rows.data(), st, (int64_t)g->plain.n + 1, nullptr);
+        BatchStats bst;
+        const gr_status rc = run_batch(g, srcs.data(), k, rows.data(), st, (int64_t)g->plain.n + 1, &bst);
         const int64_t t_done = now_ns();
         lk.lock();
         s->in_flight -= b.bytes;
@@ -1174,6 +1187,7 @@ static void server_worker(gr_server *s, int slot) {
             t.state = kDone;
             t.res.status = rc;
             t.res.t_done_ns = t_done;
+            t.res.iterations = bst.iterations;
         }
         s->cv.notify_all();
     }

@@ -50,6 +50,34 @@ def test_python_binding_names_match_the_c_abi():
         assert hasattr(gr, n), "binding lacks %s" % n
 
 
+STRUCTS = ["gr_sssp_opts", "gr_sssp_stats", "gr_tune_result", "gr_server_config", "gr_query_result"]
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct of gr.h has the size and field offsets the ctypes binding
+    assumes: a C program compiled against the header prints them."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gr.h"', "int main(void) {"]
+    for name in STRUCTS:
+        cls = getattr(gr, name)
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for field, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, field, name, field))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for name in STRUCTS:
+        cls = getattr(gr, name)
+        assert int(got["%s size" % name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got["%s.%s" % (name, field)]) == getattr(cls, field).offset, (name, field)
+    # the served-query result carries the iteration count of the launch that served it
+    assert "iterations" in dict(gr.gr_query_result._fields_)
+
+
 def test_status_strings(lib):
     assert gr.gr_status_string(gr.GR_OK) == "GR_OK"
     assert gr.gr_status_string(gr.GR_ERR_SOURCE_RANGE) == "GR_ERR_SOURCE_RANGE"
@@ -93,7 +121,8 @@ def test_bad_arguments_rejected(lib):
     assert L.gr_graph_create_csr(ctypes.byref(h), 1, 2, ro.ctypes.data, None, None, 0, 0, None) == gr.GR_ERR_INVALID_ARG
     assert L.gr_sssp(None, 0, None, None) == gr.GR_ERR_INVALID_ARG
     assert L.gr_graph_destroy(None) == gr.GR_ERR_INVALID_ARG
-    assert L.gr_graph_info(None, None, None, None, None, None, None, None) == gr.GR_ERR_INVALID_ARG
+    assert L.gr_graph_info(None, None, None, None, None) == gr.GR_ERR_INVALID_ARG
+    assert L.gr_graph_layout(None, None, None, None) == gr.GR_ERR_INVALID_ARG
 
 
 def test_last_error_is_per_thread(lib):

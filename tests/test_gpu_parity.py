@@ -10,6 +10,7 @@ import pytest
 
 import graphgen as gg
 import oracle
+from certify_rows import certify_all, dijkstra_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -299,6 +300,45 @@ def test_grid2048_config_device_loops():
 def test_rmat22_config_sampled_sources():
     g, srcs = gg.workload("rmat22")
     check_all_dirs(g, srcs[:2], "rmat22", dirs=("auto", "push"), flags=0)
+
+
+def test_rmat22_all_bench_sources_tuned_schedule():
+    """The benchmark's workload exactly: the graph tuned as the benchmark tunes
+    it, then every one of its 64 sources through gr_sssp (the tuned AUTO
+    schedule), each result certified; four also equal the oracle's Dijkstra."""
+    g, srcs = gg.workload("rmat22")
+    G = gr.Graph.from_csr(g)
+    try:
+        tuned = G.tune([int(s) for s in srcs[:4]], reps=2)
+        say("rmat22 tuned schedule: %s" % tuned)
+        rows = []
+        for i, s in enumerate(srcs):
+            d = torch.full((g.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+            gr.gr_sssp(G.handle, int(s), d)
+            torch.cuda.synchronize()
+            rows.append(d.cpu().numpy().view(np.uint32))
+        say("rmat22: certificate on all 64 tuned results")
+        certify_all(g, srcs, rows, "rmat22 tuned", workers=12)
+        say("rmat22: Dijkstra on 4 tuned results")
+        dijkstra_rows(g, srcs, rows, (0, 17, 38, 63), "rmat22 tuned")
+    finally:
+        G.close()
+
+
+def test_rmat22_asynchronous_loop():
+    g, srcs = gg.workload("rmat22")
+    G = gr.Graph.from_csr(g)
+    try:
+        rows = []
+        for s in srcs[:3]:
+            say("rmat22 asynchronous loop src=%d" % int(s))
+            got, st = run(G, s, DIRS["push"], loop=gr.GR_LOOP_ASYNC)
+            assert st["loop"] == gr.GR_LOOP_ASYNC
+            rows.append(got)
+        certify_all(g, srcs[:3], rows, "rmat22 async")
+        dijkstra_rows(g, srcs[:3], rows, (0, 2), "rmat22 async")
+    finally:
+        G.close()
 
 
 # ------------------------------------------------------------ near-far split
