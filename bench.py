@@ -23,8 +23,16 @@ Prints ONE JSON line on stdout:
               the committed rocprofv3 counter summary when it matches the
               current kernel sources, else null; query_gbs / query_frac: the
               query's algorithmic bytes over the timed wall clock.
-  cpu_baseline  the CPU oracle (binary-heap Dijkstra, one core) on a bounded
-              sample of the same workload's sources
+  cpu_baseline  the CPU oracle (binary-heap Dijkstra) on the host's cores, one
+              thread per source, over a bounded sample of the same workload's
+              sources (core count and CPU model stated)
+  batched     64 sources in one gr_sssp_batch call against the same 64 run
+              as looped single queries
+  configs     the other configurations (grid 64^2, R-MAT 20 binary32,
+              road-like 2048^2, plain grid 2048^2), single queries with the
+              graph's AUTO schedule: ms, GTEPS, rounds, relaxation inflation
+              and kernel roofline
+  serving     32 resident graphs under open-loop Poisson arrivals
 Progress goes to stderr.
 """
 import argparse
@@ -76,6 +84,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-source batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the single-query timings of the other configurations (grid 64^2, R-MAT 20 "
+                         "binary32, road-like 2048^2, grid 2048^2)")
     ap.add_argument("--serve-queries", type=int, default=1500, help="open-loop queries per load level")
     ap.add_argument("--serve-streams", type=int, default=4, help="server: concurrent batches on the device")
     ap.add_argument("--serve-wait-us", type=int, default=200, help="server: longest wait of a partial batch")
@@ -222,20 +233,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        t_cpu = 0.0
-        e_cpu = 0
-        done = 0
-        while done < len(srcs) and (t_cpu < args.cpu_seconds or done == 0):
-            s = srcs[done]
-            t1 = time.perf_counter()
-            d = oracle.dijkstra(g, s)
-            t_cpu += time.perf_counter() - t1
-            e_cpu += int(deg[d != inf].sum())
-            done += 1
-        cpu = {"value": round(e_cpu / t_cpu / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": "%d of %d sources on the full graph, %.1f s of single-thread binary-heap Dijkstra"
-                         % (done, len(srcs), t_cpu)}
+        cpu = cpu_baseline(g, srcs, deg, inf, args.cpu_seconds)
         log("cpu oracle: %s" % cpu)
 
     batched = None
@@ -245,11 +243,18 @@ def main():
                 gr.gr_sssp_ex(G.handle, s, dist, stream=stream, **opts)
                 d = dist.cpu().numpy().view(np.uint32)
                 reached[s] = int(deg[d != inf].sum())
-        batched = measure_batched(G, g, srcs, reached, ms_per_step, torch, np, gr, dev)
+        batched = measure_batched(G, g, srcs, reached, ms_per_step, torch, np, gr, dev, opts)
         log("batched: %s" % batched)
     G.close()
     del dist
     torch.cuda.empty_cache()
+
+    configs = None
+    if not args.no_configs and args.workload == "rmat22" and not args.bfs:
+        configs = {}
+        for name, steps in (("grid64", 100), ("rmat20", 20), ("road2048", 10), ("grid2048", 3)):
+            configs[name] = measure_config(name, steps, torch, np, gr, gg, dev)
+            log("config %s: %s" % (name, configs[name]))
 
     serving = None
     if not args.no_serving:
@@ -286,9 +291,127 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,
+        "configs": configs,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def host_cpu():
+    """Threads the CPU legs may use on this host (the process's affinity set, and
+    no more than OMP_NUM_THREADS when that is set) and the host's CPU model."""
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        cores = min(cores, int(omp))
+    model = "?"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return max(cores, 1), model
+
+
+def cpu_baseline(g, srcs, deg, inf, seconds):
+    """The CPU oracle (binary-heap Dijkstra, oracle.dijkstra) on the host cores:
+    one thread per source (the oracle is C called through ctypes, which releases
+    the GIL), as many sources as there are threads per wave, waves until about
+    `seconds` of wall time have passed; value = reached arcs / wall time.  A
+    single-thread figure on the first source is reported beside it."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    cores, model = host_cpu()
+    t1 = time.perf_counter()
+    d = oracle.dijkstra(g, srcs[0])
+    one_s = time.perf_counter() - t1
+    one_edges = int(deg[d != inf].sum())
+
+    def job(s):
+        dd = oracle.dijkstra(g, s)
+        return int(deg[dd != inf].sum())
+
+    done, edges = 0, 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        while done < len(srcs):
+            wave = srcs[done:done + cores]
+            edges += sum(ex.map(job, wave))
+            done += len(wave)
+            if time.perf_counter() - t0 >= seconds:
+                break
+    wall = time.perf_counter() - t0
+    return {"value": round(edges / wall / 1e9, 5), "unit": "GTEPS", "cores": cores, "kind": "oracle",
+            "sample": "%d of the %d sources on the full graph, one thread per source on %d threads, %.1f s wall "
+                      "(binary-heap Dijkstra)" % (done, len(srcs), cores, wall),
+            "cpu_model": model, "nproc": os.cpu_count(),
+            "single_thread_gteps": round(one_edges / one_s / 1e9, 5)}
+
+
+def kernel_roofline(stats_list, wall_s, q_bytes):
+    """Kernel roofline from per-query statistics gathered with timing on: the
+    algorithmic bytes of the advance rounds (12 B per relaxed edge + 20 B per
+    frontier vertex) over the summed launch times of the dominant kernel."""
+    push_us, alg, launches, last = 0.0, 0, 0, None
+    for st in stats_list:
+        alg += 12 * st["edges_pushed"] + 20 * st["push_frontier_sum"]
+        if st["loop"] == 3:
+            push_us += st["push_us"] + st["filter_us"]
+            launches += st["launches"]
+        else:
+            push_us += st["push_us"]
+            launches += st["push_launches"]
+        last = st
+    if not launches or push_us <= 0:
+        return None
+    achieved = alg / (push_us * 1e-6) / 1e9
+    kern = {2: "k_persistent", 3: "k_step", 4: "k_async"}.get(last["loop"], "k_push")
+    return {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": int(alg / launches),
+            "avg_launch_us": round(push_us / launches, 2), "launches": launches,
+            "query_gbs": round(q_bytes / wall_s / 1e9, 1),
+            "query_frac": round(q_bytes / wall_s / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def measure_config(name, steps, torch, np, gr, gg, dev):
+    """One other configuration, single-source queries with the graph's AUTO
+    schedule: time per query (wall clock around `steps` queries), GTEPS,
+    rounds, relaxation inflation, and the dominant kernel's roofline."""
+    t0 = time.time()
+    g, srcs = gg.workload(name)
+    G = gr.Graph.from_csr(g)
+    gen_s = time.time() - t0
+    s = int(srcs[0])
+    inf = gr.GR_DIST_INF_F32_BITS if g.wtype == gr.GR_W_F32 else gr.GR_DIST_INF_U32
+    dist = torch.empty(g.n, dtype=torch.int32, device=dev)
+    st = gr.gr_sssp_ex(G.handle, s, dist)
+    d = dist.cpu().numpy().view(np.uint32)
+    reached = int(np.diff(g.ro).astype(np.int64)[d != inf].sum())
+    for _ in range(2):
+        gr.gr_sssp_ex(G.handle, s, dist)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = [gr.gr_sssp_ex(G.handle, s, dist) for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    q_bytes = sum(12 * x["edges_pushed"] + 20 * x["push_frontier_sum"] for x in stats)
+    timed = [gr.gr_sssp_ex(G.handle, s, dist, timing=1) for _ in range(min(steps, 5))]
+    torch.cuda.synchronize()
+    roof = kernel_roofline(timed, wall, q_bytes)
+    G.close()
+    last = stats[-1]
+    return {"workload": WORKLOADS[name], "n": g.n, "m": g.m, "src": s,
+            "loop": {1: "host", 2: "persistent", 3: "queued", 4: "async"}.get(last["loop"], "?"),
+            "ms_per_query": round(1e3 * wall / steps, 4), "queries": steps,
+            "gteps": round(reached * steps / wall / 1e9, 4),
+            "rounds": last["iterations"], "relaxations": last["edges_pushed"],
+            "relaxation_inflation": round(last["edges_pushed"] / max(reached, 1), 3),
+            "roofline": roof, "setup_s": round(gen_s, 1)}
 
 
 def counter_traffic(kernel, workload, loop, layout, relax):
@@ -339,7 +462,7 @@ def batch_traffic(workload):
         return None
 
 
-def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev):
+def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev, opts):
     """64 sources in one gr_sssp_batch launch vs the same 64 as looped single queries."""
     k = len(srcs)
     out = torch.empty((k, g.n), dtype=torch.int32, device=dev)
@@ -353,7 +476,13 @@ def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev):
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
     edges = sum(reached[s] for s in srcs)
-    looped_ms = single_ms * k
+    # the same k sources as k single queries, one after the other, each into its own row
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, s in enumerate(srcs):
+        gr.gr_sssp_ex(G.handle, s, out[i], **opts)
+    torch.cuda.synchronize()
+    looped_ms = 1e3 * (time.perf_counter() - t0)
     res = {"k": k, "ms_per_launch": round(ms, 3), "gteps": round(edges / (ms * 1e-3) / 1e9, 3),
            "looped_ms": round(looped_ms, 3), "looped_gteps": round(edges / (looped_ms * 1e-3) / 1e9, 3),
            "speedup_vs_looped": round(looped_ms / ms, 3)}
