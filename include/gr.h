@@ -127,6 +127,30 @@ gr_status gr_graph_layout(const gr_graph *g, int32_t *has_csc, int32_t *pull_ena
  */
 gr_status gr_sssp(const gr_graph *g, int32_t src, void *dist_out, void *stream);
 
+/*
+ * gr_sssp for callers that cannot allocate memory: code that is being
+ * captured into a HIP graph, tight serving loops, and harnesses that forbid
+ * hipMalloc.  Same arguments and result as gr_sssp; it calls no hipMalloc,
+ * hipFree, pool allocation or pinned-memory allocation, and creates no event.
+ *   - Workspace: a fixed array of 96 MiB (GR_NOALLOC_SCRATCH_BYTES) that the
+ *     library holds on every GPU it runs on until the process ends.  A query
+ *     needs about 20 bytes per vertex plus 2 MiB (the plain CSR layout, one
+ *     frontier queue); a graph whose workspace exceeds the array returns
+ *     GR_ERR_NO_CAPACITY before anything is enqueued.  Graphs of up to about
+ *     four million vertices fit.
+ *   - Schedule: the queued (device-driven) loop over the plain CSR layout,
+ *     without a near-far split; the direction, filter and relaxation-filter
+ *     defaults are the graph's.  The call waits for `stream` once per chunk
+ *     of launches and returns when the query has finished.
+ *   - The current device must be the graph's device (GR_ERR_INVALID_ARG).
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents (each call clears what it reads first).  Calls that
+ *     overlap on one GPU -- from other threads or on other streams -- race
+ *     and give wrong results; serialise them.
+ */
+#define GR_NOALLOC_SCRATCH_BYTES (96u << 20)
+gr_status gr_sssp_noalloc(const gr_graph *g, int32_t src, void *dist_out, void *stream);
+
 /* Loop schedule of gr_sssp_ex (Section III-A: execution policies). */
 typedef enum {
     GR_LOOP_AUTO = 0,       /* the library's choice: gr_graph_tune's if run, else the

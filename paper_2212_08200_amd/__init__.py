@@ -38,6 +38,7 @@ GR_W_U32 = 0
 GR_W_F32 = 1
 GR_DIST_INF_U32 = 0xFFFFFFFF
 GR_DIST_INF_F32_BITS = 0x7F7FFFFF
+GR_NOALLOC_SCRATCH_BYTES = 96 << 20
 
 GR_INPUT_DEVICE = 0x1
 GR_NO_PULL = 0x2
@@ -72,7 +73,7 @@ GR_DIR_ALTERNATE = 3
 
 EXPORTED = [
     "gr_graph_create_csr", "gr_graph_destroy", "gr_graph_info", "gr_graph_layout", "gr_graph_tune", "gr_sssp",
-    "gr_sssp_ex",
+    "gr_sssp_ex", "gr_sssp_noalloc",
     "gr_bfs", "gr_bfs_ex", "gr_sssp_batch",
     "gr_server_create", "gr_server_add_graph", "gr_serve_submit", "gr_serve_poll", "gr_server_destroy",
     "gr_status_string", "gr_last_error", "gr_version",
@@ -156,6 +157,7 @@ def lib():
                 "gr_graph_tune": [vp, vp, i32, i32, vp, P(gr_tune_result)],
                 "gr_sssp": [vp, i32, vp, vp],
                 "gr_sssp_ex": [vp, i32, vp, vp, P(gr_sssp_opts), P(gr_sssp_stats)],
+                "gr_sssp_noalloc": [vp, i32, vp, vp],
                 "gr_bfs": [vp, i32, vp, vp],
                 "gr_bfs_ex": [vp, i32, vp, vp, P(gr_sssp_opts), P(gr_sssp_stats)],
                 "gr_sssp_batch": [vp, vp, i32, vp, vp],
@@ -310,6 +312,12 @@ def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direc
     _check(lib().gr_sssp_ex(g, int(src), _out_ptr(dist_out, _graph_n(g), "dist_out"), _stream(stream),
                             ctypes.byref(o), ctypes.byref(st)))
     return st.as_dict()
+
+
+def gr_sssp_noalloc(g: int, src: int, dist_out, stream=None) -> None:
+    """gr_sssp without any allocation: the workspace is the library's fixed per-device array
+    (GR_NOALLOC_SCRATCH_BYTES); calls that overlap on one GPU race."""
+    _check(lib().gr_sssp_noalloc(g, int(src), _out_ptr(dist_out, _graph_n(g), "dist_out"), _stream(stream)))
 
 
 def gr_bfs(g: int, src: int, depth_out, stream=None) -> None:

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "gr_internal.h"
+#include "gr_noalloc.h"
 #include "gr_sched.h"
 
 using namespace gr;
@@ -969,6 +970,77 @@ extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, 
 
 extern "C" gr_status gr_sssp(const gr_graph *g, int32_t src, void *dist_out, void *stream) {
     return gr_sssp_ex(g, src, dist_out, stream, nullptr, nullptr);
+}
+
+// Allocation-free variant of the queued loop: the frontier workspace is the
+// device's fixed scratch array, the loop state is read into host stack memory
+// (one synchronising copy per chunk of launches), and no event, pool block or
+// pinned buffer is created.
+static gr_status run_queued_fixed(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
+                                  void *ws) {
+    DeviceInfo di;
+    gr_status s = device_info(g->device, &di);
+    if (s != GR_OK) return s;
+    const DevGraph &dg = *rc.dg;
+    PersistentCfg cfg;
+    cfg.grid = di.num_cu * 8;
+    cfg.max_iters = (int32_t)std::min<int64_t>(rc.max_iters, INT32_MAX);
+    cfg.alpha_x16 = rc.alpha_x16;
+    cfg.direction = rc.direction;
+    cfg.filter = rc.filter;
+    cfg.dense_ratio = rc.dense_ratio;
+    cfg.delta = 0;
+    cfg.spin_ticks = 0;
+    cfg.small = rc.small && g->max_degree <= kSmallMaxDegree &&
+                (rc.direction == GR_DIR_PUSH || (rc.direction == GR_DIR_AUTO && rc.alpha_x16 == 0));
+    Frontier f;
+    frontier_carve(f, ws, dg);
+    if (!rc.bound) f.bound = nullptr;
+    // k_init clears every flag, counter and control word the loop reads
+    hipError_t e = launch_init(dg, dist, src, f, kInfU32, false, st);
+    int64_t issued = 0;
+    int64_t K = std::clamp<int64_t>(g->last_iters.load(std::memory_order_relaxed) + 1, 4, 512);
+    LoopState ls{};
+    while (e == hipSuccess) {
+        for (int64_t i = 0; i < K && e == hipSuccess; ++i)
+            e = launch_step(dg, dist, f, cfg, issued + i, nullptr, 0, nullptr, nullptr, st);
+        issued += K;
+        if (e == hipSuccess) e = hipMemcpyAsync(&ls, f.ctl + kLoopStateWord, sizeof ls, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess || ls.status != 0) break;
+        K = std::min<int64_t>(64, 2 * K);
+    }
+    if (e != hipSuccess) return hip_fail(e, "allocation-free queued loop");
+    if (ls.status == 1)
+        g->last_iters.store((int32_t)std::min<int64_t>(2 * (int64_t)ls.iter - (int64_t)ls.small_rounds + 1, INT32_MAX),
+                            std::memory_order_relaxed);
+    if (ls.status == 2) return fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)rc.max_iters);
+    if (ls.status != 1) return fail(GR_ERR_HIP, "allocation-free loop ended in state %llu", ls.status);
+    return GR_OK;
+}
+
+extern "C" gr_status gr_sssp_noalloc(const gr_graph *g, int32_t src, void *dist_out, void *stream) {
+    if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
+    if (!dist_out) return fail(GR_ERR_INVALID_ARG, "dist_out is NULL");
+    if (src < 0 || src >= g->plain.n) return fail(GR_ERR_SOURCE_RANGE, "src = %d outside [0, %d)", src, g->plain.n);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != g->device)
+        return fail(GR_ERR_INVALID_ARG, "current device %d is not the graph's device %d", dev, g->device);
+    RunCfg rc;
+    gr_status s = check_opts(g, nullptr, &rc);
+    if (s != GR_OK) return s;
+    // plain layout (one queue), no near-far split: the smallest workspace
+    rc.dg = &g->plain;
+    rc.layout = GR_LAYOUT_PLAIN;
+    rc.delta = 0;
+    const size_t need = frontier_bytes(g->plain);
+    if (need > kNoAllocScratchBytes)
+        return fail(GR_ERR_NO_CAPACITY, "the query needs %zu bytes of workspace, the fixed scratch holds %zu", need,
+                    kNoAllocScratchBytes);
+    void *ws = nullptr;
+    HIP_TRY(noalloc_scratch(&ws));
+    return run_queued_fixed(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, ws);
 }
 
 // Breadth-first search: the same operators and loops over a unit-weight view
