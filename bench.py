@@ -87,9 +87,12 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the single-query timings of the other configurations (grid 64^2, R-MAT 20 "
                          "binary32, road-like 2048^2, grid 2048^2)")
-    ap.add_argument("--serve-queries", type=int, default=1500, help="open-loop queries per load level")
-    ap.add_argument("--serve-streams", type=int, default=4, help="server: concurrent batches on the device")
-    ap.add_argument("--serve-wait-us", type=int, default=200, help="server: longest wait of a partial batch")
+    ap.add_argument("--serve-queries", type=int, default=8000, help="open-loop queries per load level")
+    ap.add_argument("--serve-fifo-queries", type=int, default=1000,
+                    help="queries of each level's trace replayed through the one-at-a-time FIFO")
+    ap.add_argument("--serve-executors", type=int, default=1,
+                    help="server: executors (each a stream with its own multi-query session)")
+    ap.add_argument("--serve-slots", type=int, default=64, help="server: live queries per executor")
     ap.add_argument("--bfs", action="store_true",
                     help="time breadth-first search (gr_bfs_ex) instead of SSSP on the same workload")
     ap.add_argument("--no-tune", action="store_true",
@@ -444,7 +447,7 @@ def batch_traffic(workload):
     launches) from the committed counter summary, or None when the summary is
     missing or the kernel sources have changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_batch_push_%s_counters.md" % workload)
+    path = os.path.join(ROOT, "profiles", "k_mq_batch_push_%s_counters.md" % workload)
     if not os.path.exists(path):
         return None
     fields = {}
@@ -452,14 +455,21 @@ def batch_traffic(workload):
         if ":" in line and not line.startswith(("|", "#", "`")):
             k, _, v = line.partition(":")
             fields[k.strip()] = v.strip()
-    src = "".join(open(os.path.join(ROOT, "paper_2212_08200_amd", "csrc", f)).read()
-                  for f in ("gr_kernels.hip", "gr_device.h", "gr_internal.h", "gr_batch.hip"))
-    if fields.get("batch_sources_sha256") != hashlib.sha256(src.encode()).hexdigest():
+    if fields.get("batch_sources_sha256") != batch_sources_sha256(ROOT):
         return None
     try:
         return int(fields["traffic_bytes_per_batch_call"])
     except (KeyError, ValueError):
         return None
+
+
+def batch_sources_sha256(root=None):
+    """sha256 of the sources of the batched call's kernels."""
+    import hashlib
+    root = root or ROOT
+    src = "".join(open(os.path.join(root, "paper_2212_08200_amd", "csrc", f)).read()
+                  for f in ("gr_multi.hip", "gr_multi.h", "gr_device.h", "gr_internal.h"))
+    return hashlib.sha256(src.encode()).hexdigest()
 
 
 def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev, opts):
@@ -472,7 +482,7 @@ def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev, opts):
     reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
-        gr.gr_sssp_batch(G.handle, s_arr, out)
+        bst = gr.gr_sssp_batch_ex(G.handle, s_arr, out)
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
     edges = sum(reached[s] for s in srcs)
@@ -483,7 +493,14 @@ def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev, opts):
         gr.gr_sssp_ex(G.handle, s, out[i], **opts)
     torch.cuda.synchronize()
     looped_ms = 1e3 * (time.perf_counter() - t0)
+    # algorithmic bytes of the batch: 8 B per arc expansion (the arc, read once for
+    # every source active at its tail) + 4 B per (arc, active source) relaxation
+    alg = 8 * bst["edges_pushed"] + 4 * bst["source_relaxations"]
     res = {"k": k, "ms_per_launch": round(ms, 3), "gteps": round(edges / (ms * 1e-3) / 1e9, 3),
+           "rounds": bst["rounds"], "replays": bst["replays"], "arc_expansions": bst["edges_pushed"],
+           "source_relaxations": bst["source_relaxations"], "algorithmic_bytes": alg,
+           "algorithmic_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+           "algorithmic_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "looped_ms": round(looped_ms, 3), "looped_gteps": round(edges / (looped_ms * 1e-3) / 1e9, 3),
            "speedup_vs_looped": round(looped_ms / ms, 3)}
     traffic = batch_traffic("rmat22") if k == 64 else None
@@ -496,10 +513,12 @@ def measure_batched(G, g, srcs, reached, single_ms, torch, np, gr, dev, opts):
 
 
 def measure_serving(args, torch, np, gr, gg, dev):
-    """32 resident graphs; capacity Q* from a closed loop with 64 queries outstanding,
-    then open-loop Poisson streams at 0.5 Q* and 0.8 Q*; latency = completion -
-    scheduled arrival (no coordinated omission).  The same trace is replayed
-    through a non-batching FIFO (max_batch 1)."""
+    """32 resident graphs served with continuous batching (gr_server_*):
+    capacity Q* from a closed loop with 64 queries outstanding, then open-loop
+    Poisson streams at 0.5 Q* and 0.8 Q*; latency = completion - scheduled
+    arrival (no coordinated omission).  The first queries of the same trace,
+    at the same arrival times, are replayed through a plain FIFO that runs one
+    query at a time (max_batch 1, one executor): a queue alone."""
     t0 = time.time()
     graphs = gg.serving_graphs()
     Gs = [gr.Graph.from_csr(x) for x in graphs]
@@ -507,54 +526,51 @@ def measure_serving(args, torch, np, gr, gg, dev):
     log("serving graphs: %d (%.1fs)" % (len(Gs), time.time() - t0))
     rng = np.random.default_rng(201)
     nq = max(args.serve_queries, 100)
+    nfifo = min(nq, args.serve_fifo_queries)
     # query mix: graph uniform over 32, source uniform over non-isolated vertices
     nonzero = [np.flatnonzero(d > 0) for d in deg]
     mix = []
-    for i in range(nq + 200):
+    for i in range(nq + 300):
         gi = int(rng.integers(0, len(graphs)))
         mix.append((gi, int(nonzero[gi][rng.integers(0, len(nonzero[gi]))])))
-    ring = 96  # output buffers per graph (more than the queries a graph has in flight)
-    bufs = [[torch.empty(x.n, dtype=torch.int32, device=dev) for _ in range(ring)] for x in graphs]
+    # one output buffer per query of a run (no two queries in flight share one)
+    outs = [torch.empty(graphs[gi].n, dtype=torch.int32, device=dev) for gi, _ in mix]
     inf = gr.GR_DIST_INF_U32
     edges_of = {}
 
-    def serve(queries, arrivals_ns, max_batch):
-        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_streams,
-                                  max_wait_us=args.serve_wait_us)
+    def serve(lo, hi, arrivals_ns, max_batch):
+        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_executors)
         try:
             gids = [gr.gr_server_add_graph(srv, G.handle) for G in Gs]
             tickets = []
-            use = [0] * len(graphs)
             start = time.monotonic_ns()
-            for (gi, s), at in zip(queries, arrivals_ns):
-                due = start + at
+            for q, at in zip(range(lo, hi), arrivals_ns):
+                gi, s = mix[q]
+                due = start + int(at)
                 while True:
                     now = time.monotonic_ns()
                     if now >= due:
                         break
                     if due - now > 200000:
                         time.sleep((due - now - 100000) / 1e9)
-                b = bufs[gi][use[gi] % ring]
-                use[gi] += 1
-                tickets.append((gr.gr_serve_submit(srv, gids[gi], s, b), due, gi, s))
-            lat = []
-            done_at = 0
+                tickets.append((gr.gr_serve_submit(srv, gids[gi], s, outs[q]), due))
+                if len(tickets) % 1000 == 0:
+                    log("  submitted %d of %d (max_batch %d)" % (len(tickets), hi - lo, max_batch))
             res = {}
             while len(res) < len(tickets):
-                for t, due, gi, s in tickets:
-                    if t in res:
-                        continue
-                    r = gr.gr_serve_poll(srv, t)
-                    if r is not None:
-                        res[t] = r
-                time.sleep(0.0002)
-            for t, due, gi, s in tickets:
+                for t, due in tickets:
+                    if t not in res:
+                        r = gr.gr_serve_poll(srv, t)
+                        if r is not None:
+                            res[t] = r
+                time.sleep(0.0005)
+            lat, done_at = [], 0
+            for t, due in tickets:
                 r = res[t]
                 assert r["status"] == gr.GR_OK
                 lat.append(r["t_done_ns"] - due)
                 done_at = max(done_at, r["t_done_ns"])
-            span = (done_at - start) / 1e9
-            return np.array(lat) / 1e6, span, res
+            return np.array(lat) / 1e6, (done_at - start) / 1e9, [res[t] for t, _ in tickets]
         finally:
             gr.gr_server_destroy(srv)
 
@@ -567,26 +583,23 @@ def measure_serving(args, torch, np, gr, gg, dev):
             edges_of[key] = int(deg[gi][dd != inf].sum())
         return edges_of[key]
 
-    def serve_closed(queries, clients, max_batch):
+    def serve_closed(lo, hi, clients, max_batch):
         """Closed loop: `clients` queries outstanding; each completion submits the next."""
-        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_streams,
-                                  max_wait_us=args.serve_wait_us)
+        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_executors)
         try:
             gids = [gr.gr_server_add_graph(srv, G.handle) for G in Gs]
-            use = [0] * len(graphs)
             pending = {}
-            it = iter(queries)
+            nxt = [lo]
             start = time.monotonic_ns()
             done = 0
 
             def submit():
-                q = next(it, None)
-                if q is None:
+                q = nxt[0]
+                if q >= hi:
                     return
-                gi, s = q
-                b = bufs[gi][use[gi] % ring]
-                use[gi] += 1
-                pending[gr.gr_serve_submit(srv, gids[gi], s, b)] = gi
+                nxt[0] += 1
+                gi, s = mix[q]
+                pending[gr.gr_serve_submit(srv, gids[gi], s, outs[q])] = gi
 
             for _ in range(clients):
                 submit()
@@ -600,31 +613,42 @@ def measure_serving(args, torch, np, gr, gg, dev):
                         done += 1
                         end_ns = max(end_ns, r["t_done_ns"])
                         submit()
+                        if done % 1000 == 0:
+                            log("  closed loop: %d of %d done" % (done, hi - lo))
                 time.sleep(0.0001)
             return done / ((end_ns - start) / 1e9)
         finally:
             gr.gr_server_destroy(srv)
 
     # capacity: closed loop with 64 queries outstanding (two per resident graph)
-    warm = mix[:100]
-    serve_closed(warm, 64, 64)
-    qstar = serve_closed(mix[100:100 + nq], 64, 64)
+    serve_closed(0, 200, 64, args.serve_slots)
+    qstar = serve_closed(300, 300 + nq, 64, args.serve_slots)
     log("serving capacity Q* = %.0f queries/s (closed loop, 64 outstanding)" % qstar)
-    out = {"graphs": len(graphs), "capacity_qps": round(qstar, 1), "capacity_clients": 64, "levels": []}
+    out = {"graphs": len(graphs), "executors": args.serve_executors, "slots": args.serve_slots,
+           "capacity_qps": round(qstar, 1), "capacity_clients": 64, "queries_per_level": nq,
+           "fifo_queries_per_level": nfifo, "levels": []}
     for frac in (0.5, 0.8):
         qps = frac * qstar
         gaps = rng.exponential(1.0 / qps, size=nq)
         arr = (np.cumsum(gaps) * 1e9).astype(np.int64)
-        trace = mix[100:100 + nq]
-        lat, span, _ = serve(trace, arr, 64)
-        lat1, span1, _ = serve(trace, arr, 1)
-        edges = sum(m_reached(gi, s) for gi, s in trace)
+        lat, span, res = serve(300, 300 + nq, arr, args.serve_slots)
+        lat1, _, _ = serve(300, 300 + nfifo, arr[:nfifo], 1)
+        edges = sum(m_reached(*mix[q]) for q in range(300, 300 + nq))
+        sizes = np.array([r["batch_size"] for r in res])
+        hist = {}
+        for lo, hi in ((1, 1), (2, 4), (5, 8), (9, 16), (17, 32), (33, 64)):
+            c = int(((sizes >= lo) & (sizes <= hi)).sum())
+            if c:
+                hist["%d" % lo if lo == hi else "%d-%d" % (lo, hi)] = c
         out["levels"].append({
-            "offered_qps": round(qps, 1), "achieved_qps": round(len(trace) / span, 1),
+            "offered_qps": round(qps, 1), "achieved_qps": round(nq / span, 1),
             "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "gteps": round(edges / span / 1e9, 3),
+            "batch_size_hist": hist,
+            "mean_rounds": round(float(np.mean([r["iterations"] for r in res])), 1),
             "fifo_unbatched_p50_ms": round(float(np.percentile(lat1, 50)), 3),
             "fifo_unbatched_p99_ms": round(float(np.percentile(lat1, 99)), 3)})
+        log("serving level %.1f Q*: %s" % (frac, out["levels"][-1]))
     for G in Gs:
         G.close()
     return out

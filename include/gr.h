@@ -302,26 +302,72 @@ gr_status gr_bfs(const gr_graph *g, int32_t src, void *depth_out, void *stream);
 gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, void *stream, const gr_sssp_opts *opts,
                     gr_sssp_stats *stats);
 
+/* Statistics of gr_sssp_batch_ex and gr_sssp_multi. */
+typedef struct {
+    int32_t rounds;             /* rounds in which some query's frontier was not empty */
+    int32_t replays;            /* replays of the captured chunk of rounds (one host wait each) */
+    int64_t edges_pushed;       /* arcs expanded (a batched arc serves every source active at its tail) */
+    int64_t frontier_sum;       /* frontier entries expanded */
+    int64_t source_relaxations; /* (arc, query) relaxations: for gr_sssp_batch_ex the (arc, active source)
+                                   pairs, for gr_sssp_multi equal to edges_pushed */
+} gr_multi_stats;
+
 /*
- * k independent SSSP queries on one graph in one batched launch.
+ * k independent SSSP queries on one graph in one batched computation
+ * (Section IV-D, Listing 4 for each source).
  *   srcs      host int32[k], each in [0, n); duplicates allowed
  *   k         1 <= k <= 64
  *   dist_out  device memory, k x n row-major: row i holds the result of srcs[i]
- * Row i is bit-identical to gr_sssp(g, srcs[i], ...).  Ordered on `stream`;
- * complete after stream synchronisation (the host also waits for the stream
- * once per round, to size the next launch).  Workspace: 274 bytes per vertex
- * (64 distance slots, two 64-bit source masks, two flag bytes) plus 12 per
- * vertex with out-arcs (the frontier queue), whatever k is, taken
- * stream-ordered from the device pool and returned before the call ends.
+ * Row i is bit-identical to gr_sssp(g, srcs[i], ...).  For k >= 2 the
+ * distances are kept vertex-major (the 64 distances of a vertex in one
+ * 256-byte row) and every arc of a frontier vertex is read once for all the
+ * sources active there, one source per wave lane.  The round loop runs on the
+ * device: every launch reads its round from device memory, so 8 rounds
+ * (push, filter) are captured once as a HIP graph and replayed; the host waits
+ * for the stream once per replay to see whether the frontier is empty, and
+ * the call returns when the result is complete.  Workspace, stream-ordered
+ * from the device pool and returned before the call ends: 256 bytes per
+ * vertex (distances) + 16 (masks) + about 28 (frontier marks and two queues).
+ * k = 1 runs gr_sssp's schedule.  The current device must be the graph's.
  */
 gr_status gr_sssp_batch(const gr_graph *g, const int32_t *srcs, int32_t k, void *dist_out, void *stream);
+/* gr_sssp_batch with statistics (stats may be NULL). */
+gr_status gr_sssp_batch_ex(const gr_graph *g, const int32_t *srcs, int32_t k, void *dist_out, void *stream,
+                           gr_multi_stats *stats);
+
+/*
+ * k independent single-source queries, each on its own graph -- graphs may
+ * repeat and may differ in size and weight type -- advanced together: every
+ * round is one push launch and one filter launch over the union of the k
+ * frontiers, spread evenly over the blocks by the frontier's arc counts
+ * (Section IV-D, Listing 4 for each query, in its own distance array).
+ *   graphs      host array of k graph handles, all on the current device
+ *   srcs        host int32[k], srcs[i] in [0, n of graphs[i])
+ *   k           1 <= k <= 64
+ *   dist_out    host array of k device pointers; dist_out[i] receives the n
+ *               values (of graphs[i]'s weight type) of query i and is its
+ *               working array (the k buffers must not overlap)
+ *   stats       optional
+ *   iterations  optional host int32[k]: rounds in which query i's frontier
+ *               was not empty
+ * dist_out[i] is bit-identical to gr_sssp(graphs[i], srcs[i], ...).  The
+ * arcs of the k graphs must total less than 2^31 (GR_ERR_INVALID_ARG).  The
+ * round loop runs on the device from one captured HIP graph of 8 rounds; the
+ * call waits for the stream once per replay and returns when every query is
+ * done.  Workspace: 26 bytes per vertex summed over the queries (two union
+ * queues) + 2 bytes per vertex of each query (frontier marks), stream-ordered
+ * from the device pool and returned before the call ends.
+ */
+gr_status gr_sssp_multi(const gr_graph *const *graphs, const int32_t *srcs, int32_t k, void *const *dist_out,
+                        void *stream, gr_multi_stats *stats, int32_t *iterations);
 
 /* ---- serving ----------------------------------------------------------- */
 
 typedef struct {
-    int32_t max_batch;      /* queries per batched launch, 1..64 (0 = 64) */
-    int32_t num_streams;    /* concurrent batches on the device, 1..8 (0 = 2) */
-    int32_t max_wait_us;    /* how long a partial batch may wait for company (0 = 200) */
+    int32_t max_batch;      /* queries one executor runs together, 1..64 (0 = 64) */
+    int32_t num_streams;    /* executors, each with its own stream, 1..8 (0 = 1) */
+    int32_t max_wait_us;    /* unused: queries join a running executor at its next chunk of
+                               rounds, so none waits for company (must be >= 0) */
     int32_t reserved[5];
 } gr_server_config;
 
@@ -329,18 +375,24 @@ typedef struct {
     int32_t status;      /* GR_OK, or the query's error */
     int32_t graph_id;
     int32_t src;
-    int32_t batch_size;  /* queries that shared its launch */
+    int32_t batch_size;  /* queries live in its executor right after it was admitted */
     int64_t t_submit_ns; /* CLOCK_MONOTONIC times */
-    int64_t t_start_ns;
+    int64_t t_start_ns;  /* admission into an executor */
     int64_t t_done_ns;
-    int32_t iterations;  /* advance/filter rounds of the launch that served the query (for the
-                            asynchronous loop: worklist phases) */
+    int32_t iterations;  /* rounds in which the query's frontier was not empty */
     int32_t reserved;
 } gr_query_result;
 
-/* A query server: resident graphs, admission by device-memory footprint,
- * batching of queries that arrive while others run.  hbm_budget_bytes bounds
- * the device workspace of queries in flight.  cfg may be NULL. */
+/* A query server with continuous batching.  Graphs stay resident; each
+ * executor (a host thread with its own stream) keeps a multi-query session of
+ * up to max_batch live queries whose rounds advance together (the engine of
+ * gr_sssp_multi, one captured HIP graph of 8 rounds replayed per chunk).
+ * Queries wait in one FIFO and join an executor between chunks, in arrival
+ * order, as slots and memory free up: a query's footprint (2 bytes per vertex
+ * of frontier marks + 26 bytes per vertex of the executor's union queues) must
+ * fit hbm_budget_bytes next to every query already admitted.  A query is
+ * complete when a chunk ends with its frontier empty; its distances are then
+ * final in its dist_out.  cfg may be NULL. */
 gr_status gr_server_create(gr_server **out, size_t hbm_budget_bytes, const gr_server_config *cfg);
 /* Registers a graph (not copied; it must outlive the server). */
 gr_status gr_server_add_graph(gr_server *s, const gr_graph *g, int32_t *graph_id);

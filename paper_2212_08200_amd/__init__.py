@@ -74,7 +74,7 @@ GR_DIR_ALTERNATE = 3
 EXPORTED = [
     "gr_graph_create_csr", "gr_graph_destroy", "gr_graph_info", "gr_graph_layout", "gr_graph_tune", "gr_sssp",
     "gr_sssp_ex", "gr_sssp_noalloc",
-    "gr_bfs", "gr_bfs_ex", "gr_sssp_batch",
+    "gr_bfs", "gr_bfs_ex", "gr_sssp_batch", "gr_sssp_batch_ex", "gr_sssp_multi",
     "gr_server_create", "gr_server_add_graph", "gr_serve_submit", "gr_serve_poll", "gr_server_destroy",
     "gr_status_string", "gr_last_error", "gr_version",
 ]
@@ -121,6 +121,14 @@ class gr_tune_result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class gr_multi_stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("replays", ctypes.c_int32), ("edges_pushed", ctypes.c_int64),
+                ("frontier_sum", ctypes.c_int64), ("source_relaxations", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class gr_server_config(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("num_streams", ctypes.c_int32), ("max_wait_us", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 5)]
@@ -161,6 +169,8 @@ def lib():
                 "gr_bfs": [vp, i32, vp, vp],
                 "gr_bfs_ex": [vp, i32, vp, vp, P(gr_sssp_opts), P(gr_sssp_stats)],
                 "gr_sssp_batch": [vp, vp, i32, vp, vp],
+                "gr_sssp_batch_ex": [vp, vp, i32, vp, vp, P(gr_multi_stats)],
+                "gr_sssp_multi": [vp, vp, i32, vp, vp, P(gr_multi_stats), vp],
                 "gr_server_create": [P(vp), ctypes.c_size_t, P(gr_server_config)],
                 "gr_server_add_graph": [vp, vp, P(i32)],
                 "gr_serve_submit": [vp, i32, i32, vp, P(ctypes.c_uint64)],
@@ -338,6 +348,36 @@ def gr_sssp_batch(g: int, srcs, dist_out, stream=None) -> None:
     s = np.ascontiguousarray(srcs, dtype=np.int32)
     out = _out_ptr(dist_out, _graph_n(g) * max(int(s.size), 1), "dist_out")
     _check(lib().gr_sssp_batch(g, s.ctypes.data if s.size else None, int(s.size), out, _stream(stream)))
+
+
+def gr_sssp_batch_ex(g: int, srcs, dist_out, stream=None) -> dict:
+    """gr_sssp_batch with its statistics (rounds, replays, edges_pushed, frontier_sum, source_relaxations)."""
+    s = np.ascontiguousarray(srcs, dtype=np.int32)
+    out = _out_ptr(dist_out, _graph_n(g) * max(int(s.size), 1), "dist_out")
+    st = gr_multi_stats()
+    _check(lib().gr_sssp_batch_ex(g, s.ctypes.data if s.size else None, int(s.size), out, _stream(stream),
+                                  ctypes.byref(st)))
+    return st.as_dict()
+
+
+def gr_sssp_multi(graphs, srcs, dist_outs, stream=None) -> dict:
+    """Queries (graphs[i], srcs[i]) advanced together; dist_outs[i] receives query i.  Returns the
+    statistics plus 'iterations' (rounds with a non-empty frontier, per query)."""
+    k = len(graphs)
+    if len(srcs) != k or len(dist_outs) != k:
+        raise GrError(GR_ERR_INVALID_ARG, "graphs, srcs and dist_outs differ in length")
+    hs = (ctypes.c_void_p * max(k, 1))(*[int(g) for g in graphs])
+    s = np.ascontiguousarray(srcs, dtype=np.int32)
+    outs = (ctypes.c_void_p * max(k, 1))(*[_out_ptr(d, _graph_n(g), "dist_outs[%d]" % i)
+                                           for i, (g, d) in enumerate(zip(graphs, dist_outs))])
+    it = np.zeros(max(k, 1), dtype=np.int32)
+    st = gr_multi_stats()
+    _check(lib().gr_sssp_multi(ctypes.cast(hs, ctypes.c_void_p), s.ctypes.data if s.size else None, int(k),
+                               ctypes.cast(outs, ctypes.c_void_p), _stream(stream), ctypes.byref(st),
+                               it.ctypes.data))
+    d = st.as_dict()
+    d["iterations"] = [int(x) for x in it[:k]]
+    return d
 
 
 # ---- serving ----------------------------------------------------------------

@@ -11,6 +11,7 @@
 #include <thread>
 #include <unordered_map>
 #include <cstdarg>
+#include <cstddef>
 #include <cmath>
 #include <cfloat>
 #include <cstdio>
@@ -22,6 +23,7 @@
 #include <vector>
 
 #include "gr_internal.h"
+#include "gr_multi.h"
 #include "gr_noalloc.h"
 #include "gr_sched.h"
 
@@ -1092,99 +1094,409 @@ extern "C" gr_status gr_bfs(const gr_graph *g, int32_t src, void *depth_out, voi
 // ---------------------------------------------------------------------------
 // batched multi-source queries
 
-struct BatchStats {
-    int32_t iterations = 0;
-    int64_t edges = 0;  // arc expansions (each serves every source active at its tail)
+// One query with the graph's AUTO schedule (a batch of one source).
+static gr_status run_single_auto(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st,
+                                 gr_multi_stats *stats) {
+    RunCfg rc;
+    gr_status s = check_opts(g, nullptr, &rc);
+    if (s != GR_OK) return s;
+    const int loop = g->auto_loop;
+    gr_sssp_stats one{};
+    if (loop == GR_LOOP_ASYNC) s = run_async(g, src, dist, st, rc, &one);
+    else if (loop == GR_LOOP_QUEUED) s = run_queued(g, src, dist, st, rc, &one);
+    else if (loop == GR_LOOP_PERSISTENT) s = run_persistent(g, src, dist, st, rc, &one);
+    else s = run_host_loop(g, src, dist, st, rc, &one);
+    if (s == GR_OK && stats) {
+        stats->rounds = one.iterations;
+        stats->replays = 0;
+        stats->edges_pushed = one.edges_pushed;
+        stats->frontier_sum = one.frontier_sum;
+        stats->source_relaxations = one.edges_pushed;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// multi-query sessions (gr_multi.h): one-shot gr_sssp_multi calls and the
+// query server's executors
+
+static inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes of the session's control block readback: everything before the slot
+// table (counters, round state, statistics, per-slot round counts).
+static constexpr size_t kMqReadBytes = offsetof(MqCtl, nlive);
+static_assert(kMqReadBytes % 8 == 0, "readback is whole words");
+
+struct MqSession {
+    int device = 0;
+    int grid = 0;   // push launch
+    int fgrid = 0;  // filter launch
+    int rounds_per_replay = 0;
+    int64_t qcap = 0;
+    hipStream_t st = nullptr;  // the stream the memory was taken on (and is returned on)
+    void *mem = nullptr;
+    MqBufs b{};
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned char *h = nullptr;  // pinned: two readback buffers
+    bool own_h = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int64_t replays = 0;
 };
 
-// Runs k <= kBatchLanes queries of graph g on stream st; row s of the result
-// goes to out_rows[s] (device pointers).  The host waits for the stream once
-// per iteration to read the frontier size.
-static gr_status run_batch(const gr_graph *g, const int32_t *srcs, int32_t k, uint32_t *const *out_rows,
-                           hipStream_t st, int64_t max_iters, BatchStats *bs) {
-    if (k == 1) {
-        // one source: the single-source path with the graph's AUTO schedule
-        // (its loop needs no host round trip per round)
-        RunCfg rc;
-        gr_status s = check_opts(g, nullptr, &rc);
-        if (s != GR_OK) return s;
-        rc.max_iters = max_iters;
-        const int loop = g->auto_loop;
-        gr_sssp_stats one{};
-        if (loop == GR_LOOP_ASYNC) s = run_async(g, srcs[0], out_rows[0], st, rc, &one);
-        else if (loop == GR_LOOP_QUEUED) s = run_queued(g, srcs[0], out_rows[0], st, rc, &one);
-        else if (loop == GR_LOOP_PERSISTENT) s = run_persistent(g, srcs[0], out_rows[0], st, rc, &one);
-        else s = run_host_loop(g, srcs[0], out_rows[0], st, rc, &one);
-        if (bs) {
-            bs->iterations = one.iterations;
-            bs->edges = one.edges_pushed;
-        }
-        return s;
-    }
+static void mq_destroy(MqSession *s) {
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
+    for (auto &e : s->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->h && s->own_h) (void)hipHostFree(s->h);
+    if (s->mem) (void)hipFreeAsync(s->mem, s->st);
+    *s = MqSession{};
+}
+
+// Queue memory per entry: (first arc, vertex) 8 + prefix 4 + slot 1, two queues.
+static size_t mq_queue_bytes(int64_t qcap) {
+    const size_t c = (size_t)std::max<int64_t>(qcap, 1);
+    return 2 * (al256(c * 8) + al256(c * 4) + al256(c));
+}
+
+// What one captured round launches: the multi-query push and filter, or the
+// batched same-graph push (vertex-major distances D, weight type wt) and filter.
+struct MqMode {
+    uint32_t *D = nullptr;  // non-NULL: batched same-graph queries
+    uint64_t *mask[2] = {nullptr, nullptr};
+    int wt = 0;
+};
+
+// Allocates a session for queues of qcap entries (stream-ordered on st),
+// captures `rounds` rounds as one HIP graph, and clears the control block on
+// st.  own_pinned: a pinned readback buffer of its own (long-lived sessions);
+// otherwise the calling thread's.
+static gr_status mq_create(MqSession *s, int64_t qcap, int rounds, hipStream_t st, const MqMode &mode,
+                           bool own_pinned) {
+    static_assert(2 * ((kMqReadBytes + 255) & ~size_t(255)) <= 8192, "readbacks fit the thread's pinned buffer");
+    *s = MqSession{};
+    HIP_TRY(hipGetDevice(&s->device));
     DeviceInfo di;
-    gr_status s = device_info(g->device, &di);
-    if (s != GR_OK) return s;
-    unsigned long long *hp = pinned_slot();
-    if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
-    const DevGraph &dg = g->plain;
-    void *ws = nullptr;
-    HIP_TRY(hipMallocAsync(&ws, batch_bytes(dg), st));
-    BatchWs w;
-    batch_carve(w, ws, dg);
-    // Staging copies are read by the stream before this function returns.
-    std::vector<uint32_t *> rows(out_rows, out_rows + k);
-    std::vector<int32_t> sv(srcs, srcs + k);
-    hipError_t e = hipMemcpyAsync(w.out_ptrs, rows.data(), sizeof(uint32_t *) * k, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(w.srcs, sv.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_batch_init(dg, w, k, st);
-    // The filter of "iteration -1" turns the source flags into frontier 0.
-    if (e == hipSuccess) e = launch_filter(dg, w.f, -1, nullptr, false, nullptr, false, kInfU32, st);
+    gr_status gs = device_info(s->device, &di);
+    if (gs != GR_OK) return gs;
+    // batched push: many small blocks balance the uneven per-arc work (64
+    // sources on R-MAT 22: 84.6 ms with 128 blocks per CU, 94.3 with 8)
+    s->grid = mode.D ? di.num_cu * 128 : di.num_cu * 8;
+    s->fgrid = di.num_cu * 4;
+    s->rounds_per_replay = rounds;
+    s->qcap = std::max<int64_t>(qcap, 1);
+    s->st = st;
+    const size_t cb = mq_ctl_bytes();
+    hipError_t e = hipMallocAsync(&s->mem, cb + mq_queue_bytes(s->qcap), st);
+    if (e != hipSuccess) {
+        s->mem = nullptr;
+        return fail(GR_ERR_OUT_OF_MEMORY, "multi-query session of %lld queue entries: %s", (long long)s->qcap,
+                    hipGetErrorString(e));
+    }
+    char *p = static_cast<char *>(s->mem);
+    s->b.ctl = reinterpret_cast<MqCtl *>(p);
+    p += cb;
+    const size_t c = (size_t)s->qcap;
+    for (int i = 0; i < 2; ++i) {
+        s->b.qse[i] = reinterpret_cast<uint2 *>(p);
+        p += al256(c * 8);
+        s->b.qs[i] = reinterpret_cast<int32_t *>(p);
+        p += al256(c * 4);
+        s->b.qslot[i] = reinterpret_cast<uint8_t *>(p);
+        p += al256(c);
+    }
+    s->b.qcap = s->qcap;
+    s->b.mask[0] = mode.mask[0];
+    s->b.mask[1] = mode.mask[1];
+    if (own_pinned) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&s->h), 2 * al256(kMqReadBytes), hipHostMallocDefault);
+        s->own_h = e == hipSuccess;
+    } else {
+        s->h = reinterpret_cast<unsigned char *>(pinned_slot());
+        if (!s->h) e = hipErrorOutOfMemory;
+    }
+    if (e != hipSuccess) {
+        s->h = nullptr;
+        mq_destroy(s);
+        return fail(GR_ERR_OUT_OF_MEMORY, "pinned readback buffer");
+    }
+    for (auto &x : s->ev)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
+    // every launch reads its round from the control block, so one capture
+    // serves every replay of the session
+    if (e == hipSuccess) e = hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        hipError_t e1 = hipSuccess;
+        for (int i = 0; i < rounds && e1 == hipSuccess; ++i)
+            e1 = mode.D ? mq_batch_round(s->b, mode.D, mode.wt, s->grid, s->fgrid, s->cap)
+                        : mq_round(s->b, s->grid, s->fgrid, s->cap);
+        e = hipStreamEndCapture(s->cap, &s->graph);
+        if (e == hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiateWithFlags(&s->exec, s->graph, 0);
+    if (e == hipSuccess) e = mq_reset(s->b, st);
+    if (e != hipSuccess) {
+        mq_destroy(s);
+        return hip_fail(e, "multi-query session set-up");
+    }
+    return GR_OK;
+}
+
+// Per-query workspace: next-frontier marks (2 x nflag) and dirty-group bytes (2 x ngroups).
+static size_t mq_slot_bytes(int32_t n) {
+    const int64_t ng = groups_for(n);
+    return al256((size_t)ng * kGroupVerts * 2) + al256((size_t)ng * 2);
+}
+
+static MqSlot mq_slot(const gr_graph *g, uint32_t *dist, void *ws, int wt) {
+    MqSlot s{};
+    s.ro = g->plain.ro;
+    s.adj = g->plain.adj;
+    s.dist = dist;
+    s.n = g->plain.n;
+    s.wt = wt;
+    s.ngroups = (int32_t)groups_for(s.n);
+    s.nflag = s.ngroups * kGroupVerts;
+    s.flags = static_cast<uint8_t *>(ws);
+    s.dirty = static_cast<uint8_t *>(ws) + al256((size_t)s.nflag * 2);
+    return s;
+}
+
+// Live set of an update: slot ids and the prefix sum of their group counts.
+static void mq_live(MqUpdate &u, const std::vector<int> &live, const std::vector<int32_t> &ngroups_of_slot) {
+    u.nlive = (int32_t)live.size();
+    std::memset(u.live, 0, sizeof u.live);
+    int32_t acc = 0;
+    for (size_t i = 0; i < live.size(); ++i) {
+        u.live[i] = (uint8_t)live[i];
+        u.gpre[i] = acc;
+        acc += ngroups_of_slot[live[i]];
+    }
+    for (size_t i = live.size(); i <= (size_t)kMqSlots; ++i) u.gpre[i] = acc;
+}
+
+struct MqRead {
+    unsigned long long round;  // round the next push runs
+    int32_t F, E;              // its queue
+    unsigned long long slot_cnt[kMqSlots];
+    unsigned long long slot_rounds[kMqSlots];
+    unsigned long long rounds, edges, frontier;
+};
+
+static MqRead mq_parse(const unsigned char *h) {
+    MqCtl c;
+    std::memcpy(static_cast<void *>(&c), h, kMqReadBytes);
+    MqRead r{};
+    r.round = c.st_round[0];
+    r.F = (int32_t)(c.cnt[r.round % 3][0] & 0xFFFFFFFFull);
+    r.E = (int32_t)(c.cnt[r.round % 3][0] >> 32);
+    for (int s = 0; s < kMqSlots; ++s) {
+        r.slot_cnt[s] = c.slot_cnt[r.round % 3][s];
+        r.slot_rounds[s] = c.slot_rounds[s];
+    }
+    r.rounds = c.rounds;
+    r.edges = c.edges;
+    r.frontier = c.frontier;
+    return r;
+}
+
+// Enqueues one replay of the captured rounds and the readback into buffer i.
+static hipError_t mq_replay(MqSession *s, int i, hipStream_t st) {
+    hipError_t e = hipGraphLaunch(s->exec, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(hp, counters_after(w.f, -1), sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    int64_t iter = 0;
+        e = hipMemcpyAsync(s->h + i * al256(kMqReadBytes), s->b.ctl, kMqReadBytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(s->ev[i], st);
+    if (e == hipSuccess) ++s->replays;
+    return e;
+}
+
+static gr_status check_same_device(const gr_graph *g) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != g->device) return fail(GR_ERR_INVALID_ARG, "current device %d is not the graph's device %d", dev,
+                                      g->device);
+    return GR_OK;
+}
+
+static constexpr int kMqRoundsPerReplay = 8;
+
+extern "C" gr_status gr_sssp_multi(const gr_graph *const *graphs, const int32_t *srcs, int32_t k,
+                                   void *const *dist_out, void *stream, gr_multi_stats *stats,
+                                   int32_t *iterations) {
+    if (!graphs || !srcs || !dist_out) return fail(GR_ERR_INVALID_ARG, "NULL graphs, srcs or dist_out");
+    if (k < 1 || k > kMqSlots) return fail(GR_ERR_INVALID_ARG, "k = %d outside [1, %d]", k, kMqSlots);
+    int64_t sum_n = 0, sum_m = 0;
+    for (int32_t i = 0; i < k; ++i) {
+        const gr_graph *g = graphs[i];
+        if (!g) return fail(GR_ERR_INVALID_ARG, "graphs[%d] is NULL", i);
+        if (!dist_out[i]) return fail(GR_ERR_INVALID_ARG, "dist_out[%d] is NULL", i);
+        if (srcs[i] < 0 || srcs[i] >= g->plain.n)
+            return fail(GR_ERR_SOURCE_RANGE, "srcs[%d] = %d outside [0, %d)", i, srcs[i], g->plain.n);
+        gr_status s = check_same_device(g);
+        if (s != GR_OK) return s;
+        sum_n += g->plain.n;
+        sum_m += g->plain.m;
+    }
+    if (sum_m > INT32_MAX)
+        return fail(GR_ERR_INVALID_ARG, "the queries' graphs hold %lld arcs together, more than 2^31 - 1",
+                    (long long)sum_m);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MqSession ses;
+    gr_status gs = mq_create(&ses, sum_n, kMqRoundsPerReplay, st, MqMode{}, false);
+    if (gs != GR_OK) return gs;
+    std::vector<size_t> off((size_t)k + 1, 0);
+    for (int32_t i = 0; i < k; ++i) off[i + 1] = off[i] + mq_slot_bytes(graphs[i]->plain.n);
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, off[k], st);
+    if (e != hipSuccess) {
+        mq_destroy(&ses);
+        return hip_fail(e, "hipMallocAsync");
+    }
+    std::vector<int> live;
+    std::vector<int32_t> ngr(kMqSlots, 0);
+    for (int32_t i = 0; i < k; ++i) {
+        live.push_back(i);
+        ngr[i] = (int32_t)groups_for(graphs[i]->plain.n);
+    }
+    for (int32_t i0 = 0; i0 < k && e == hipSuccess; i0 += 16) {
+        MqUpdate u{};
+        u.nadmit = std::min<int32_t>(16, k - i0);
+        for (int32_t j = 0; j < u.nadmit; ++j) {
+            const int32_t i = i0 + j;
+            u.admit_slot[j] = i;
+            u.admit_src[j] = srcs[i];
+            u.admit[j] = mq_slot(graphs[i], static_cast<uint32_t *>(dist_out[i]), static_cast<char *>(ws) + off[i],
+                                 graphs[i]->plain.wt);
+        }
+        if (i0 + 16 >= k) mq_live(u, live, ngr);
+        else u.nlive = -1;
+        e = mq_update(ses.b, u, st);
+    }
     gr_status status = GR_OK;
+    MqRead rd{};
     while (e == hipSuccess) {
-        const int32_t F = (int32_t)(hp[0] & 0xFFFFFFFFull), E = (int32_t)(hp[0] >> 32);
-        if (F == 0) break;
-        if (iter >= max_iters) {
-            status = fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)max_iters);
+        e = mq_replay(&ses, 0, st);
+        if (e == hipSuccess) e = hipEventSynchronize(ses.ev[0]);
+        if (e != hipSuccess) break;
+        rd = mq_parse(ses.h);
+        if (rd.F == 0) break;
+        bool over = false;
+        for (int32_t i = 0; i < k; ++i)
+            over = over || rd.slot_rounds[i] > (unsigned long long)graphs[i]->plain.n + 1;
+        if (over) {
+            status = fail(GR_ERR_ITER_LIMIT, "a query ran past n + 1 rounds");
             break;
         }
-        e = launch_batch_push(dg, w, iter, F, E, di.num_cu, st);
-        if (e == hipSuccess)
-            e = launch_filter(dg, w.f, iter, w.mask[iter & 1], (int64_t)F * kBatchDenseRatio >= dg.n, nullptr, false,
-                              kInfU32, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hp, counters_after(w.f, iter), sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (bs) bs->edges += E;
-        ++iter;
     }
-    if (e == hipSuccess && status == GR_OK) e = launch_batch_output(dg, w, k, st);
+    if (e == hipSuccess) e = hipFreeAsync(ws, st);
+    else (void)hipFreeAsync(ws, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipError_t e2 = hipFreeAsync(ws, st);
-    if (bs) bs->iterations = (int32_t)iter;
-    if (e != hipSuccess) return hip_fail(e, "batched sssp");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    if (e == hipSuccess && stats) {
+        stats->rounds = (int32_t)rd.rounds;
+        stats->replays = (int32_t)ses.replays;
+        stats->edges_pushed = (int64_t)rd.edges;
+        stats->frontier_sum = (int64_t)rd.frontier;
+        stats->source_relaxations = (int64_t)rd.edges;
+    }
+    if (e == hipSuccess && iterations)
+        for (int32_t i = 0; i < k; ++i) iterations[i] = (int32_t)rd.slot_rounds[i];
+    mq_destroy(&ses);
+    if (e != hipSuccess) return hip_fail(e, "multi-query loop");
     return status;
 }
 
-extern "C" gr_status gr_sssp_batch(const gr_graph *g, const int32_t *srcs, int32_t k, void *dist_out,
-                                   void *stream) {
+// Batched same-graph queries (gr_sssp_batch, k >= 2): vertex-major distances,
+// one wave lane per source, the round loop on the device, replayed from one
+// captured HIP graph; the host reads the control block once per replay.
+static gr_status run_batch_dev(const gr_graph *g, const int32_t *srcs, int32_t k, uint32_t *const *out_rows,
+                               hipStream_t st, gr_multi_stats *stats) {
+    const DevGraph &dg = g->plain;
+    const int64_t n = dg.n;
+    const size_t dbytes = al256((size_t)n * kBatchLanes * 4), mbytes = al256((size_t)n * 8);
+    void *ws = nullptr;
+    HIP_TRY(hipMallocAsync(&ws, dbytes + 2 * mbytes + mq_slot_bytes(dg.n), st));
+    char *p = static_cast<char *>(ws);
+    MqMode mode;
+    mode.D = reinterpret_cast<uint32_t *>(p);
+    mode.mask[0] = reinterpret_cast<uint64_t *>(p + dbytes);
+    mode.mask[1] = reinterpret_cast<uint64_t *>(p + dbytes + mbytes);
+    mode.wt = dg.wt;
+    MqSession ses;
+    gr_status gs = mq_create(&ses, n, kMqRoundsPerReplay, st, mode, false);
+    if (gs != GR_OK) {
+        (void)hipFreeAsync(ws, st);
+        return gs;
+    }
+    const MqSlot slot = mq_slot(g, nullptr, p + dbytes + 2 * mbytes, dg.wt);
+    MqBatchSrc bs{};
+    bs.k = k;
+    for (int32_t i = 0; i < k; ++i) bs.src[i] = srcs[i];
+    hipError_t e = mq_batch_init(ses.b, slot, mode.D, bs, st);
+    gr_status status = GR_OK;
+    MqRead rd{};
+    while (e == hipSuccess) {
+        e = mq_replay(&ses, 0, st);
+        if (e == hipSuccess) e = hipEventSynchronize(ses.ev[0]);
+        if (e != hipSuccess) break;
+        rd = mq_parse(ses.h);
+        if (rd.F == 0) break;
+        if (rd.rounds > (unsigned long long)n + 1) {
+            status = fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)n + 1);
+            break;
+        }
+    }
+    unsigned long long pairs = 0;
+    if (e == hipSuccess && status == GR_OK) {
+        MqOutRows rows{};
+        for (int32_t i = 0; i < k; ++i) rows.row[i] = out_rows[i];
+        e = mq_batch_output(mode.D, dg.n, k, rows, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ses.h, &ses.b.ctl->pairs, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) std::memcpy(&pairs, ses.h, sizeof pairs);
+    }
+    (void)hipFreeAsync(ws, st);
+    const int64_t replays = ses.replays;
+    mq_destroy(&ses);
+    if (e != hipSuccess) return hip_fail(e, "batched queries");
+    if (stats) {
+        stats->rounds = (int32_t)rd.rounds;
+        stats->replays = (int32_t)replays;
+        stats->edges_pushed = (int64_t)rd.edges;
+        stats->frontier_sum = (int64_t)rd.frontier;
+        stats->source_relaxations = (int64_t)pairs;
+    }
+    return status;
+}
+
+extern "C" gr_status gr_sssp_batch_ex(const gr_graph *g, const int32_t *srcs, int32_t k, void *dist_out,
+                                      void *stream, gr_multi_stats *stats) {
     if (!g) return fail(GR_ERR_INVALID_ARG, "graph is NULL");
     if (!srcs || !dist_out) return fail(GR_ERR_INVALID_ARG, "NULL srcs or dist_out");
     if (k < 1 || k > kBatchLanes) return fail(GR_ERR_INVALID_ARG, "k = %d outside [1, %d]", k, kBatchLanes);
     for (int32_t i = 0; i < k; ++i)
         if (srcs[i] < 0 || srcs[i] >= g->plain.n)
             return fail(GR_ERR_SOURCE_RANGE, "srcs[%d] = %d outside [0, %d)", i, srcs[i], g->plain.n);
+    gr_status s = check_same_device(g);
+    if (s != GR_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (k == 1) return run_single_auto(g, srcs[0], static_cast<uint32_t *>(dist_out), st, stats);
     std::vector<uint32_t *> rows((size_t)k);
     for (int32_t i = 0; i < k; ++i) rows[i] = static_cast<uint32_t *>(dist_out) + (size_t)i * g->plain.n;
-    return run_batch(g, srcs, k, rows.data(), static_cast<hipStream_t>(stream), (int64_t)g->plain.n + 1, nullptr);
+    return run_batch_dev(g, srcs, k, rows.data(), st, stats);
+}
+
+extern "C" gr_status gr_sssp_batch(const gr_graph *g, const int32_t *srcs, int32_t k, void *dist_out,
+                                   void *stream) {
+    return gr_sssp_batch_ex(g, srcs, k, dist_out, stream, nullptr);
 }
 
 // ---------------------------------------------------------------------------
-// query server
+// query server: continuous batching over multi-query sessions
 
 static int64_t now_ns() {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
@@ -1205,64 +1517,215 @@ struct gr_server {
     std::mutex mu;
     std::condition_variable cv;
     std::vector<const gr_graph *> graphs;
-    std::unique_ptr<BatchPolicy> policy;
+    std::unique_ptr<SlotPolicy> policy;
     std::unordered_map<uint64_t, Ticket> tickets;
     uint64_t next_ticket = 1;
     size_t in_flight = 0;
     bool stopping = false;
-    std::vector<hipStream_t> streams;
     std::vector<std::thread> workers;
 };
 
-static size_t batch_footprint(const gr_graph *g) { return batch_bytes(g->plain); }
+static QuerySize query_size(const gr_graph *g) {
+    // its marks and dirty bytes, and its share of the session's two queues
+    return QuerySize{mq_slot_bytes(g->plain.n) + (size_t)g->plain.n * 26, g->plain.n, g->plain.m};
+}
 
-// One worker per stream: takes the next batch the policy admits, runs it,
-// publishes the results.  Batches on different streams overlap on the device.
-static void server_worker(gr_server *s, int slot) {
+// One executor: a session of up to max_batch slots on its own stream.  Each
+// pass admits what fits into free slots (an update launch), enqueues a replay
+// of the captured rounds, and then processes the readback of the previous
+// replay, so the device always has the next chunk of rounds queued.  A query
+// is complete when a readback taken after its admission shows no entry of its
+// slot in the next round's queue; its distances are then final (they are the
+// caller's buffer, updated in place).
+struct LiveQuery {
+    SchedQuery q;
+    QuerySize z;
+    void *ws = nullptr;
+    int64_t admit_replay = 0;  // first replay enqueued after its admission
+    int32_t batch = 0;
+};
+
+static void server_worker(gr_server *s, int exec_id) {
     (void)hipSetDevice(s->device);
-    hipStream_t st = s->streams[slot];
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    const int nslots = s->cfg.max_batch;
+    MqSession ses;
+    bool have_ses = false;
+    int64_t qcap = 0;
+    std::vector<LiveQuery> slot((size_t)kMqSlots);
+    std::vector<bool> used((size_t)kMqSlots, false);
+    std::vector<int32_t> ngr((size_t)kMqSlots, 0);
+    std::vector<int32_t> qrounds((size_t)kMqSlots, 0);
+    int nused = 0;
+    int64_t used_n = 0, used_m = 0;
+    bool live_changed = false;
+    int64_t outstanding = -1;  // replay whose readback is pending
+    gr_status broken = GR_OK;   // a HIP failure ends every query of this executor with it
+    if (!st) broken = fail(GR_ERR_HIP, "query server: no stream for an executor");
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        SchedBatch b;
-        int64_t wake = 0;
-        const BatchPolicy::Decision d = s->policy->next(now_ns(), s->in_flight, s->stopping, &b, &wake);
-        if (d != BatchPolicy::kLaunch) {
-            if (s->stopping && s->policy->pending() == 0) return;
-            if (d == BatchPolicy::kWaitUntil)
-                s->cv.wait_for(lk, std::chrono::nanoseconds(std::max<int64_t>(wake - now_ns(), 1000)));
-            else
-                s->cv.wait(lk);
+        // 1. admissions
+        std::vector<SchedQuery> adm;
+        if (broken == GR_OK && st) {
+            const SchedQuery *h = s->policy->head();
+            if (h && nused == 0) {
+                // the session's queue holds max_batch queries of the largest registered graph
+                int64_t need = 1;
+                for (const gr_graph *g : s->graphs) need = std::max<int64_t>(need, g->plain.n);
+                need *= nslots;
+                if (!have_ses || need > qcap) {
+                    lk.unlock();
+                    if (have_ses) {
+                        (void)hipStreamSynchronize(st);
+                        mq_destroy(&ses);
+                        have_ses = false;
+                        outstanding = -1;  // nothing live: its readback is not needed
+                    }
+                    gr_status gs = mq_create(&ses, need, kMqRoundsPerReplay, st, MqMode{}, true);
+                    lk.lock();
+                    if (gs != GR_OK) broken = gs;
+                    else {
+                        have_ses = true;
+                        qcap = need;
+                    }
+                }
+            }
+            if (have_ses)
+                adm = s->policy->admit(SessionRoom{nslots - nused, qcap - used_n, (int64_t)INT32_MAX - used_m},
+                                       &s->in_flight);
+        }
+        if (broken != GR_OK) {
+            // fail everything this executor holds and every query still queued
+            for (int i = 0; i < kMqSlots; ++i)
+                if (used[i]) {
+                    Ticket &t = s->tickets[slot[i].q.ticket];
+                    t.state = kDone;
+                    t.res.status = broken;
+                    t.res.t_done_ns = now_ns();
+                    s->in_flight -= slot[i].z.bytes;
+                    used[i] = false;
+                }
+            nused = 0;
+            for (const SchedQuery &q : s->policy->take_all()) {
+                Ticket &t = s->tickets[q.ticket];
+                t.state = kDone;
+                t.res.status = broken;
+                t.res.t_done_ns = now_ns();
+            }
+            s->cv.notify_all();
+            if (s->stopping) break;
+            s->cv.wait(lk);
             continue;
         }
-        s->in_flight += b.bytes;
-        const int64_t t_start = now_ns();
-        const gr_graph *g = s->graphs[b.graph];
-        const int32_t k = (int32_t)b.queries.size();
-        std::vector<int32_t> srcs(k);
-        std::vector<uint32_t *> rows(k);
-        for (int32_t i = 0; i < k; ++i) {
-            srcs[i] = b.queries[i].src;
-            rows[i] = static_cast<uint32_t *>(b.queries[i].dst);
-            Ticket &t = s->tickets[b.queries[i].ticket];
+        const int64_t t_adm = now_ns();
+        std::vector<std::pair<int, const gr_graph *>> newq;
+        for (const SchedQuery &q : adm) {
+            int i = 0;
+            while (used[i]) ++i;
+            used[i] = true;
+            ++nused;
+            LiveQuery &L = slot[i];
+            L = LiveQuery{};
+            L.q = q;
+            L.z = query_size(s->graphs[q.graph]);
+            used_n += L.z.n;
+            used_m += L.z.m;
+            ngr[i] = (int32_t)groups_for(s->graphs[q.graph]->plain.n);
+            newq.emplace_back(i, s->graphs[q.graph]);
+            Ticket &t = s->tickets[q.ticket];
             t.state = kRunning;
-            t.res.t_start_ns = t_start;
-            t.res.batch_size = k;
+            t.res.t_start_ns = t_adm;
+        }
+        for (auto &x : newq) slot[x.first].batch = nused;
+        if (!adm.empty()) live_changed = true;
+        const bool any_live = nused > 0;
+        if (!any_live && outstanding < 0) {
+            if (s->stopping && s->policy->pending() == 0) break;
+            s->cv.wait(lk);
+            continue;
         }
         lk.unlock();
-        BatchStats bst;
-        const gr_status rc = run_batch(g, srcs.data(), k, rows.data(), st, (int64_t)g->plain.n + 1, &bst);
+        hipError_t e = hipSuccess;
+        // 2. slot workspaces and the update launch (admissions + live set)
+        for (auto &x : newq) {
+            if (e == hipSuccess) e = hipMallocAsync(&slot[x.first].ws, mq_slot_bytes(x.second->plain.n), st);
+        }
+        if (e == hipSuccess && live_changed) {
+            std::vector<int> live;
+            for (int i = 0; i < kMqSlots; ++i)
+                if (used[i]) live.push_back(i);
+            size_t j = 0;
+            do {
+                MqUpdate u{};
+                u.nadmit = 0;
+                while (j < newq.size() && u.nadmit < 16) {
+                    const int i = newq[j].first;
+                    u.admit_slot[u.nadmit] = i;
+                    u.admit_src[u.nadmit] = slot[i].q.src;
+                    u.admit[u.nadmit] = mq_slot(newq[j].second, static_cast<uint32_t *>(slot[i].q.dst), slot[i].ws,
+                                                newq[j].second->plain.wt);
+                    ++u.nadmit;
+                    ++j;
+                }
+                if (j >= newq.size()) mq_live(u, live, ngr);
+                else u.nlive = -1;
+                e = mq_update(ses.b, u, st);
+            } while (e == hipSuccess && j < newq.size());
+            live_changed = false;
+        }
+        for (auto &x : newq) slot[x.first].admit_replay = ses.replays;
+        // 3. the next replay
+        int64_t issued = -1;
+        if (e == hipSuccess && any_live) {
+            issued = ses.replays;
+            e = mq_replay(&ses, (int)(issued & 1), st);
+        }
+        // 4. the previous replay's readback
+        std::vector<int> done;
+        if (e == hipSuccess && outstanding >= 0) {
+            e = hipEventSynchronize(ses.ev[outstanding & 1]);
+            if (e == hipSuccess) {
+                const MqRead rd = mq_parse(ses.h + (outstanding & 1) * al256(kMqReadBytes));
+                for (int i = 0; i < kMqSlots; ++i)
+                    if (used[i] && outstanding >= slot[i].admit_replay && rd.slot_cnt[i] == 0ull) {
+                        done.push_back(i);
+                        qrounds[i] = (int32_t)rd.slot_rounds[i];
+                    }
+            }
+        }
+        outstanding = issued;
+        // finished queries' workspaces are freed after the replay just issued (stream order)
+        for (int i : done)
+            if (e == hipSuccess) e = hipFreeAsync(slot[i].ws, st);
         const int64_t t_done = now_ns();
         lk.lock();
-        s->in_flight -= b.bytes;
-        for (const SchedQuery &q : b.queries) {
-            Ticket &t = s->tickets[q.ticket];
+        for (int i : done) {
+            Ticket &t = s->tickets[slot[i].q.ticket];
             t.state = kDone;
-            t.res.status = rc;
+            t.res.status = GR_OK;
             t.res.t_done_ns = t_done;
-            t.res.iterations = bst.iterations;
+            t.res.batch_size = slot[i].batch;
+            t.res.iterations = qrounds[i];
+            s->in_flight -= slot[i].z.bytes;
+            used[i] = false;
+            --nused;
+            used_n -= slot[i].z.n;
+            used_m -= slot[i].z.m;
+            ngr[i] = 0;
+            live_changed = true;
         }
-        s->cv.notify_all();
+        if (!done.empty()) s->cv.notify_all();
+        if (e != hipSuccess) {
+            broken = hip_fail(e, "query server executor");
+            outstanding = -1;
+        }
     }
+    lk.unlock();
+    if (st) (void)hipStreamSynchronize(st);
+    if (have_ses) mq_destroy(&ses);
+    if (st) (void)hipStreamDestroy(st);
+    (void)exec_id;
 }
 
 extern "C" gr_status gr_server_create(gr_server **out, size_t hbm_budget_bytes, const gr_server_config *cfg) {
@@ -1270,11 +1733,10 @@ extern "C" gr_status gr_server_create(gr_server **out, size_t hbm_budget_bytes, 
     *out = nullptr;
     gr_server_config c{};
     if (cfg) c = *cfg;
-    if (c.max_batch == 0) c.max_batch = kBatchLanes;
-    if (c.num_streams == 0) c.num_streams = 2;
-    if (c.max_wait_us == 0) c.max_wait_us = 200;
-    if (c.max_batch < 1 || c.max_batch > kBatchLanes)
-        return fail(GR_ERR_INVALID_ARG, "max_batch = %d outside [1, %d]", c.max_batch, kBatchLanes);
+    if (c.max_batch == 0) c.max_batch = kMqSlots;
+    if (c.num_streams == 0) c.num_streams = 1;
+    if (c.max_batch < 1 || c.max_batch > kMqSlots)
+        return fail(GR_ERR_INVALID_ARG, "max_batch = %d outside [1, %d]", c.max_batch, kMqSlots);
     if (c.num_streams < 1 || c.num_streams > 8)
         return fail(GR_ERR_INVALID_ARG, "num_streams = %d outside [1, 8]", c.num_streams);
     if (c.max_wait_us < 0) return fail(GR_ERR_INVALID_ARG, "max_wait_us = %d is negative", c.max_wait_us);
@@ -1285,17 +1747,7 @@ extern "C" gr_status gr_server_create(gr_server **out, size_t hbm_budget_bytes, 
     s->budget = hbm_budget_bytes;
     s->cfg = c;
     gr_server *raw = s.get();
-    s->policy.reset(new BatchPolicy(c.max_batch, (int64_t)c.max_wait_us * 1000, hbm_budget_bytes,
-                                    [raw](int32_t gid) { return batch_footprint(raw->graphs[gid]); }));
-    for (int i = 0; i < c.num_streams; ++i) {
-        hipStream_t st;
-        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-        if (e != hipSuccess) {
-            for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
-            return hip_fail(e, "hipStreamCreate");
-        }
-        s->streams.push_back(st);
-    }
+    s->policy.reset(new SlotPolicy(hbm_budget_bytes, [raw](int32_t gid) { return query_size(raw->graphs[gid]); }));
     for (int i = 0; i < c.num_streams; ++i) s->workers.emplace_back(server_worker, raw, i);
     *out = s.release();
     return GR_OK;
@@ -1303,6 +1755,8 @@ extern "C" gr_status gr_server_create(gr_server **out, size_t hbm_budget_bytes, 
 
 extern "C" gr_status gr_server_add_graph(gr_server *s, const gr_graph *g, int32_t *graph_id) {
     if (!s || !g || !graph_id) return fail(GR_ERR_INVALID_ARG, "NULL argument");
+    if (g->device != s->device)
+        return fail(GR_ERR_INVALID_ARG, "graph on device %d, server on device %d", g->device, s->device);
     std::lock_guard<std::mutex> lk(s->mu);
     s->graphs.push_back(g);
     *graph_id = (int32_t)s->graphs.size() - 1;
@@ -1318,7 +1772,7 @@ extern "C" gr_status gr_serve_submit(gr_server *s, int32_t graph_id, int32_t src
         return fail(GR_ERR_INVALID_ARG, "unknown graph id %d", graph_id);
     const gr_graph *g = s->graphs[graph_id];
     if (src < 0 || src >= g->plain.n) return fail(GR_ERR_SOURCE_RANGE, "src = %d outside [0, %d)", src, g->plain.n);
-    const size_t need = batch_footprint(g);
+    const size_t need = query_size(g).bytes;
     if (need > s->budget)
         return fail(GR_ERR_NO_CAPACITY, "a query on graph %d needs %zu bytes, budget is %zu", graph_id, need,
                     s->budget);
@@ -1353,7 +1807,6 @@ extern "C" gr_status gr_server_destroy(gr_server *s) {
     }
     s->cv.notify_all();
     for (std::thread &t : s->workers) t.join();
-    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     delete s;
     return GR_OK;
 }

@@ -1,14 +1,19 @@
-// Admission and batching policy of the query server (plain C++, no HIP, so
-// that it can be unit-tested on the host with an injected clock).
+// Admission policy of the query server (plain C++, no HIP, so that it can be
+// unit-tested on the host with injected sizes).
 //
-// Queries wait in one FIFO.  When an executor slot is free, the policy forms
-// a batch for the graph of the OLDEST waiting query (so no graph starves):
-// up to max_batch of that graph's queries, in arrival order.  The batch
-// launches when it is full, when its oldest query has waited max_wait_ns, or
-// when draining; otherwise the slot waits until that deadline or the next
-// arrival.  A batch is admitted only if the device memory it needs fits in
-// the budget next to the batches already running; otherwise the slot waits
-// for a running batch to finish.
+// The server runs continuous batching: each executor keeps a multi-query
+// session whose rounds advance every live query together, and new queries
+// join it between chunks of rounds as slots and memory free up.  Queries wait
+// in one FIFO; an executor with free slots admits queries from the head, in
+// arrival order, while each one fits:
+//   - a free slot of the session;
+//   - the device-memory budget, next to the workspace of every query already
+//     admitted by any executor;
+//   - the session's queue capacity (the sum of the vertex counts of its live
+//     queries) and the int32 arc range of one round (the sum of their arc
+//     counts).
+// The head is never overtaken, so no query starves: when the head does not
+// fit, admission stops until a query completes.
 #pragma once
 
 #include <cstddef>
@@ -27,64 +32,55 @@ struct SchedQuery {
     int64_t t_submit_ns;
 };
 
-struct SchedBatch {
-    int32_t graph = -1;
-    std::vector<SchedQuery> queries;
-    size_t bytes = 0;
+// Sizes of a query on a graph.
+struct QuerySize {
+    size_t bytes;  // device workspace while it is live
+    int64_t n;     // vertices (its share of the session's queue)
+    int64_t m;     // arcs (bound on its share of one round's arcs)
 };
 
-class BatchPolicy {
+// What an executor has left when it asks for admissions.
+struct SessionRoom {
+    int free_slots;
+    int64_t free_queue;  // queue entries not reserved by live queries
+    int64_t free_arcs;   // arcs of one round not reserved by live queries
+};
+
+class SlotPolicy {
    public:
-    // footprint(graph): device bytes one batch on that graph needs.
-    BatchPolicy(int max_batch, int64_t max_wait_ns, size_t budget, std::function<size_t(int32_t)> footprint)
-        : max_batch_(max_batch), max_wait_ns_(max_wait_ns), budget_(budget), footprint_(std::move(footprint)) {}
+    SlotPolicy(size_t budget, std::function<QuerySize(int32_t)> size) : budget_(budget), size_(std::move(size)) {}
 
     void push(const SchedQuery &q) { q_.push_back(q); }
     size_t pending() const { return q_.size(); }
+    const SchedQuery *head() const { return q_.empty() ? nullptr : &q_.front(); }
 
-    enum Decision { kLaunch = 1, kWaitUntil = 2, kWaitForEvent = 3 };
+    // Takes queries from the head while they fit (see above); in_flight is the
+    // workspace already admitted, and grows by what is admitted here.
+    std::vector<SchedQuery> admit(SessionRoom room, size_t *in_flight) {
+        std::vector<SchedQuery> out;
+        while (!q_.empty() && room.free_slots > 0) {
+            const QuerySize z = size_(q_.front().graph);
+            if (*in_flight + z.bytes > budget_ || z.n > room.free_queue || z.m > room.free_arcs) break;
+            out.push_back(q_.front());
+            q_.pop_front();
+            *in_flight += z.bytes;
+            room.free_slots -= 1;
+            room.free_queue -= z.n;
+            room.free_arcs -= z.m;
+        }
+        return out;
+    }
 
-    // Called for a free slot at time now with in_flight bytes already admitted.
-    // kLaunch: *out holds the batch (removed from the queue).  kWaitUntil:
-    // retry at *wake_ns (or on an arrival).  kWaitForEvent: retry after an
-    // arrival or a completion.
-    Decision next(int64_t now_ns, size_t in_flight, bool draining, SchedBatch *out, int64_t *wake_ns) {
-        if (q_.empty()) return kWaitForEvent;
-        const SchedQuery &head = q_.front();
-        const int32_t g = head.graph;
-        std::vector<size_t> pick;
-        for (size_t i = 0; i < q_.size() && (int)pick.size() < max_batch_; ++i)
-            if (q_[i].graph == g) pick.push_back(i);
-        const bool full = (int)pick.size() >= max_batch_;
-        const bool aged = now_ns - head.t_submit_ns >= max_wait_ns_;
-        if (!full && !aged && !draining) {
-            *wake_ns = head.t_submit_ns + max_wait_ns_;
-            return kWaitUntil;
-        }
-        const size_t bytes = footprint_(g);
-        if (in_flight + bytes > budget_) return kWaitForEvent;
-        out->graph = g;
-        out->bytes = bytes;
-        out->queries.clear();
-        std::deque<SchedQuery> rest;
-        size_t j = 0;
-        for (size_t i = 0; i < q_.size(); ++i) {
-            if (j < pick.size() && pick[j] == i) {
-                out->queries.push_back(q_[i]);
-                ++j;
-            } else {
-                rest.push_back(q_[i]);
-            }
-        }
-        q_.swap(rest);
-        return kLaunch;
+    // Empties the queue (the executor failed): every waiting query.
+    std::vector<SchedQuery> take_all() {
+        std::vector<SchedQuery> out(q_.begin(), q_.end());
+        q_.clear();
+        return out;
     }
 
    private:
-    int max_batch_;
-    int64_t max_wait_ns_;
     size_t budget_;
-    std::function<size_t(int32_t)> footprint_;
+    std::function<QuerySize(int32_t)> size_;
     std::deque<SchedQuery> q_;
 };
 

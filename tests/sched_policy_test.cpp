@@ -1,5 +1,5 @@
-// Host unit test of the server's admission / batching policy (gr_sched.h):
-// an injected clock and footprints, no GPU.  Exits non-zero on failure.
+// Host unit test of the server's admission policy (gr_sched.h): injected
+// query sizes, no GPU.  Exits non-zero on failure.
 #include <cstdio>
 #include <cstdlib>
 
@@ -13,57 +13,60 @@
         }                                                            \
     } while (0)
 
-using gr::BatchPolicy;
-using gr::SchedBatch;
+using gr::QuerySize;
 using gr::SchedQuery;
+using gr::SessionRoom;
+using gr::SlotPolicy;
 
-static SchedQuery q(uint64_t t, int32_t g, int64_t at) { return SchedQuery{t, g, (int32_t)t, nullptr, at}; }
+static SchedQuery q(uint64_t t, int32_t g) { return SchedQuery{t, g, (int32_t)t, nullptr, (int64_t)t}; }
 
 int main() {
-    const int64_t W = 1000;  // max wait
-    // footprint: graph 0 = 100 bytes, graph 1 = 300 bytes
-    BatchPolicy p(4, W, 400, [](int32_t g) { return g == 0 ? (size_t)100 : (size_t)300; });
-    SchedBatch b;
-    int64_t wake = -1;
+    // graph 0: 100 bytes, 10 vertices, 40 arcs; graph 1: 300 bytes, 50 vertices, 200 arcs
+    SlotPolicy p(400, [](int32_t g) { return g == 0 ? QuerySize{100, 10, 40} : QuerySize{300, 50, 200}; });
+    size_t in_flight = 0;
 
-    // empty queue: wait for an event
-    CHECK(p.next(0, 0, false, &b, &wake) == BatchPolicy::kWaitForEvent);
+    // empty queue: nothing admitted
+    CHECK(p.admit(SessionRoom{4, 1000, 1000}, &in_flight).empty());
 
-    // a partial batch waits until the oldest query is max_wait old
-    p.push(q(1, 0, 10));
-    p.push(q(2, 1, 20));
-    p.push(q(3, 0, 30));
-    CHECK(p.next(100, 0, false, &b, &wake) == BatchPolicy::kWaitUntil);
-    CHECK(wake == 10 + W);
-    // ...then launches the oldest query's graph, keeping arrival order
-    CHECK(p.next(10 + W, 0, false, &b, &wake) == BatchPolicy::kLaunch);
-    CHECK(b.graph == 0 && b.queries.size() == 2 && b.queries[0].ticket == 1 && b.queries[1].ticket == 3);
-    CHECK(b.bytes == 100);
-    CHECK(p.pending() == 1);
+    // FIFO order, as many as fit: 0, 1 fit the budget (400); the next 0 does not
+    p.push(q(1, 0));
+    p.push(q(2, 1));
+    p.push(q(3, 0));
+    std::vector<SchedQuery> a = p.admit(SessionRoom{4, 1000, 1000}, &in_flight);
+    CHECK(a.size() == 2 && a[0].ticket == 1 && a[1].ticket == 2);
+    CHECK(in_flight == 400 && p.pending() == 1);
 
-    // graph 1 does not fit next to 200 bytes in flight (budget 400)
-    CHECK(p.next(5000, 200, false, &b, &wake) == BatchPolicy::kWaitForEvent);
-    CHECK(p.next(5000, 100, false, &b, &wake) == BatchPolicy::kLaunch);
-    CHECK(b.graph == 1 && b.queries.size() == 1 && b.queries[0].ticket == 2);
+    // the head waits for memory; a completion (100 bytes back) lets it in
+    CHECK(p.admit(SessionRoom{4, 1000, 1000}, &in_flight).empty());
+    in_flight -= 100;
+    a = p.admit(SessionRoom{4, 1000, 1000}, &in_flight);
+    CHECK(a.size() == 1 && a[0].ticket == 3 && in_flight == 400);
 
-    // a full batch launches at once, at most max_batch queries, FIFO
-    for (uint64_t t = 10; t < 16; ++t) p.push(q(t, 0, 6000));
-    CHECK(p.next(6000, 0, false, &b, &wake) == BatchPolicy::kLaunch);
-    CHECK(b.queries.size() == 4 && b.queries[0].ticket == 10 && b.queries[3].ticket == 13);
-    CHECK(p.pending() == 2);
+    // slots bound admission
+    in_flight = 0;
+    for (uint64_t t = 10; t < 16; ++t) p.push(q(t, 0));
+    a = p.admit(SessionRoom{2, 1000, 1000}, &in_flight);
+    CHECK(a.size() == 2 && a[0].ticket == 10 && a[1].ticket == 11 && in_flight == 200);
+    // queue capacity bounds admission (10 vertices each: 25 entries admit two)
+    in_flight = 0;
+    a = p.admit(SessionRoom{8, 25, 1000}, &in_flight);
+    CHECK(a.size() == 2 && a[0].ticket == 12);
+    // one round's arcs bound admission (40 arcs each: 79 admit one)
+    in_flight = 0;
+    a = p.admit(SessionRoom{8, 1000, 79}, &in_flight);
+    CHECK(a.size() == 1 && a[0].ticket == 14);
+    a = p.admit(SessionRoom{8, 1000, 1000}, &in_flight);
+    CHECK(a.size() == 1 && a[0].ticket == 15 && p.pending() == 0);
 
-    // draining ignores max_wait
-    CHECK(p.next(6001, 0, true, &b, &wake) == BatchPolicy::kLaunch);
-    CHECK(b.queries.size() == 2 && b.queries[0].ticket == 14);
-    CHECK(p.pending() == 0);
-
-    // no starvation: the oldest query's graph goes first even if another graph has more queries
-    p.push(q(20, 1, 7000));
-    for (uint64_t t = 21; t < 25; ++t) p.push(q(t, 0, 7001));
-    CHECK(p.next(7000 + W, 0, false, &b, &wake) == BatchPolicy::kLaunch);
-    CHECK(b.graph == 1 && b.queries[0].ticket == 20);
-    CHECK(p.next(7001, 0, false, &b, &wake) == BatchPolicy::kLaunch);  // graph 0 now full (4)
-    CHECK(b.graph == 0 && b.queries.size() == 4);
+    // no overtaking: a large head blocks smaller queries behind it
+    in_flight = 200;
+    p.push(q(20, 1));
+    p.push(q(21, 0));
+    CHECK(p.admit(SessionRoom{8, 1000, 1000}, &in_flight).empty());
+    CHECK(p.head()->ticket == 20);
+    in_flight = 0;
+    a = p.admit(SessionRoom{8, 1000, 1000}, &in_flight);
+    CHECK(a.size() == 2 && a[0].ticket == 20 && a[1].ticket == 21);
 
     std::printf("ok\n");
     return 0;

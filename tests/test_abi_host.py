@@ -50,7 +50,8 @@ def test_python_binding_names_match_the_c_abi():
         assert hasattr(gr, n), "binding lacks %s" % n
 
 
-STRUCTS = ["gr_sssp_opts", "gr_sssp_stats", "gr_tune_result", "gr_server_config", "gr_query_result"]
+STRUCTS = ["gr_sssp_opts", "gr_sssp_stats", "gr_tune_result", "gr_server_config", "gr_query_result",
+           "gr_multi_stats"]
 
 
 def test_struct_layouts_match_the_header(tmp_path):

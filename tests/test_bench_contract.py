@@ -40,10 +40,10 @@ def test_counter_summary_for_other_sources_or_settings_reads_as_none(tmp_path, m
     (fake / "profiles").mkdir(parents=True)
     csrc = fake / "paper_2212_08200_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for f in ("gr_kernels.hip", "gr_device.h", "gr_internal.h", "gr_batch.hip"):
+    for f in ("gr_kernels.hip", "gr_device.h", "gr_internal.h", "gr_multi.hip", "gr_multi.h"):
         text = open(os.path.join(ROOT, "paper_2212_08200_amd", "csrc", f)).read()
-        (csrc / f).write_text(text + (" " if f == "gr_batch.hip" else ""))
-    name = "k_batch_push_rmat22_counters.md"
+        (csrc / f).write_text(text + (" " if f == "gr_multi.hip" else ""))
+    name = "k_mq_batch_push_rmat22_counters.md"
     (fake / "profiles" / name).write_text(open(os.path.join(ROOT, "profiles", name)).read())
     monkeypatch.setattr(bench, "ROOT", str(fake))
     assert bench.batch_traffic("rmat22") is None

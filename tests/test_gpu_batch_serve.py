@@ -208,7 +208,7 @@ def test_server_errors_and_drain():
     g = gg.rmat(12, 16, gseed=3, pseed=4, wseed=5)
     G = gr.Graph.from_csr(g)
     try:
-        small = gr.gr_server_create(1 << 20)  # 1 MiB: a batch on this graph needs more
+        small = gr.gr_server_create(64 << 10)  # 64 KiB: a query on this graph needs more
         gid = gr.gr_server_add_graph(small, G.handle)
         out = torch.empty(g.n, dtype=torch.int32, device="cuda")
         with pytest.raises(gr.GrError) as ei:

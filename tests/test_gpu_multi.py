@@ -1,0 +1,154 @@
+"""GPU parity of the multi-query engine: gr_sssp_multi (queries on several
+graphs of different sizes and weight types advanced together, the round loop
+replayed from one captured HIP graph) and the statistics of the batched call
+(gr_sssp_batch_ex), against the CPU oracle: every result passes the oracle's
+shortest-path certificate and equals its Dijkstra bit for bit (tolerance 0)."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from certify_rows import certify_all
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+gr = pytest.importorskip("paper_2212_08200_amd")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_multi(Gs, graphs, qs):
+    """qs: list of (graph index, source).  Returns the rows (host) and the statistics."""
+    outs = [torch.full((graphs[gi].n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda") for gi, _ in qs]
+    st = gr.gr_sssp_multi([Gs[gi].handle for gi, _ in qs], [s for _, s in qs], outs)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy().view(np.uint32) for o in outs], st
+
+
+def check(graphs, qs, rows, tag):
+    for i, ((gi, s), got) in enumerate(zip(qs, rows)):
+        want = oracle.dijkstra(graphs[gi], int(s))
+        if not np.array_equal(got, want):
+            v = int(np.flatnonzero(got != want)[0])
+            raise AssertionError("%s query %d (graph %d, src %d): vertex %d got 0x%08x want 0x%08x" % (
+                tag, i, gi, s, v, int(got[v]), int(want[v])))
+        code, v = oracle.certify(graphs[gi], int(s), np.ascontiguousarray(got))
+        assert code == oracle.CERT_OK, "%s query %d: certificate fails at %d" % (tag, i, v)
+
+
+def mixed_graphs():
+    zero = gg.from_arcs(6, [(0, 1, 0), (1, 2, 5), (0, 2, 5), (2, 3, 0), (4, 5, 1), (3, 3, 2)])
+    return [gg.rmat(12, 16, gseed=31, pseed=32, wseed=33),                  # uint32, skewed
+            gg.grid(40, 34, whi=1000),                                      # uint32, many rounds
+            gg.rmat(11, 16, gseed=35, pseed=36, wseed=37, wtype=gg.W_F32),  # binary32
+            gg.uniform(3000, 20000, 38, 39, whi=3),                         # directed, small weights
+            zero,                                                           # zero arcs, self-loop
+            gg.from_arcs(1, []),                                            # a single vertex
+            gg.grid(5000 // 50, 40, whi=20)]                                # 100 x 100 grid
+
+
+def test_multi_mixed_graphs_and_types():
+    graphs = mixed_graphs()
+    Gs = [gr.Graph.from_csr(g) for g in graphs]
+    try:
+        qs = []
+        for gi, g in enumerate(graphs):
+            srcs = [0] if g.n == 1 else [int(s) for s in gg.pick_sources(g, 50 + gi, 3)]
+            qs += [(gi, s) for s in srcs]
+        qs.append((4, 5))  # a source without out-arcs: everything else unreachable
+        qs.append((0, int(qs[0][1])))  # the same query twice in one launch
+        say("multi: %d queries over %d graphs" % (len(qs), len(graphs)))
+        rows, st = run_multi(Gs, graphs, qs)
+        check(graphs, qs, rows, "mixed")
+        assert np.array_equal(rows[0], rows[-1])
+        assert st["rounds"] >= max(st["iterations"]) >= 1 and st["replays"] >= 1
+        assert st["iterations"][-2] == 0  # the source without arcs never had a frontier entry
+        # the same queries in another order and alone give the same rows
+        rev = list(reversed(qs))
+        rows2, _ = run_multi(Gs, graphs, rev)
+        for a, b in zip(rows, reversed(rows2)):
+            assert np.array_equal(a, b)
+        for i in (0, 3, 9):
+            one, _ = run_multi(Gs, graphs, [qs[i]])
+            assert np.array_equal(one[0], rows[i])
+    finally:
+        for G in Gs:
+            G.close()
+
+
+def test_multi_64_queries_serving_shapes():
+    # graphs of the serving workload's kinds and uneven sizes (R-MAT scales 12-15, grids 64-256)
+    graphs = [gg.rmat(12 + i % 4, 16, gseed=60 + i, pseed=61 + i, wseed=62 + i) for i in range(4)] + \
+             [gg.grid(side, 70 + side, whi=255) for side in (64, 128, 256)]
+    Gs = [gr.Graph.from_csr(g) for g in graphs]
+    try:
+        rng = np.random.default_rng(77)
+        qs = []
+        for i in range(64):
+            gi = int(rng.integers(0, len(graphs)))
+            qs.append((gi, int(gg.pick_sources(graphs[gi], 100 + i, 1)[0])))
+        say("multi: 64 queries over %d graphs" % len(graphs))
+        rows, st = run_multi(Gs, graphs, qs)
+        for gi in range(len(graphs)):
+            idx = [i for i, (g2, _) in enumerate(qs) if g2 == gi]
+            if idx:
+                certify_all(graphs[gi], [qs[i][1] for i in idx], [rows[i] for i in idx], "multi64 graph %d" % gi)
+        check(graphs, qs[:8], rows[:8], "multi64")
+        assert st["replays"] >= st["rounds"] // 8
+        # a second call on the same graphs (fresh session, reused pool memory) is exact too
+        rows2, _ = run_multi(Gs, graphs, qs[8:24])
+        for a, b in zip(rows[8:24], rows2):
+            assert np.array_equal(a, b)
+    finally:
+        for G in Gs:
+            G.close()
+
+
+def test_multi_argument_errors():
+    g = gg.grid(8, 3)
+    G = gr.Graph.from_csr(g)
+    try:
+        out = torch.zeros(g.n, dtype=torch.int32, device="cuda")
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_multi([], [], [])
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_multi([G.handle] * 65, [0] * 65, [out] * 65)
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_multi([G.handle, G.handle], [0, g.n], [out, out])
+        assert ei.value.status == gr.GR_ERR_SOURCE_RANGE
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_multi([G.handle], [0], [torch.zeros(g.n - 1, dtype=torch.int32, device="cuda")])
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
+    finally:
+        G.close()
+
+
+def test_batch_statistics_and_rows():
+    g = gg.rmat(14, 16, gseed=81, pseed=82, wseed=83)
+    G = gr.Graph.from_csr(g)
+    try:
+        srcs = gg.pick_sources(g, 84, 40)
+        srcs[5] = srcs[3]  # a duplicate source
+        out = torch.full((len(srcs), g.n), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+        say("batch_ex rmat14 k=40")
+        st = gr.gr_sssp_batch_ex(G.handle, srcs, out)
+        torch.cuda.synchronize()
+        rows = out.cpu().numpy().view(np.uint32)
+        certify_all(g, srcs, rows, "batch_ex")
+        for i in (0, 5, 39):
+            assert np.array_equal(rows[i], oracle.dijkstra(g, int(srcs[i])))
+        assert st["rounds"] >= 1 and st["replays"] >= 1
+        assert st["source_relaxations"] >= st["edges_pushed"] > 0
+        # every source relaxes at least the arcs it reaches, once
+        deg = np.diff(g.ro).astype(np.int64)
+        reached = sum(int(deg[rows[i] != gr.GR_DIST_INF_U32].sum()) for i in range(len(srcs)))
+        assert st["source_relaxations"] >= reached
+    finally:
+        G.close()
