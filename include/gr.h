@@ -178,7 +178,7 @@ typedef enum {
 
 /* Traversal direction policy (Section III-C: push vs pull). */
 typedef enum {
-    GR_DIR_AUTO = 0,      /* switch on frontier work (alpha rule) */
+    GR_DIR_AUTO = 0,      /* switch on frontier size (alpha and beta rules below) */
     GR_DIR_PUSH = 1,      /* push every iteration */
     GR_DIR_PULL = 2,      /* pull every iteration (needs pull enabled) */
     GR_DIR_ALTERNATE = 3  /* push and pull alternately (a test of switching) */
@@ -194,7 +194,9 @@ typedef enum {
 typedef struct {
     int32_t loop;       /* gr_loop_mode */
     int32_t direction;  /* gr_direction */
-    int32_t alpha_x16;  /* pull when frontier out-edges * alpha_x16 >= 16 * m; 0 = default */
+    int32_t alpha_x16;  /* GR_DIR_AUTO, after a push round: pull when frontier out-edges *
+                           alpha_x16 >= 16 * m; 0 = the graph's default (never, unless
+                           gr_graph_tune chose a value) */
     int32_t max_iters;  /* iteration cap; 0 = n + 1 (never reached for w >= 0) */
     int32_t layout;     /* gr_layout */
     int32_t timing;     /* 1: time every operator launch with HIP events (stats *_us fields) */
@@ -216,6 +218,9 @@ typedef struct {
                              min: GR_RELAX_* below.  0 = the graph's default (the bound
                              array on graphs of maximum out-degree > 64, unless
                              gr_graph_tune chose otherwise; breadth-first search: dist). */
+    int32_t beta;         /* GR_DIR_AUTO, after a pull round: keep pulling while the frontier
+                             holds at least n / beta vertices, else push (0 = 24).  Pull ->
+                             push and push -> pull (alpha_x16) are Beamer et al.'s rules. */
 } gr_sssp_opts;
 
 /* Relaxation filters of push (gr_sssp_opts.relax_filter).  Either way the

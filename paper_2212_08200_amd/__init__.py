@@ -95,7 +95,7 @@ class gr_sssp_opts(ctypes.Structure):
     _fields_ = [("loop", ctypes.c_int32), ("direction", ctypes.c_int32), ("alpha_x16", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("layout", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32), ("delta", ctypes.c_uint32),
-                ("relax_filter", ctypes.c_int32)]
+                ("relax_filter", ctypes.c_int32), ("beta", ctypes.c_int32)]
 
 
 class gr_sssp_stats(ctypes.Structure):
@@ -312,12 +312,12 @@ def gr_sssp(g: int, src: int, dist_out, stream=None) -> None:
 
 def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
                max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, barrier_timeout_us=0, delta=0,
-               relax_filter=0) -> dict:
+               relax_filter=0, beta=0) -> dict:
     """delta: near-far split width as weight-type bits (see delta_bits), 0 = graph default, GR_DELTA_OFF = off.
     relax_filter: GR_RELAX_DIST / GR_RELAX_BOUND, 0 = graph default."""
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
                      timing=timing, filter=filter, barrier_timeout_us=barrier_timeout_us, delta=delta,
-                     relax_filter=relax_filter)
+                     relax_filter=relax_filter, beta=beta)
     st = gr_sssp_stats()
     _check(lib().gr_sssp_ex(g, int(src), _out_ptr(dist_out, _graph_n(g), "dist_out"), _stream(stream),
                             ctypes.byref(o), ctypes.byref(st)))
@@ -335,9 +335,11 @@ def gr_bfs(g: int, src: int, depth_out, stream=None) -> None:
 
 
 def gr_bfs_ex(g: int, src: int, depth_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
-              max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, relax_filter=0, barrier_timeout_us=0) -> dict:
+              max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, relax_filter=0, barrier_timeout_us=0,
+              beta=0) -> dict:
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
-                     timing=timing, filter=filter, relax_filter=relax_filter, barrier_timeout_us=barrier_timeout_us)
+                     timing=timing, filter=filter, relax_filter=relax_filter, barrier_timeout_us=barrier_timeout_us,
+                     beta=beta)
     st = gr_sssp_stats()
     _check(lib().gr_bfs_ex(g, int(src), _out_ptr(depth_out, _graph_n(g), "depth_out"), _stream(stream),
                            ctypes.byref(o), ctypes.byref(st)))

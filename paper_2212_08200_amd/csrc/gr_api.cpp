@@ -133,6 +133,9 @@ static constexpr int32_t kPartitionMinN = 1 << 17;
 static inline int32_t locality_span(int32_t n) { return std::max(n / 64, 64); }
 // Small rounds of the queued loop apply to graphs of at most this degree.
 static constexpr int32_t kSmallMaxDegree = 64;
+// Pull -> push when the frontier holds fewer than n / beta vertices (Beamer et
+// al.'s default).
+static constexpr int32_t kDefaultBeta = 24;
 static constexpr int32_t kAsyncDefaultMaxN = 1 << 16;  // see graph_build
 
 struct gr_graph {
@@ -473,6 +476,7 @@ struct RunCfg {
     int loop;
     int direction;
     int32_t alpha_x16;
+    int32_t beta;  // pull -> push when |frontier| * beta < n
     int64_t max_iters;
     bool max_iters_given;  // set by the caller (else the default cap)
     bool timing;
@@ -490,6 +494,8 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
     rc->loop = o ? o->loop : GR_LOOP_AUTO;
     rc->direction = o ? o->direction : GR_DIR_AUTO;
     rc->alpha_x16 = (o && o->alpha_x16 > 0) ? o->alpha_x16 : g->auto_alpha_x16;
+    rc->beta = (o && o->beta > 0) ? o->beta : kDefaultBeta;
+    if (o && o->beta < 0) return fail(GR_ERR_INVALID_ARG, "beta = %d is negative", o->beta);
     rc->max_iters = (o && o->max_iters > 0) ? o->max_iters : (int64_t)g->plain.n + 1;
     rc->max_iters_given = o && o->max_iters > 0;
     const int layout = o ? o->layout : GR_LAYOUT_AUTO;
@@ -543,13 +549,19 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
     return GR_OK;
 }
 
-static bool choose_pull(const gr_graph *g, const RunCfg &rc, int64_t iter, int64_t E) {
+// AUTO: push -> pull when the frontier's out-arcs reach m / alpha; pull ->
+// push when the frontier holds fewer than n / beta vertices (Beamer et al.'s
+// two rules, with hysteresis on the previous round's direction).
+static bool choose_pull(const gr_graph *g, const RunCfg &rc, int64_t iter, int64_t E, int64_t F, bool prev) {
     if (!g->pull) return false;
     switch (rc.direction) {
         case GR_DIR_PUSH: return false;
         case GR_DIR_PULL: return true;
         case GR_DIR_ALTERNATE: return (iter & 1) != 0;
-        default: return rc.alpha_x16 > 0 && E * rc.alpha_x16 >= (int64_t)16 * g->plain.m;
+        default:
+            if (rc.alpha_x16 <= 0) return false;
+            if (prev) return F * rc.beta >= (int64_t)g->plain.n;
+            return E * rc.alpha_x16 >= (int64_t)16 * g->plain.m;
     }
 }
 
@@ -594,6 +606,7 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
         read_counts(hp, &c);
     }
     int64_t iter = 0;
+    bool prev_pull = false;
     while (e == hipSuccess) {
         // An empty frontier ends the query unless the near-far split holds
         // vertices back: then the round only raises the threshold and filters.
@@ -605,7 +618,8 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
         }
         if (idle) T = next_threshold(c.far_min, rc.delta, dg.wt);
         const int64_t E = c.Esum();
-        const bool pull = !idle && choose_pull(g, rc, iter, E);
+        const bool pull = !idle && choose_pull(g, rc, iter, E, c.Fsum(), prev_pull);
+        prev_pull = pull;
         if (timed) (void)hipEventRecord(ev[0], st);
         if (idle) {
         } else if (pull) {
@@ -663,6 +677,7 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     if (cfg.grid < kMaxParts) return fail(GR_ERR_HIP, "no co-resident grid for the device-driven loop");
     cfg.max_iters = (int32_t)std::min<int64_t>(rc.max_iters, INT32_MAX);
     cfg.alpha_x16 = rc.alpha_x16;
+    cfg.beta = rc.beta;
     cfg.direction = rc.direction;
     cfg.filter = rc.filter;
     cfg.dense_ratio = rc.dense_ratio;
@@ -735,12 +750,13 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     if (s != GR_OK) return s;
     unsigned long long *hp = pinned_slot();
     if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
-    static_assert(2 * sizeof(LoopState) <= 256, "pinned slot holds two loop states");
+    static_assert(2 * sizeof(LoopState) <= 8192, "pinned slot holds two loop states");
     const DevGraph &dg = *rc.dg;
     PersistentCfg cfg;
     cfg.grid = di.num_cu * 8;
     cfg.max_iters = (int32_t)std::min<int64_t>(rc.max_iters, INT32_MAX);
     cfg.alpha_x16 = rc.alpha_x16;
+    cfg.beta = rc.beta;
     cfg.direction = rc.direction;
     cfg.filter = rc.filter;
     cfg.dense_ratio = rc.dense_ratio;
@@ -988,6 +1004,7 @@ static gr_status run_queued_fixed(const gr_graph *g, int32_t src, uint32_t *dist
     cfg.grid = di.num_cu * 8;
     cfg.max_iters = (int32_t)std::min<int64_t>(rc.max_iters, INT32_MAX);
     cfg.alpha_x16 = rc.alpha_x16;
+    cfg.beta = rc.beta;
     cfg.direction = rc.direction;
     cfg.filter = rc.filter;
     cfg.dense_ratio = rc.dense_ratio;
@@ -1122,6 +1139,11 @@ static gr_status run_single_auto(const gr_graph *g, int32_t src, uint32_t *dist,
 
 static inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Multi-query rounds whose queue holds fewer than kMqNarrowArcs arcs replay a
+// capture on kMqNarrowGrid blocks per launch.
+static constexpr int kMqNarrowGrid = 256;
+static constexpr int64_t kMqNarrowArcs = 256 * 2048;
+
 // Bytes of the session's control block readback: everything before the slot
 // table (counters, round state, statistics, per-slot round counts).
 static constexpr size_t kMqReadBytes = offsetof(MqCtl, nlive);
@@ -1137,8 +1159,12 @@ struct MqSession {
     void *mem = nullptr;
     MqBufs b{};
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // captured rounds: [0] on the full grids, [1] on narrow grids for rounds
+    // whose queue holds few arcs (the multi-query engine; a launch of many
+    // idle blocks costs more than the work of a short round)
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int nexec = 0;
     unsigned char *h = nullptr;  // pinned: two readback buffers
     bool own_h = false;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1146,8 +1172,10 @@ struct MqSession {
 };
 
 static void mq_destroy(MqSession *s) {
-    if (s->exec) (void)hipGraphExecDestroy(s->exec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
+    for (int i = 0; i < 2; ++i) {
+        if (s->exec[i]) (void)hipGraphExecDestroy(s->exec[i]);
+        if (s->graph[i]) (void)hipGraphDestroy(s->graph[i]);
+    }
     if (s->cap) (void)hipStreamDestroy(s->cap);
     for (auto &e : s->ev)
         if (e) (void)hipEventDestroy(e);
@@ -1228,16 +1256,19 @@ static gr_status mq_create(MqSession *s, int64_t qcap, int rounds, hipStream_t s
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
     // every launch reads its round from the control block, so one capture
     // serves every replay of the session
-    if (e == hipSuccess) e = hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed);
-    if (e == hipSuccess) {
-        hipError_t e1 = hipSuccess;
-        for (int i = 0; i < rounds && e1 == hipSuccess; ++i)
-            e1 = mode.D ? mq_batch_round(s->b, mode.D, mode.wt, s->grid, s->fgrid, s->cap)
-                        : mq_round(s->b, s->grid, s->fgrid, s->cap);
-        e = hipStreamEndCapture(s->cap, &s->graph);
-        if (e == hipSuccess) e = e1;
+    s->nexec = mode.D ? 1 : 2;
+    for (int x = 0; x < s->nexec && e == hipSuccess; ++x) {
+        const int pg = x == 0 ? s->grid : kMqNarrowGrid, fg = x == 0 ? s->fgrid : kMqNarrowGrid;
+        e = hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            hipError_t e1 = hipSuccess;
+            for (int i = 0; i < rounds && e1 == hipSuccess; ++i)
+                e1 = mode.D ? mq_batch_round(s->b, mode.D, mode.wt, pg, fg, s->cap) : mq_round(s->b, pg, fg, s->cap);
+            e = hipStreamEndCapture(s->cap, &s->graph[x]);
+            if (e == hipSuccess) e = e1;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiateWithFlags(&s->exec[x], s->graph[x], 0);
     }
-    if (e == hipSuccess) e = hipGraphInstantiateWithFlags(&s->exec, s->graph, 0);
     if (e == hipSuccess) e = mq_reset(s->b, st);
     if (e != hipSuccess) {
         mq_destroy(s);
@@ -1304,9 +1335,12 @@ static MqRead mq_parse(const unsigned char *h) {
     return r;
 }
 
-// Enqueues one replay of the captured rounds and the readback into buffer i.
-static hipError_t mq_replay(MqSession *s, int i, hipStream_t st) {
-    hipError_t e = hipGraphLaunch(s->exec, st);
+// Enqueues one replay of the captured rounds and the readback into buffer i;
+// last_E: arcs of the latest queue read back (-1: unknown), which picks the
+// narrow grids when it is small.
+static hipError_t mq_replay(MqSession *s, int i, hipStream_t st, int64_t last_E = -1) {
+    const int x = (s->nexec > 1 && last_E >= 0 && last_E < kMqNarrowArcs) ? 1 : 0;
+    hipError_t e = hipGraphLaunch(s->exec[x], st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->h + i * al256(kMqReadBytes), s->b.ctl, kMqReadBytes, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipEventRecord(s->ev[i], st);
@@ -1378,11 +1412,13 @@ extern "C" gr_status gr_sssp_multi(const gr_graph *const *graphs, const int32_t 
     }
     gr_status status = GR_OK;
     MqRead rd{};
+    int64_t last_E = -1;
     while (e == hipSuccess) {
-        e = mq_replay(&ses, 0, st);
+        e = mq_replay(&ses, 0, st, last_E);
         if (e == hipSuccess) e = hipEventSynchronize(ses.ev[0]);
         if (e != hipSuccess) break;
         rd = mq_parse(ses.h);
+        last_E = rd.E;
         if (rd.F == 0) break;
         bool over = false;
         for (int32_t i = 0; i < k; ++i)
@@ -1561,6 +1597,7 @@ static void server_worker(gr_server *s, int exec_id) {
     int64_t used_n = 0, used_m = 0;
     bool live_changed = false;
     int64_t outstanding = -1;  // replay whose readback is pending
+    int64_t last_E = -1;       // arcs of the queue in the latest readback
     gr_status broken = GR_OK;   // a HIP failure ends every query of this executor with it
     if (!st) broken = fail(GR_ERR_HIP, "query server: no stream for an executor");
     std::unique_lock<std::mutex> lk(s->mu);
@@ -1581,6 +1618,7 @@ static void server_worker(gr_server *s, int exec_id) {
                         mq_destroy(&ses);
                         have_ses = false;
                         outstanding = -1;  // nothing live: its readback is not needed
+                        last_E = -1;
                     }
                     gr_status gs = mq_create(&ses, need, kMqRoundsPerReplay, st, MqMode{}, true);
                     lk.lock();
@@ -1679,7 +1717,7 @@ static void server_worker(gr_server *s, int exec_id) {
         int64_t issued = -1;
         if (e == hipSuccess && any_live) {
             issued = ses.replays;
-            e = mq_replay(&ses, (int)(issued & 1), st);
+            e = mq_replay(&ses, (int)(issued & 1), st, last_E);
         }
         // 4. the previous replay's readback
         std::vector<int> done;
@@ -1687,6 +1725,7 @@ static void server_worker(gr_server *s, int exec_id) {
             e = hipEventSynchronize(ses.ev[outstanding & 1]);
             if (e == hipSuccess) {
                 const MqRead rd = mq_parse(ses.h + (outstanding & 1) * al256(kMqReadBytes));
+                last_E = rd.E;
                 for (int i = 0; i < kMqSlots; ++i)
                     if (used[i] && outstanding >= slot[i].admit_replay && rd.slot_cnt[i] == 0ull) {
                         done.push_back(i);

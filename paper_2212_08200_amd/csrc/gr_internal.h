@@ -70,6 +70,9 @@ struct DevGraph {
 //                    then the device-driven loop state
 struct Frontier {
     uint8_t *flags[2];
+    uint32_t *bits;  // the frontier as one bit per vertex (word w: vertices 32w .. 32w + 31), written by
+                     // the filter for the next round and by init; read by pull
+
     uint8_t *far[2];
     int32_t *cand[2];  // candidate lists of the small rounds (queued loop)
     unsigned long long *ccount;  // their counters: 3 rounds x kCandRegions
@@ -116,6 +119,8 @@ struct LoopState {
     unsigned long long st_round[2];  // queued loop state machine, by launch parity: round ...
     unsigned long long st_phase[2];  // ... and phase the launch runs
     unsigned long long small_rounds;
+    unsigned long long last_pull[2];  // queued loop: whether the advance of round r pulled, at r & 1
+                                      // (direction hysteresis; read one round later)
 };
 static_assert(kLoopStateWord + sizeof(LoopState) / 8 <= kCtlWords, "loop state fits the control block");
 // Small-round statistics by candidate region: expanded vertices with arcs in
@@ -152,7 +157,12 @@ hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Fro
                        bool use_far, hipStream_t st);
 hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, const FrontierCounts &c,
                        int num_cu, hipStream_t st);
+// Pull over the partitioned layout when the graph is symmetric (arcs into a
+// destination range from sources in partition k are read by blocks on XCD k),
+// else over the transposed copy.
 hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st);
+// The pull that launch_pull runs: 1 partitioned, 0 over the transposed copy.
+bool pull_partitioned(const DevGraph &g);
 // zmask: optional per-vertex 64-bit masks (batched queries) cleared by the filter.
 // dense: stream the membership lists (large frontiers) instead of visiting
 // the 4096-vertex groups that hold flags (small frontiers).
@@ -167,6 +177,7 @@ unsigned long long *counters_after(const Frontier &f, int64_t iter);
 struct PersistentCfg {
     int32_t max_iters;
     int32_t alpha_x16;
+    int32_t beta;         // pull -> push when |frontier| * beta < n
     int32_t direction;    // gr_direction
     int32_t filter;       // 0 auto, 1 group, 2 streaming
     int32_t dense_ratio;  // auto filter: streaming when |frontier| * dense_ratio >= n
@@ -240,21 +251,8 @@ hipError_t launch_async(const DevGraph &g, uint32_t *dist, const Frontier &f, vo
 // Restarts the list with the spilled vertices (those past cap stay spilled).
 hipError_t launch_async_relist(const DevGraph &g, const Frontier &f, void *ws, int64_t cap, hipStream_t st);
 
-// Batched multi-source (gr_batch.hip): up to kBatchLanes sources, one per
-// wave lane, distances vertex-major D[v * kBatchLanes + s].
+// Batched multi-source queries: up to kBatchLanes sources, one per wave lane
+// (gr_multi.hip).
 constexpr int kBatchLanes = 64;
-struct BatchWs {
-    uint32_t *D;
-    uint64_t *mask[2];   // per-vertex active-source masks, by iteration parity
-    Frontier f;          // shared frontier (flags, one-partition queue, counters)
-    uint32_t **out_ptrs; // device array: output row pointer of each slot
-    int32_t *srcs;       // device array: source of each slot
-};
-size_t batch_bytes(const DevGraph &g);
-void batch_carve(BatchWs &w, void *base, const DevGraph &g);
-hipError_t launch_batch_init(const DevGraph &g, const BatchWs &w, int32_t k, hipStream_t st);
-hipError_t launch_batch_push(const DevGraph &g, const BatchWs &w, int64_t iter, int32_t F, int32_t E, int num_cu,
-                             hipStream_t st);
-hipError_t launch_batch_output(const DevGraph &g, const BatchWs &w, int32_t k, hipStream_t st);
 
 }  // namespace gr

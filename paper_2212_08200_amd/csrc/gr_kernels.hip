@@ -1,7 +1,8 @@
 // HIP kernels for frontier-driven SSSP on gfx950 (MI355X).
 //
 // Operators (Osama et al., Section IV-C) on a CSR graph (Section IV-A) and a
-// frontier kept both as a dense bitmap and as sparse queues (Section IV-B):
+// frontier kept as byte marks (written by push), a dense bitmap (one bit per
+// vertex, read by pull) and sparse queues (Section IV-B):
 //   k_init    dist = INF, dist[src] = 0, frontier = {src} (Listing 4 set-up)
 //   k_push    advance, push direction (Listing 3, with Listing 4's condition):
 //             every out-edge of the sparse frontier is relaxed with an atomic
@@ -92,6 +93,7 @@ struct InitArgs {
     int32_t src;
     const int32_t *pro;
     uint8_t *flags0, *flags1;
+    uint32_t *bits;        // frontier bitmap
     uint8_t *far0, *far1;  // NULL when the near-far split is off
     unsigned long long *ccount;  // candidate-list counters (queued loop), NULL if absent
     uint32_t *bound;             // relaxation filter (see relax_bound), NULL if off
@@ -122,6 +124,7 @@ __global__ __launch_bounds__(kBlk) void k_init(InitArgs a) {
         if (w == sw) reinterpret_cast<uint32_t *>(&z)[(src >> 2) & 3] = 1u << ((src & 3) * 8);
         reinterpret_cast<uint4 *>(a.flags0)[w] = z;
     }
+    for (int64_t w = tid; w < a.nflag / 32; w += stride) a.bits[w] = (w == (src >> 5)) ? 1u << (src & 31) : 0u;
     if (blockIdx.x == 0) {
         for (int t = threadIdx.x; t < kCtlWords; t += kBlk) a.ctl[t] = 0ull;
         __syncthreads();
@@ -328,15 +331,19 @@ __global__ __launch_bounds__(kBlk) void k_push(PushArgs a) {
 // pull advance: block owns vertices [v0, v0 + kBlk); its in-arcs are the
 // contiguous CSC range [ro_in[v0], ro_in[v0 + kBlk]).  Lanes stride over that
 // range, map each arc to its owner by binary search in LDS, and fold the
-// candidates dist[u] (+) w of active u into an LDS min per owner.  Then each
-// owner compares with dist[v], stores the improvement (it is the only writer
-// of dist[v] in this launch) and each wave writes its 64-bit bitmap word.
+// candidates dist[u] (+) w of active u (bit u of the frontier bitmap) into an
+// LDS min per owner.  Then each owner compares with dist[v], stores the
+// improvement (it is the only writer of dist[v] in this launch) and marks v.
 constexpr int kPullItems = 8;
+
+__device__ __forceinline__ bool in_frontier(const uint32_t *__restrict__ bits, uint32_t u) {
+    return (bits[u >> 5] >> (u & 31)) & 1u;
+}
 
 template <int WT>
 __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict__ ro_in,
                                            const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
-                                           const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags,
+                                           const uint32_t *__restrict__ cbits, uint8_t *__restrict__ nflags,
                                            uint32_t *__restrict__ bound, int64_t vb) {
     __shared__ int32_t sOff[kBlk + 1];
     __shared__ uint32_t sMin[kBlk];
@@ -359,9 +366,9 @@ __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict_
             xr[it] = min(x0 + it * kBlk, a1 - 1);
             arc[it] = load_arc(adj_in + xr[it]);
         }
-        uint8_t fl[kPullItems];
+        bool fl[kPullItems];
 #pragma unroll
-        for (int it = 0; it < kPullItems; ++it) fl[it] = cflags[arc[it].x];
+        for (int it = 0; it < kPullItems; ++it) fl[it] = in_frontier(cbits, arc[it].x);
         // distances only of active in-neighbours (the loads stay batched:
         // each one is predicated on its own lane's flag)
         uint32_t du[kPullItems];
@@ -404,7 +411,7 @@ __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict_
 // unreached owners and searched like the push's windows.
 __device__ __forceinline__ void pull_block_bfs(int32_t n, const int32_t *__restrict__ ro_in,
                                                const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
-                                               const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags,
+                                               const uint32_t *__restrict__ cbits, uint8_t *__restrict__ nflags,
                                                uint32_t *__restrict__ bound, int64_t vb) {
     __shared__ int32_t sPre[kBlk + 1];
     __shared__ int32_t sStart[kBlk];
@@ -444,9 +451,9 @@ __device__ __forceinline__ void pull_block_bfs(int32_t n, const int32_t *__restr
         uint2 arc[kPullItems];
 #pragma unroll
         for (int it = 0; it < kPullItems; ++it) arc[it] = load_arc(adj_in + sStart[pos[it]] + (xr[it] - sPre[pos[it]]));
-        uint8_t fl[kPullItems];
+        bool fl[kPullItems];
 #pragma unroll
-        for (int it = 0; it < kPullItems; ++it) fl[it] = cflags[arc[it].x];
+        for (int it = 0; it < kPullItems; ++it) fl[it] = in_frontier(cbits, arc[it].x);
         uint32_t du[kPullItems];
 #pragma unroll
         for (int it = 0; it < kPullItems; ++it) du[it] = fl[it] ? dist[arc[it].x] : kInfU32;
@@ -465,13 +472,90 @@ __device__ __forceinline__ void pull_block_bfs(int32_t n, const int32_t *__restr
     }
 }
 
+// Partitioned pull (symmetric graphs with the partitioned layout): the
+// in-arcs of v are its out-arcs, and those from sources in partition k are
+// the contiguous run padj[pro[v*8 + k] .. pro[(v+1)*8 + k]) -- so block b,
+// placed on XCD b % 8 like the push's blocks, takes partition k = b % 8 and
+// the 256 destinations of chunk b / 8, and its gathers of the frontier bits
+// and distances of the sources stay in that XCD's slice (a 64 KB bitmap
+// slice and a 2 MB distance slice at n = 4M), the same locality the
+// partitioned push gets for its destinations.  Each block folds its
+// candidates into an LDS min per destination; the eight blocks of a chunk
+// then combine theirs with an atomic min, issued only when the candidate is
+// below the distance read (the same rule as push's relaxation).
+template <int WT>
+__device__ __forceinline__ void pull_part_block(int32_t n, const int32_t *__restrict__ pro,
+                                                const uint2 *__restrict__ padj, uint32_t *__restrict__ dist,
+                                                const uint32_t *__restrict__ cbits, uint8_t *__restrict__ nflags,
+                                                uint32_t *__restrict__ bound, int64_t vb) {
+    __shared__ int32_t sOff[kBlk + 1];
+    __shared__ uint32_t sMin[kBlk];
+    const int k = (int)(vb % kMaxParts);
+    const int32_t v0 = (int32_t)((vb / kMaxParts) * kBlk);
+    const int32_t nv = min(kBlk, n - v0);
+    for (int t = threadIdx.x; t <= kBlk; t += kBlk)
+        sOff[t] = (t <= nv) ? pro[(int64_t)(v0 + t) * kMaxParts + k] : INT32_MAX;
+    sMin[threadIdx.x] = kInfU32;
+    __syncthreads();
+    const int32_t a0 = sOff[0], a1 = sOff[nv];
+    const uint32_t inf = WT == 0 ? kInfU32 : kInfF32;
+    for (int32_t x0 = a0 + threadIdx.x; x0 < a1; x0 += kBlk * kPullItems) {
+        int32_t xr[kPullItems];
+        uint2 arc[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) {
+            xr[it] = min(x0 + it * kBlk, a1 - 1);
+            arc[it] = load_arc(padj + xr[it]);
+        }
+        bool fl[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) fl[it] = in_frontier(cbits, arc[it].x);
+        uint32_t du[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) du[it] = fl[it] ? dist[arc[it].x] : inf;
+        int32_t pos[kPullItems];
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) pos[it] = 0;
+#pragma unroll
+        for (int b = kBlk / 2; b >= 1; b >>= 1) {
+#pragma unroll
+            for (int it = 0; it < kPullItems; ++it) {
+                const int32_t p = pos[it] + b;
+                pos[it] = (sOff[p] <= xr[it]) ? p : pos[it];
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kPullItems; ++it) {
+            const bool act = (x0 + it * kBlk < a1) && du[it] != inf;
+            if (act) atomicMin(&sMin[pos[it]], plus<WT>(du[it], arc[it].y));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        const uint32_t v = (uint32_t)(v0 + threadIdx.x);
+        const uint32_t cand = sMin[threadIdx.x];
+        if (cand < (bound ? bound[v] : dist[v])) {
+            if (bound) relax_bound<false>(dist, bound, nflags, v, cand);
+            else relax_commit<false>(dist, nflags, v, cand);
+        }
+    }
+}
+
 template <int WT>
 __global__ __launch_bounds__(kBlk) void k_pull(int32_t n, const int32_t *__restrict__ ro_in,
                                                const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
-                                               const uint8_t *__restrict__ cflags, uint8_t *__restrict__ nflags,
+                                               const uint32_t *__restrict__ cbits, uint8_t *__restrict__ nflags,
                                                uint32_t *__restrict__ bound) {
-    if constexpr (WT == 2) pull_block_bfs(n, ro_in, adj_in, dist, cflags, nflags, bound, blockIdx.x);
-    else pull_block<WT>(n, ro_in, adj_in, dist, cflags, nflags, bound, blockIdx.x);
+    if constexpr (WT == 2) pull_block_bfs(n, ro_in, adj_in, dist, cbits, nflags, bound, blockIdx.x);
+    else pull_block<WT>(n, ro_in, adj_in, dist, cbits, nflags, bound, blockIdx.x);
+}
+
+template <int WT>
+__global__ __launch_bounds__(kBlk) void k_pull_part(int32_t n, const int32_t *__restrict__ pro,
+                                                    const uint2 *__restrict__ padj, uint32_t *__restrict__ dist,
+                                                    const uint32_t *__restrict__ cbits, uint8_t *__restrict__ nflags,
+                                                    uint32_t *__restrict__ bound) {
+    pull_part_block<WT>(n, pro, padj, dist, cbits, nflags, bound, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -494,6 +578,7 @@ struct FilterArgs {
     const uint8_t *far_cur;  // near-far split (NULL: off): held-back flags read ...
     uint8_t *far_next;       // ... and written
     uint32_t threshold;
+    uint16_t *nbits;         // the next frontier's bitmap, 16 vertices per granule (NULL: not kept)
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
     unsigned long long *ctl_next;
@@ -610,6 +695,7 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t g, con
             atomicMax(ctl_next + kFarMaxInvWord, (unsigned long long)sh_far_inv);
         }
     }
+    if (a.nbits) a.nbits[base >> 4] = (uint16_t)mask16;
     if (!__syncthreads_or(mask16 != 0)) return;  // uniform per block
 
     // x[k] = entries of partition k, x[NP + k] = their arcs
@@ -686,6 +772,7 @@ struct DenseFilterArgs {
     const uint8_t *far_cur;  // as in FilterArgs
     uint8_t *far_next;
     uint32_t threshold;
+    uint16_t *nbits;         // as in FilterArgs
     uint2 *qse[kMaxParts];
     int32_t *qs[kMaxParts];
     unsigned long long *ctl_next;
@@ -718,11 +805,14 @@ __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t v
             reinterpret_cast<uint4 *>(cflags)[w] = make_uint4(0u, 0u, 0u, 0u);
             if (zmask)
                 for (int q = 0; q < 16; ++q) zmask[w * 16 + q] = 0ull;
+            uint32_t nb = (far_cur || a.nbits) ? nonzero_bytes(reinterpret_cast<const uint4 *>(nflags)[w]) : 0u;
             if (far_cur) {
-                const uint32_t cand = nonzero_bytes(reinterpret_cast<const uint4 *>(nflags)[w]) |
-                                      nonzero_bytes(reinterpret_cast<const uint4 *>(far_cur)[w]);
-                reinterpret_cast<uint4 *>(far_next)[w] = bytes_of_bits(held_back(a.dist, w * 16, cand, T, &cnt, &inv));
+                const uint32_t cand = nb | nonzero_bytes(reinterpret_cast<const uint4 *>(far_cur)[w]);
+                const uint32_t held = held_back(a.dist, w * 16, cand, T, &cnt, &inv);
+                reinterpret_cast<uint4 *>(far_next)[w] = bytes_of_bits(held);
+                nb = cand & ~held;
             }
+            if (a.nbits) a.nbits[w] = (uint16_t)nb;
         }
         if (far_cur) {
             __syncthreads();
@@ -846,7 +936,9 @@ struct PersistArgs {
     uint8_t *far[2];      // NULL when the near-far split is off
     unsigned long long *ctl;
     int32_t n, m, ngroups;
-    int32_t max_iters, alpha_x16, direction, filter, dense_ratio;
+    int32_t max_iters, alpha_x16, beta, direction, filter, dense_ratio;
+    const uint32_t *bits;  // the current frontier's bitmap (pull)
+    int32_t part_pull;     // pull over the partitioned layout (symmetric graphs)
     uint32_t delta;
     uint64_t spin_ticks;
     // queued loop, small rounds: the CSR as given, the candidate lists (in
@@ -895,13 +987,39 @@ __device__ __forceinline__ uint32_t next_threshold_dev(uint32_t far_min, uint32_
     return t > far_min ? t : far_min + 1u;
 }
 
-__device__ __forceinline__ bool pick_pull(const PersistArgs &a, int64_t iter, int64_t Es) {
+// Direction of round iter.  AUTO: push -> pull when the frontier's out-arcs
+// reach m / alpha (Es * alpha_x16 >= 16 m); pull -> push when the frontier
+// holds fewer than n / beta vertices (the two switching rules of Beamer et
+// al., with hysteresis: prev is the direction of the previous round).
+__device__ __forceinline__ bool pick_pull(const PersistArgs &a, int64_t iter, int64_t Es, int64_t Fs, bool prev) {
     switch (a.direction) {
         case 1: return false;
         case 2: return true;
         case 3: return (iter & 1) != 0;
-        default: return a.alpha_x16 > 0 && Es * a.alpha_x16 >= (int64_t)16 * a.m;
+        default:
+            if (a.alpha_x16 <= 0) return false;
+            if (prev) return Fs * a.beta >= (int64_t)a.n;
+            return Es * a.alpha_x16 >= (int64_t)16 * a.m;
     }
+}
+
+// One block's share of a pull round (blocks vb of nvb = pull_blocks()).
+template <int WT, int NP>
+__device__ __forceinline__ void pull_share(const PersistArgs &a, uint8_t *nf, int64_t vb) {
+    if constexpr (WT == 2) {
+        pull_block_bfs(a.n, a.ro_in, a.adj_in, a.dist, a.bits, nf, a.bound, vb);
+    } else if constexpr (NP == kMaxParts) {
+        if (a.part_pull) pull_part_block<WT>(a.n, a.fg.pro, a.padj, a.dist, a.bits, nf, a.bound, vb);
+        else pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, a.bits, nf, a.bound, vb);
+    } else {
+        pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, a.bits, nf, a.bound, vb);
+    }
+}
+
+template <int WT, int NP>
+__device__ __forceinline__ int64_t pull_blocks(const PersistArgs &a) {
+    const int64_t chunks = ((int64_t)a.n + kBlk - 1) / kBlk;
+    return (WT != 2 && NP == kMaxParts && a.part_pull) ? chunks * kMaxParts : chunks;
 }
 
 template <int WT, int NP>
@@ -910,6 +1028,7 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
     const int64_t G = gridDim.x, b = blockIdx.x;
     const int kb = (int)(b % NP);
     const int64_t jb = b / NP, B = G / NP;
+    bool prev_pull = false;  // every block takes the same decisions from the same counters
     for (int64_t iter = 0;; ++iter) {
         const SlotTotals t = slot_totals<NP>(a.ctl + (iter % kCtlSlots) * kSlotWords, kb);
         if ((t.Fs == 0 && t.far_cnt == 0) || iter >= a.max_iters) {
@@ -922,7 +1041,8 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
         // An empty frontier with held-back vertices: this round only raises
         // the near-far threshold and filters.
         const bool idle = t.Fs == 0;
-        const bool pull = !idle && pick_pull(a, iter, t.Es);
+        const bool pull = !idle && pick_pull(a, iter, t.Es, t.Fs, prev_pull);
+        prev_pull = pull;
         uint8_t *cf = a.flags[iter & 1];
         uint8_t *nf = a.flags[(iter + 1) & 1];
         if (idle) {
@@ -930,8 +1050,8 @@ __global__ __launch_bounds__(kBlk) void k_persistent(PersistArgs a) {
                 __hip_atomic_store(&ls->threshold, (unsigned long long)next_threshold_dev<WT>(t.far_min, a.delta),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (pull) {
-            const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
-            for (int64_t vb = b; vb < nvb; vb += G) pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, a.bound, vb);
+            const int64_t nvb = pull_blocks<WT, NP>(a);
+            for (int64_t vb = b; vb < nvb; vb += G) pull_share<WT, NP>(a, nf, vb);
         } else {
             const int32_t per = (int32_t)max<int64_t>(kMinChunk, ((int64_t)t.Ek + B - 1) / B);
             push_range<WT, false>(a.padj, a.dist, a.fg.qse[kb], a.fg.qs[kb], t.Fk, t.Ek, per, jb, nf,
@@ -1242,7 +1362,10 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
             // round r + 1 may run later and add into it)
             if (b == 0)
                 for (int t = threadIdx.x; t < kSlotWords; t += kBlk) a.ctl[((r + 2) % kCtlSlots) * kSlotWords + t] = 0ull;
-            if (lead) ls->small_rounds += 1ull;
+            if (lead) {
+                ls->small_rounds += 1ull;
+                ls->last_pull[r & 1] = 0ull;
+            }
             small_round<WT, O32>(a, r, ls, sPre);
             ran = kRanSmall;
             next_r = r + 1;
@@ -1266,10 +1389,14 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
             // counters of round r + 2's list (last read when round r - 1 began)
             if (b == 0 && threadIdx.x < kCandRegions) a.ccount[((r + 2) % 3) * kCandRegions + threadIdx.x] = 0ull;
             if (t.Fs == 0) {  // held-back vertices only: raise the threshold, the filter releases them
-                if (lead) ls->threshold = next_threshold_dev<WT>(t.far_min, a.delta);
-            } else {
-                const bool pull = pick_pull(a, r, t.Es);
                 if (lead) {
+                    ls->threshold = next_threshold_dev<WT>(t.far_min, a.delta);
+                    ls->last_pull[r & 1] = 0ull;
+                }
+            } else {
+                const bool pull = pick_pull(a, r, t.Es, t.Fs, ls->last_pull[(r + 1) & 1] != 0ull);
+                if (lead) {
+                    ls->last_pull[r & 1] = pull ? 1ull : 0ull;
                     ls->frontier_sum += (unsigned long long)t.Fs;
                     if ((unsigned long long)t.Fs > ls->frontier_max) ls->frontier_max = (unsigned long long)t.Fs;
                     if (pull) {
@@ -1280,14 +1407,10 @@ __global__ __launch_bounds__(kBlk) void k_step(PersistArgs a, int64_t launch) {
                         ls->push_frontier_sum += (unsigned long long)t.Fs;
                     }
                 }
-                uint8_t *cf = a.flags[r & 1];
                 uint8_t *nf = a.flags[(r + 1) & 1];
                 if (pull) {
-                    const int64_t nvb = ((int64_t)a.n + kBlk - 1) / kBlk;
-                    for (int64_t vb = b; vb < nvb; vb += G) {
-                        if constexpr (WT == 2) pull_block_bfs(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, a.bound, vb);
-                        else pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, cf, nf, a.bound, vb);
-                    }
+                    const int64_t nvb = pull_blocks<WT, NP>(a);
+                    for (int64_t vb = b; vb < nvb; vb += G) pull_share<WT, NP>(a, nf, vb);
                 } else {
                     // Candidate appends only when this round cannot improve many
                     // more vertices than the list holds (a too-long list just
@@ -1636,6 +1759,7 @@ hipError_t launch_init(const DevGraph &g, uint32_t *dist, int32_t src, const Fro
     a.pro = g.pro;
     a.flags0 = f.flags[0];
     a.flags1 = f.flags[1];
+    a.bits = f.bits;
     a.ccount = f.ccount;
     a.rstat = f.rstat;
     a.bound = f.bound;
@@ -1699,18 +1823,25 @@ hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int
     return hipGetLastError();
 }
 
-hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st) {
-    const int grid = (g.n + kBlk - 1) / kBlk;
+bool pull_partitioned(const DevGraph &g) { return g.np == kMaxParts && g.ro_in == g.ro && g.adj_in == g.adj; }
+
+template <int WT>
+static void pull_dispatch(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st) {
     const int p = (int)(iter & 1), np1 = p ^ 1;
-    if (g.wt == 1)
-        hipLaunchKernelGGL(k_pull<1>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
-                           f.flags[np1], f.bound);
-    else if (g.wt == 2)
-        hipLaunchKernelGGL(k_pull<2>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
-                           f.flags[np1], f.bound);
+    const int64_t chunks = (g.n + kBlk - 1) / kBlk;
+    if (WT != 2 && pull_partitioned(g))
+        hipLaunchKernelGGL(k_pull_part<WT>, dim3((unsigned)(chunks * kMaxParts)), dim3(kBlk), 0, st, g.n, g.pro,
+                           g.padj, dist, f.bits, f.flags[np1], f.bound);
     else
-        hipLaunchKernelGGL(k_pull<0>, dim3(grid), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.flags[p],
+        hipLaunchKernelGGL(k_pull<WT>, dim3((unsigned)chunks), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.bits,
                            f.flags[np1], f.bound);
+    (void)p;
+}
+
+hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st) {
+    if (g.wt == 1) pull_dispatch<1>(g, dist, f, iter, st);
+    else if (g.wt == 2) pull_dispatch<2>(g, dist, f, iter, st);
+    else pull_dispatch<0>(g, dist, f, iter, st);
     return hipGetLastError();
 }
 
@@ -1743,6 +1874,7 @@ hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uin
         a.far_cur = use_far ? f.far[p] : nullptr;
         a.far_next = use_far ? f.far[p ^ 1] : nullptr;
         a.threshold = threshold;
+        a.nbits = reinterpret_cast<uint16_t *>(f.bits);
         hipLaunchKernelGGL(k_filter_dense, dim3((unsigned)blocks), dim3(kBlk), 0, st, a);
         return hipGetLastError();
     }
@@ -1762,6 +1894,7 @@ hipError_t launch_filter(const DevGraph &g, const Frontier &f, int64_t iter, uin
     a.far_cur = use_far ? f.far[p] : nullptr;
     a.far_next = use_far ? f.far[p ^ 1] : nullptr;
     a.threshold = threshold;
+    a.nbits = reinterpret_cast<uint16_t *>(f.bits);
     if (g.np == 1) hipLaunchKernelGGL(k_filter<1>, dim3(f.ngroups), dim3(kBlk), 0, st, a);
     else hipLaunchKernelGGL(k_filter<kMaxParts>, dim3(f.ngroups), dim3(kBlk), 0, st, a);
     return hipGetLastError();
@@ -1907,6 +2040,7 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     fg.far_cur = nullptr;
     fg.far_next = nullptr;
     fg.threshold = 0u;
+    fg.nbits = reinterpret_cast<uint16_t *>(f.bits);
     fg.nflags = nullptr;
     fg.cflags = nullptr;
     fg.ctl_next = nullptr;
@@ -1928,6 +2062,7 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     fd.far_cur = nullptr;
     fd.far_next = nullptr;
     fd.threshold = 0u;
+    fd.nbits = reinterpret_cast<uint16_t *>(f.bits);
     fd.ctl_next = nullptr;
     fd.ctl_zero = nullptr;
     for (int k = 0; k < kMaxParts; ++k) {
@@ -1960,6 +2095,9 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     a.ngroups = f.ngroups;
     a.max_iters = cfg.max_iters;
     a.alpha_x16 = cfg.alpha_x16;
+    a.beta = cfg.beta > 0 ? cfg.beta : 24;
+    a.bits = f.bits;
+    a.part_pull = pull_partitioned(g) ? 1 : 0;
     a.direction = cfg.direction;
     a.filter = cfg.filter;
     a.dense_ratio = cfg.dense_ratio;
@@ -2018,6 +2156,7 @@ size_t frontier_bytes(const DevGraph &g) {
     const int64_t ng = groups_for(g.n);
     size_t b = 0;
     b += 4 * align256((size_t)ng * kGroupVerts);  // flags, held-back flags
+    b += align256((size_t)ng * kGroupVerts / 8);   // frontier bitmap
     b += 2 * align256(sizeof(int32_t) * (size_t)cand_capacity(g.n));
     b += align256(sizeof(unsigned long long) * 3 * kCandRegions);
     b += align256(sizeof(unsigned long long) * kStatWords);
@@ -2044,6 +2183,8 @@ void frontier_carve(Frontier &f, void *base, const DevGraph &g) {
         f.far[i] = reinterpret_cast<uint8_t *>(p);
         p += align256((size_t)f.nflag);
     }
+    f.bits = reinterpret_cast<uint32_t *>(p);
+    p += align256((size_t)f.nflag / 8);
     f.cand_cap = cand_capacity(g.n);
     for (int i = 0; i < 2; ++i) {
         f.cand[i] = reinterpret_cast<int32_t *>(p);

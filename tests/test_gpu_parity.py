@@ -59,8 +59,6 @@ def check_all_dirs(g, srcs, tag, dirs=("push", "auto", "pull", "alternate"), fla
                 for d in dirs:
                     if d in ("pull", "alternate") and not info["pull_enabled"]:
                         continue
-                    if d == "pull" and lay != layouts[0]:
-                        continue  # pull does not use the push layout
                     for lp in loops:
                         for rf in RELAX if d != "pull" else RELAX[:1]:
                             say("case %s src=%d dir=%s layout=%d loop=%s relax=%d n=%d m=%d" % (
@@ -182,6 +180,39 @@ def test_persistent_loop_stats_match_host_loop():
             st = gr.gr_sssp_ex(G.handle, 0, dist, loop=LOOPS[lp], timing=1)
             torch.cuda.synchronize()
             assert st["push_us"] > 0 and st["iterations"] == L, lp
+    finally:
+        G.close()
+
+
+def test_direction_switch_alpha_beta_rules():
+    """AUTO switching (Beamer et al.'s two rules): push -> pull once the frontier's
+    out-arcs reach m / alpha, pull -> push once the frontier holds fewer than
+    n / beta vertices.  beta = 1 leaves pull after every pull round; a huge beta
+    keeps pulling to the end.  Both pulls (over the partitioned layout and over
+    the transposed copy) and every loop driver give the oracle's distances."""
+    g = gg.rmat(14, 16, gseed=41, pseed=42, wseed=43)
+    G = gr.Graph.from_csr(g, flags=gr.GR_FORCE_PARTITION)
+    try:
+        dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        for s in [int(x) for x in gg.pick_sources(g, 44, 2)]:
+            want = oracle.dijkstra(g, s)
+            for lay in (gr.GR_LAYOUT_PLAIN, gr.GR_LAYOUT_PARTITIONED):
+                for lp in ("host", "persistent", "queued"):
+                    pulls = {}
+                    for beta in (1, 1 << 30):
+                        say("alpha/beta rmat14 src=%d layout=%d loop=%s beta=%d" % (s, lay, lp, beta))
+                        st = gr.gr_sssp_ex(G.handle, s, dist, loop=LOOPS[lp], layout=lay, alpha_x16=64, beta=beta)
+                        torch.cuda.synchronize()
+                        assert_same(dist.cpu().numpy().view(np.uint32), want, "alpha/beta %s beta %d" % (lp, beta))
+                        pulls[beta] = (st["pull_iterations"], st["iterations"])
+                    p1, it1 = pulls[1]
+                    pb, itb = pulls[1 << 30]
+                    assert p1 >= 1, "the alpha rule never switched to pull"
+                    assert p1 <= (it1 + 1) // 2, "beta = 1 pulled twice in a row"
+                    assert pb >= p1 and pb >= 2  # a huge beta keeps pulling once it started
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_ex(G.handle, 0, dist, beta=-1)
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
     finally:
         G.close()
 
