@@ -80,6 +80,9 @@ def main():
                     help="near-far split width in weight units (0: the graph's default)")
     ap.add_argument("--relax", type=int, default=0,
                     help="push relaxation filter (0 graph default, 1 pre-read dist, 2 upper-bound array)")
+    ap.add_argument("--local-hops", type=int, default=0,
+                    help="small rounds: hops a block expands before handing improvements to the next round "
+                         "(0: the graph's default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-source batched comparison")
@@ -93,6 +96,7 @@ def main():
     ap.add_argument("--serve-executors", type=int, default=1,
                     help="server: executors (each a stream with its own multi-query session)")
     ap.add_argument("--serve-slots", type=int, default=64, help="server: live queries per executor")
+    ap.add_argument("--serve-local-hops", type=int, default=0, help="server: local hops (0: the library's default)")
     ap.add_argument("--bfs", action="store_true",
                     help="time breadth-first search (gr_bfs_ex) instead of SSSP on the same workload")
     ap.add_argument("--no-tune", action="store_true",
@@ -143,10 +147,12 @@ def main():
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
     opts = dict(loop=args.loop, direction=args.direction, layout=args.layout, filter=args.filter, alpha_x16=args.alpha,
-                delta=gr.delta_bits(args.delta, g.wtype) if args.delta > 0 else 0, relax_filter=args.relax)
+                delta=gr.delta_bits(args.delta, g.wtype) if args.delta > 0 else 0, relax_filter=args.relax,
+                local_hops=args.local_hops)
 
     tuned = None
-    explicit = args.loop or args.direction or args.layout or args.filter or args.alpha or args.delta or args.relax
+    explicit = (args.loop or args.direction or args.layout or args.filter or args.alpha or args.delta or args.relax
+                or args.local_hops)
     if not args.no_tune and not explicit and not args.bfs:
         # the autotuner picks the AUTO schedule from a few of the workload's sources
         t0 = time.time()
@@ -289,7 +295,8 @@ def main():
                    "relaxations_per_query": round(relax / max(args.steps, 1)),
                    "relaxation_inflation": round(relax / max(edges, 1), 3),
                    "tuned": ({k: tuned[k] for k in ("layout", "loop", "dense_ratio", "alpha_x16", "delta", "small",
-                                                   "relax_filter", "async_blocks", "best_ms", "default_ms", "trials")}
+                                                   "relax_filter", "async_blocks", "local_hops", "best_ms",
+                                                   "default_ms", "trials")}
                              if tuned else None)},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -539,7 +546,8 @@ def measure_serving(args, torch, np, gr, gg, dev):
     edges_of = {}
 
     def serve(lo, hi, arrivals_ns, max_batch):
-        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_executors)
+        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_executors,
+                                  local_hops=args.serve_local_hops)
         try:
             gids = [gr.gr_server_add_graph(srv, G.handle) for G in Gs]
             tickets = []
@@ -585,7 +593,8 @@ def measure_serving(args, torch, np, gr, gg, dev):
 
     def serve_closed(lo, hi, clients, max_batch):
         """Closed loop: `clients` queries outstanding; each completion submits the next."""
-        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_executors)
+        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_executors,
+                                  local_hops=args.serve_local_hops)
         try:
             gids = [gr.gr_server_add_graph(srv, G.handle) for G in Gs]
             pending = {}

@@ -221,6 +221,12 @@ typedef struct {
     int32_t beta;         /* GR_DIR_AUTO, after a pull round: keep pulling while the frontier
                              holds at least n / beta vertices, else push (0 = 24).  Pull ->
                              push and push -> pull (alpha_x16) are Beamer et al.'s rules. */
+    int32_t local_hops;   /* small rounds (filter 3 or the graph's default): a block expands
+                             the vertices it improved again, with the distance that improved
+                             them, for up to local_hops - 1 further hops before handing the
+                             rest to the next round (1 = every improvement waits for the next
+                             round).  0 = the graph's default (4, unless gr_graph_tune chose
+                             another); at most 64. */
 } gr_sssp_opts;
 
 /* Relaxation filters of push (gr_sssp_opts.relax_filter).  Either way the
@@ -275,12 +281,13 @@ typedef struct {
     int32_t small;        /* 1: small rounds (filter 3) in the queued loop */
     int32_t relax_filter; /* GR_RELAX_DIST or GR_RELAX_BOUND */
     int32_t async_blocks; /* blocks of the asynchronous loop (0: the library's default) */
+    int32_t local_hops;   /* small rounds' local hops (see gr_sssp_opts) */
 } gr_tune_result;
 
 /*
  * Autotuner: times candidate schedules -- push layout, loop driver, filter
- * threshold, pull threshold, near-far split width, small rounds, relaxation filter,
- * the asynchronous loop's block count -- with a greedy search (one knob at a time, each
+ * threshold, pull threshold, near-far split width, small rounds and their local
+ * hops, relaxation filter, the asynchronous loop's block count -- with a greedy search (one knob at a time, each
  * candidate timed as the median of `reps` queries from srcs[0..nsrcs)), and
  * keeps the fastest as the graph's AUTO configuration.  Every candidate
  * computes the same distances.  When the environment variable GR_TUNE_CACHE
@@ -373,7 +380,10 @@ typedef struct {
     int32_t num_streams;    /* executors, each with its own stream, 1..8 (0 = 1) */
     int32_t max_wait_us;    /* unused: queries join a running executor at its next chunk of
                                rounds, so none waits for company (must be >= 0) */
-    int32_t reserved[5];
+    int32_t local_hops;     /* push blocks expand the vertices they improved on graphs of degree
+                               <= 8 for up to local_hops - 1 further hops within a round (as
+                               gr_sssp_opts.local_hops; 1..64, 0 = 4) */
+    int32_t reserved[4];
 } gr_server_config;
 
 typedef struct {

@@ -95,7 +95,7 @@ class gr_sssp_opts(ctypes.Structure):
     _fields_ = [("loop", ctypes.c_int32), ("direction", ctypes.c_int32), ("alpha_x16", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("layout", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32), ("delta", ctypes.c_uint32),
-                ("relax_filter", ctypes.c_int32), ("beta", ctypes.c_int32)]
+                ("relax_filter", ctypes.c_int32), ("beta", ctypes.c_int32), ("local_hops", ctypes.c_int32)]
 
 
 class gr_sssp_stats(ctypes.Structure):
@@ -115,7 +115,8 @@ class gr_tune_result(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("loop", ctypes.c_int32), ("dense_ratio", ctypes.c_int32),
                 ("alpha_x16", ctypes.c_int32), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
                 ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("delta", ctypes.c_uint32),
-                ("small", ctypes.c_int32), ("relax_filter", ctypes.c_int32), ("async_blocks", ctypes.c_int32)]
+                ("small", ctypes.c_int32), ("relax_filter", ctypes.c_int32), ("async_blocks", ctypes.c_int32),
+                ("local_hops", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -131,7 +132,7 @@ class gr_multi_stats(ctypes.Structure):
 
 class gr_server_config(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("num_streams", ctypes.c_int32), ("max_wait_us", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("local_hops", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class gr_query_result(ctypes.Structure):
@@ -312,12 +313,12 @@ def gr_sssp(g: int, src: int, dist_out, stream=None) -> None:
 
 def gr_sssp_ex(g: int, src: int, dist_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
                max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, barrier_timeout_us=0, delta=0,
-               relax_filter=0, beta=0) -> dict:
+               relax_filter=0, beta=0, local_hops=0) -> dict:
     """delta: near-far split width as weight-type bits (see delta_bits), 0 = graph default, GR_DELTA_OFF = off.
     relax_filter: GR_RELAX_DIST / GR_RELAX_BOUND, 0 = graph default."""
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
                      timing=timing, filter=filter, barrier_timeout_us=barrier_timeout_us, delta=delta,
-                     relax_filter=relax_filter, beta=beta)
+                     relax_filter=relax_filter, beta=beta, local_hops=local_hops)
     st = gr_sssp_stats()
     _check(lib().gr_sssp_ex(g, int(src), _out_ptr(dist_out, _graph_n(g), "dist_out"), _stream(stream),
                             ctypes.byref(o), ctypes.byref(st)))
@@ -336,10 +337,10 @@ def gr_bfs(g: int, src: int, depth_out, stream=None) -> None:
 
 def gr_bfs_ex(g: int, src: int, depth_out, stream=None, loop=GR_LOOP_AUTO, direction=GR_DIR_AUTO, alpha_x16=0,
               max_iters=0, layout=GR_LAYOUT_AUTO, timing=0, filter=0, relax_filter=0, barrier_timeout_us=0,
-              beta=0) -> dict:
+              beta=0, local_hops=0) -> dict:
     o = gr_sssp_opts(loop=loop, direction=direction, alpha_x16=alpha_x16, max_iters=max_iters, layout=layout,
                      timing=timing, filter=filter, relax_filter=relax_filter, barrier_timeout_us=barrier_timeout_us,
-                     beta=beta)
+                     beta=beta, local_hops=local_hops)
     st = gr_sssp_stats()
     _check(lib().gr_bfs_ex(g, int(src), _out_ptr(depth_out, _graph_n(g), "depth_out"), _stream(stream),
                            ctypes.byref(o), ctypes.byref(st)))
@@ -384,8 +385,9 @@ def gr_sssp_multi(graphs, srcs, dist_outs, stream=None) -> dict:
 
 # ---- serving ----------------------------------------------------------------
 
-def gr_server_create(hbm_budget_bytes: int, max_batch=0, num_streams=0, max_wait_us=0) -> int:
-    cfg = gr_server_config(max_batch=max_batch, num_streams=num_streams, max_wait_us=max_wait_us)
+def gr_server_create(hbm_budget_bytes: int, max_batch=0, num_streams=0, max_wait_us=0, local_hops=0) -> int:
+    cfg = gr_server_config(max_batch=max_batch, num_streams=num_streams, max_wait_us=max_wait_us,
+                           local_hops=local_hops)
     h = ctypes.c_void_p()
     _check(lib().gr_server_create(ctypes.byref(h), int(hbm_budget_bytes), ctypes.byref(cfg)))
     return h.value

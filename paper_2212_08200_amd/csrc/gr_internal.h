@@ -185,6 +185,7 @@ struct PersistentCfg {
     uint64_t spin_ticks;  // grid-barrier wait bound, in wall_clock64 ticks
     uint32_t delta;       // near-far split width (weight-type bits); 0 = off
     int32_t small;        // queued loop: rounds from a short candidate list may skip the filter
+    int32_t local_hops;   // small rounds: hops a block expands before appending (1 = none)
 };
 // Largest co-resident grid for the graph's layout (0 if none).
 int persistent_grid(const DevGraph &g, int num_cu);

@@ -951,6 +951,7 @@ struct PersistArgs {
     uint32_t *bound;             // relaxation filter (NULL: pre-read dist)
     int32_t cand_region;
     int32_t small;
+    int32_t local_hops;  // small rounds: hops expanded inside the block before appending (1 = none)
     int8_t *phase_log;  // timing: phase each launch ran (NULL: off)
     int64_t phase_log_cap;
 };
@@ -1155,7 +1156,71 @@ __device__ __forceinline__ int64_t cand_prefix(const unsigned long long *cnt, in
 // search).  Improved vertices are marked in the next flags and appended to
 // the next candidate list.  Used only on graphs whose largest degree is small
 // (see run_queued), so one block's share stays bounded.
+//
+// Local hops (local_hops > 1): the light vertices a block improves are not
+// all handed to the next round; up to kLocalCap of them are kept in LDS with
+// the candidate distance that improved them and expanded again by the same
+// block, for up to local_hops - 1 further hops, before the improvements of
+// the last hop (and any that do not fit) are appended.  Expanding v with its
+// own candidate c is a relaxation from a real path (dist[v] <= c once the
+// atomic has executed); if another relaxation lowered dist[v] further, that
+// one marked and appended (or expanded) v itself, so every decrease is still
+// followed by an expansion with that value or a smaller one.  The marks of
+// locally expanded vertices stay set, which only costs a repeated expansion
+// if a flag scan follows.  On bounded-degree graphs of long diameter this
+// takes several hops of the wavefront per launch instead of one.
 constexpr int kLight = 8;
+constexpr int kLocalCap = 1024;
+
+// Thread-mapped expansion of up to kLight arcs of v (first arc st, deg arcs)
+// with distance du: take[it] says arc it improved its destination vv[it] to
+// nd[it] (atomic min and mark issued).
+template <int WT, bool O32>
+__device__ __forceinline__ void expand_light(const PersistArgs &a, uint8_t *nf, bool on, int32_t st, int32_t deg,
+                                             uint32_t du, uint32_t (&vv)[kLight], uint32_t (&nd)[kLight],
+                                             bool (&take)[kLight]) {
+    uint2 arc[kLight];
+    uint32_t cur[kLight];
+#pragma unroll
+    for (int it = 0; it < kLight; ++it)
+        arc[it] = (on && it < deg) ? load_arc(elem<O32>(a.adj, (uint32_t)(st + it))) : make_uint2(0u, 0u);
+#pragma unroll
+    for (int it = 0; it < kLight; ++it) {
+        nd[it] = plus<WT>(du, arc[it].y);
+        cur[it] = (on && it < deg) ? *elem<O32>(a.bound ? a.bound : a.dist, arc[it].x) : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kLight; ++it) {
+        take[it] = on && it < deg && nd[it] < cur[it];
+        vv[it] = arc[it].x;
+        if (take[it]) {
+            if (a.bound)
+                relax_bound<O32>(a.dist, a.bound, nf, arc[it].x, nd[it]);
+            else
+                relax_commit<O32>(a.dist, nf, arc[it].x, nd[it]);
+        }
+    }
+}
+
+// Routes a thread's improvements: into the block's LDS list for the next
+// local hop while there is room (glob[it] = false), else to the global
+// candidate list (glob[it] = true).
+__device__ __forceinline__ void route_local(bool keep, const uint32_t (&vv)[kLight], const uint32_t (&nd)[kLight],
+                                            const bool (&take)[kLight], bool (&glob)[kLight], uint32_t *lv,
+                                            uint32_t *ld, int32_t *ln) {
+#pragma unroll
+    for (int it = 0; it < kLight; ++it) {
+        glob[it] = take[it];
+        if (take[it] && keep) {
+            const int32_t p = atomicAdd(ln, 1);
+            if (p < kLocalCap) {
+                lv[p] = vv[it];
+                ld[p] = nd[it];
+                glob[it] = false;
+            }
+        }
+    }
+}
 
 template <int WT, bool O32>
 __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, LoopState *ls, const int32_t *sPre) {
@@ -1164,6 +1229,9 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
     __shared__ int32_t hDeg[kBlk];
     __shared__ uint32_t hDu[kBlk];
     __shared__ int32_t hCount;
+    __shared__ uint32_t lV[2][kLocalCap], lD[2][kLocalCap];
+    __shared__ int32_t lN[2];
+    const int hops = a.local_hops > 1 ? a.local_hops : 1;
     const int64_t nin = sPre[kCandRegions];
     const int32_t R = a.cand_region;
     const int32_t *__restrict__ cin = a.cand[r & 1];
@@ -1172,12 +1240,20 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
     unsigned int *curw = reinterpret_cast<unsigned int *>(a.flags[r & 1]);
     uint8_t *nf = a.flags[(r + 1) & 1];
     int32_t st_win = 0, st_arcs = 0;
-    for (int64_t j0 = (int64_t)blockIdx.x * kBlk; j0 < nin; j0 += (int64_t)gridDim.x * kBlk) {
-        if (threadIdx.x == 0) hCount = 0;
+    // candidates are dealt evenly over the blocks (at most one pass of 256
+    // each when they fit), so that a short list still spreads over many
+    // blocks -- with local hops each block then grows a small local frontier
+    const int64_t per = (nin + gridDim.x - 1) / gridDim.x;
+    const int64_t cbeg = (int64_t)blockIdx.x * per, cend = min(nin, cbeg + per);
+    for (int64_t j0 = cbeg; j0 < cend; j0 += kBlk) {
+        if (threadIdx.x == 0) {
+            hCount = 0;
+            lN[0] = 0;
+        }
         __syncthreads();
         const int64_t j = j0 + threadIdx.x;
         int32_t v = -1;
-        if (j < nin) {
+        if (j < cend) {
             int q = 0;  // region of j: largest q with sPre[q] <= j
 #pragma unroll
             for (int b = kCandRegions / 2; b >= 1; b >>= 1) q = (sPre[q + b] <= j) ? q + b : q;
@@ -1205,29 +1281,11 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
             hDu[h] = du;
         }
         {  // thread-mapped expansion
-            uint2 arc[kLight];
-            uint32_t cur[kLight], nd[kLight], vv[kLight];
-            bool take[kLight];
-#pragma unroll
-            for (int it = 0; it < kLight; ++it)
-                arc[it] = (light && it < deg) ? load_arc(elem<O32>(a.adj, (uint32_t)(st + it))) : make_uint2(0u, 0u);
-#pragma unroll
-            for (int it = 0; it < kLight; ++it) {
-                nd[it] = plus<WT>(du, arc[it].y);
-                cur[it] = (light && it < deg) ? *elem<O32>(a.bound ? a.bound : a.dist, arc[it].x) : 0u;
-            }
-#pragma unroll
-            for (int it = 0; it < kLight; ++it) {
-                take[it] = light && it < deg && nd[it] < cur[it];
-                vv[it] = arc[it].x;
-                if (take[it]) {
-                    if (a.bound)
-                        relax_bound<O32>(a.dist, a.bound, nf, arc[it].x, nd[it]);
-                    else
-                        relax_commit<O32>(a.dist, nf, arc[it].x, nd[it]);
-                }
-            }
-            block_append<kLight>(co, vv, take);
+            uint32_t nd[kLight], vv[kLight];
+            bool take[kLight], glob[kLight];
+            expand_light<WT, O32>(a, nf, light, st, deg, du, vv, nd, take);
+            route_local(hops > 1, vv, nd, take, glob, lV[0], lD[0], &lN[0]);
+            block_append<kLight>(co, vv, glob);
         }
         __syncthreads();
         const int hc = hCount;
@@ -1279,6 +1337,40 @@ __device__ __forceinline__ void small_round(const PersistArgs &a, int64_t r, Loo
             }
         }
         __syncthreads();  // LDS reuse
+        // local hops over the light vertices this block improved
+        for (int h = 1; h < hops; ++h) {
+            const int sp = (h - 1) & 1, dp = h & 1;
+            const int32_t nloc = min(lN[sp], kLocalCap);
+            if (nloc == 0) break;  // uniform: LDS read after a barrier
+            if (threadIdx.x == 0) lN[dp] = 0;
+            __syncthreads();
+            const bool last = h == hops - 1;
+            for (int32_t i0 = 0; i0 < nloc; i0 += kBlk) {
+                const int32_t i = i0 + (int32_t)threadIdx.x;
+                int32_t lst = 0, ldeg = 0;
+                uint32_t lv = 0, lc = 0;
+                if (i < nloc) {
+                    lv = lV[sp][i];
+                    lc = lD[sp][i];
+                    lst = a.ro[lv];
+                    ldeg = a.ro[lv + 1] - lst;
+                }
+                const bool lon = i < nloc && ldeg > 0 && ldeg <= kLight;
+                st_win += lon ? 1 : 0;
+                st_arcs += lon ? ldeg : 0;
+                uint32_t nd[kLight], vv[kLight];
+                bool take[kLight], glob[kLight];
+                expand_light<WT, O32>(a, nf, lon, lst, ldeg, lc, vv, nd, take);
+                route_local(!last, vv, nd, take, glob, lV[dp], lD[dp], &lN[dp]);
+                // a heavier vertex is expanded by the next round: it is already
+                // marked (its improvement marked it); append it
+                uint32_t hv[1] = {lv};
+                bool hb[1] = {i < nloc && ldeg > kLight};
+                block_append<kLight>(co, vv, glob);
+                block_append<1>(co, hv, hb);
+            }
+            __syncthreads();
+        }
     }
     // statistics per region (so that blocks rarely share an address): the
     // round's expanded vertices, and running totals folded in at the end
@@ -2084,6 +2176,7 @@ static void persist_args(const DevGraph &g, uint32_t *dist, const Frontier &f, c
     a.bound = f.bound;
     a.cand_region = f.cand_cap / kCandRegions;
     a.small = cfg.small && f.cand[0] != nullptr ? 1 : 0;
+    a.local_hops = cfg.local_hops > 1 ? cfg.local_hops : 1;
     a.phase_log = nullptr;
     a.phase_log_cap = 0;
     a.far[0] = cfg.delta ? f.far[0] : nullptr;

@@ -35,7 +35,20 @@ struct MqSlot {
     int32_t wt;          // 0 uint32, 1 binary32, 2 unit steps (BFS)
     int32_t ngroups;     // groups of kGroupVerts vertices
     int32_t nflag;       // bytes per flag array (ngroups * kGroupVerts)
+    int32_t light;       // 1: every vertex has at most kMqLight out-arcs (local hops apply)
+    int32_t pad;
 };
+
+// Local hops (MqBufs::local_hops > 1): a push block keeps up to kMqLocalCap of
+// the vertices it improved in queries on light graphs, with the candidate
+// distance that improved them, and expands them again itself, one thread per
+// vertex, for up to local_hops - 1 further hops; only the improvements it does
+// not expand are marked for the next round.  Expanding v with its own
+// candidate c relaxes a real path (dist[v] <= c once the atomic executed); a
+// relaxation that lowered dist[v] further marked or expanded v itself, so every
+// decrease is still followed by an expansion with that value or a smaller one.
+constexpr int kMqLight = 8;
+constexpr int kMqLocalCap = 1024;
 
 // Control block of a session (device memory, cleared at session start).
 // Counters that many blocks update sit on 256-byte lines of their own.
@@ -64,6 +77,7 @@ struct MqBufs {
     int64_t qcap;       // entries per queue
     uint64_t *mask[2];  // batched same-graph queries: per-vertex active-source masks by round
                         // parity, cleared by the filter for the round's entries (NULL otherwise)
+    int32_t local_hops; // multi-query push: see kMqLocalCap (1 = none)
 };
 
 // Batched same-graph queries (up to kBatchLanes sources, one per wave lane):

@@ -82,6 +82,34 @@ __global__ __launch_bounds__(kBlk) void k_mq_update(MqBufs b, MqUpdate u) {
 }
 
 // ---------------------------------------------------------------------------
+// Local-hop list of a push block: (slot, vertex, candidate) entries, with a
+// direct-mapped table from (slot, vertex) to its entry, so that a vertex
+// improved again before its hop keeps one entry with the smaller candidate.
+// A table miss (another key in the way, or an entry still being written by
+// another wave) only adds a second entry, which is harmless: each entry is
+// one expansion.
+constexpr int kMqTag = 2048;
+
+__device__ __forceinline__ bool local_keep(uint32_t v, uint32_t nd, int sl, uint32_t *lv, uint32_t *ld, uint8_t *ls,
+                                           int32_t *ln, int32_t *tag) {
+    const uint32_t h = (v * 2654435761u + (uint32_t)sl * 40503u) >> 21;  // 11 bits
+    // the entry's fields are written before its tag is published (release),
+    // and read after the tag (acquire), so a hit sees a complete entry
+    const int32_t q = __hip_atomic_load(&tag[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (q >= 0 && q < kMqLocalCap && lv[q] == v && ls[q] == (uint8_t)sl) {
+        atomicMin(&ld[q], nd);
+        return true;
+    }
+    const int32_t p = atomicAdd(ln, 1);
+    if (p >= kMqLocalCap) return false;
+    lv[p] = v;
+    ld[p] = nd;
+    ls[p] = (uint8_t)sl;
+    __hip_atomic_store(&tag[h], p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // push of the round in st_round[0]
 
 __global__ __launch_bounds__(kBlk) void k_mq_push(MqBufs b) {
@@ -93,8 +121,15 @@ __global__ __launch_bounds__(kBlk) void k_mq_push(MqBufs b) {
     __shared__ uint8_t *tFl[kMqSlots];
     __shared__ uint8_t *tDirty[kMqSlots];
     __shared__ const uint2 *tAdj[kMqSlots];
+    __shared__ const int32_t *tRo[kMqSlots];
     __shared__ int32_t tWt[kMqSlots];
+    __shared__ int32_t tLight[kMqSlots];
+    __shared__ uint32_t lV[2][kMqLocalCap], lD[2][kMqLocalCap];
+    __shared__ uint8_t lS[2][kMqLocalCap];
+    __shared__ int32_t lN[2];
+    __shared__ int32_t lTag[kMqTag];
     MqCtl *ctl = b.ctl;
+    const int hops = b.local_hops > 1 ? b.local_hops : 1;
     const unsigned long long r = ctl->st_round[0];
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->st_round[1] = r;
     const unsigned long long c = ld_relaxed(&ctl->cnt[r % 3][0]);
@@ -121,8 +156,12 @@ __global__ __launch_bounds__(kBlk) void k_mq_push(MqBufs b) {
         tFl[threadIdx.x] = s.flags + (size_t)nxt * s.nflag;
         tDirty[threadIdx.x] = s.dirty + (size_t)nxt * s.ngroups;
         tAdj[threadIdx.x] = s.adj;
+        tRo[threadIdx.x] = s.ro;
         tWt[threadIdx.x] = s.wt;
+        tLight[threadIdx.x] = s.light;
     }
+    if (threadIdx.x == 0) lN[0] = 0;
+    for (int t = threadIdx.x; t < kMqTag; t += kBlk) lTag[t] = -1;
     __syncthreads();
     const uint2 *__restrict__ qse = b.qse[cur];
     const int32_t *__restrict__ qs = b.qs[cur];
@@ -181,14 +220,68 @@ __global__ __launch_bounds__(kBlk) void k_mq_push(MqBufs b) {
                     if (x0 + it * kBlk < wend && nd[it] < cv[it]) {
                         const uint32_t v = arc[it].x;
                         __hip_atomic_fetch_min(tDist[sl[it]] + v, nd[it], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        tFl[sl[it]][v] = 1;
-                        tDirty[sl[it]][v >> kGroupShift] = 1;
+                        const bool kept =
+                            hops > 1 && tLight[sl[it]] && local_keep(v, nd[it], sl[it], lV[0], lD[0], lS[0], &lN[0], lTag);
+                        if (!kept) {
+                            tFl[sl[it]][v] = 1;
+                            tDirty[sl[it]][v >> kGroupShift] = 1;
+                        }
                     }
                 }
             }
             i0 += cnt;
             e = wend;
             __syncthreads();  // window reuse
+        }
+    }
+    // local hops over the light-graph vertices this block improved
+    uint32_t st_v = 0, st_e = 0;
+    for (int h = 1; h < hops; ++h) {
+        const int sp = (h - 1) & 1, dp = h & 1;
+        __syncthreads();
+        const int32_t nloc = min(lN[sp], kMqLocalCap);
+        if (nloc == 0) break;  // uniform: LDS read after a barrier
+        __syncthreads();       // every thread has read lN[sp] before lN[dp] is reset
+        if (threadIdx.x == 0) lN[dp] = 0;
+        for (int t = threadIdx.x; t < kMqTag; t += kBlk) lTag[t] = -1;
+        __syncthreads();
+        const bool last = h == hops - 1;
+        for (int32_t i = threadIdx.x; i < nloc; i += kBlk) {
+            const uint32_t v = lV[sp][i], c = lD[sp][i];
+            const int sl = lS[sp][i];
+            const int32_t st = tRo[sl][v];
+            const int32_t deg = min(tRo[sl][v + 1] - st, kMqLight);
+            uint2 arc[kMqLight];
+            uint32_t cur[kMqLight], nd[kMqLight];
+#pragma unroll
+            for (int it = 0; it < kMqLight; ++it) arc[it] = it < deg ? load_arc(tAdj[sl] + st + it) : make_uint2(0u, 0u);
+#pragma unroll
+            for (int it = 0; it < kMqLight; ++it) {
+                nd[it] = plus_wt(tWt[sl], c, arc[it].y);
+                cur[it] = it < deg ? tDist[sl][arc[it].x] : 0u;
+            }
+            st_v += deg > 0 ? 1u : 0u;
+            st_e += (uint32_t)deg;
+#pragma unroll
+            for (int it = 0; it < kMqLight; ++it) {
+                if (it < deg && nd[it] < cur[it]) {
+                    const uint32_t w = arc[it].x;
+                    __hip_atomic_fetch_min(tDist[sl] + w, nd[it], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const bool kept = !last && local_keep(w, nd[it], sl, lV[dp], lD[dp], lS[dp], &lN[dp], lTag);
+                    if (!kept) {
+                        tFl[sl][w] = 1;
+                        tDirty[sl][w >> kGroupShift] = 1;
+                    }
+                }
+            }
+        }
+    }
+    if (hops > 1) {
+        int32_t x[2] = {(int32_t)st_v, (int32_t)st_e}, tot[2];
+        block_scan<2>(x, tot);
+        if (threadIdx.x == 0 && tot[0] > 0) {
+            atomicAdd(&ctl->frontier, (unsigned long long)tot[0]);
+            atomicAdd(&ctl->edges, (unsigned long long)tot[1]);
         }
     }
 }
@@ -436,11 +529,19 @@ __global__ __launch_bounds__(kBlk) void k_mq_batch_push(MqBufs b, uint32_t *__re
                 arc[it] = load_arc(adj + sRow[pos[it]] + (uint32_t)(x - sS[pos[it]]));
                 msk[it] = mcur[sU[pos[it]]];
             }
+            // Every lane loads: an inactive lane reads its entry of u's row (being
+            // read for du anyway) instead of v's, so no line of v's row that no
+            // active lane needs is fetched, and the loads stay unpredicated (a
+            // predicated load with a default value costs a wait for every load
+            // in flight on the path that writes the default).
 #pragma unroll
             for (int it = 0; it < kBatchArcs; ++it) {
                 const bool act = (msk[it] & lanebit) != 0ull;
-                du[it] = act ? D[(int64_t)sU[pos[it]] * kBatchLanes + lane] : 0u;
-                dv[it] = act ? D[(int64_t)arc[it].x * kBatchLanes + lane] : 0u;
+                const uint32_t u = sU[pos[it]];
+                uint32_t w = act ? arc[it].x : u;
+                asm volatile("" : "+v"(w));  // keeps the select: no load-or-copy branch
+                du[it] = D[(int64_t)u * kBatchLanes + lane];
+                dv[it] = D[(int64_t)w * kBatchLanes + lane];
             }
 #pragma unroll
             for (int it = 0; it < kBatchArcs; ++it) {

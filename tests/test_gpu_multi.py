@@ -152,3 +152,51 @@ def test_batch_statistics_and_rows():
         assert st["source_relaxations"] >= reached
     finally:
         G.close()
+
+
+@pytest.mark.parametrize("hops", [1, 3, 16])
+def test_server_local_hops_grids(hops):
+    """Served queries on bounded-degree graphs (grids, with and without
+    shortcuts, binary32) with local hops in the multi-query push: every
+    result equals the oracle's Dijkstra."""
+    graphs = [gg.grid(120, 91, whi=1000), gg.grid(200, 92, whi=255, shortcuts=40, sseed=93),
+              gg.grid(64, 94, wtype=gg.W_F32), gg.rmat(11, 16, gseed=95, pseed=96, wseed=97)]
+    Gs = [gr.Graph.from_csr(g) for g in graphs]
+    srv = gr.gr_server_create(4 << 30, max_batch=16, local_hops=hops)
+    try:
+        gids = [gr.gr_server_add_graph(srv, G.handle) for G in Gs]
+        qs, tickets = [], []
+        for i in range(40):
+            gi = i % len(graphs)
+            s = int(gg.pick_sources(graphs[gi], 300 + i, 1)[0])
+            out = torch.full((graphs[gi].n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+            qs.append((gi, s, out))
+        say("server local hops %d: 40 queries" % hops)
+        for gi, s, out in qs:
+            tickets.append(gr.gr_serve_submit(srv, gids[gi], s, out))
+        import time
+        done = {}
+        t0 = time.time()
+        while len(done) < len(tickets):
+            for t in tickets:
+                if t not in done:
+                    r = gr.gr_serve_poll(srv, t)
+                    if r is not None:
+                        done[t] = r
+            assert time.time() - t0 < 60, "served queries did not finish"
+            time.sleep(0.001)
+        for t, (gi, s, out) in zip(tickets, qs):
+            assert done[t]["status"] == gr.GR_OK
+            got = out.cpu().numpy().view(np.uint32)
+            want = oracle.dijkstra(graphs[gi], s)
+            if not np.array_equal(got, want):
+                v = int(np.flatnonzero(got != want)[0])
+                raise AssertionError("hops %d graph %d src %d: vertex %d got 0x%08x want 0x%08x" % (
+                    hops, gi, s, v, int(got[v]), int(want[v])))
+    finally:
+        gr.gr_server_destroy(srv)
+        for G in Gs:
+            G.close()
+    with pytest.raises(gr.GrError) as ei:
+        gr.gr_server_create(1 << 30, local_hops=65)
+    assert ei.value.status == gr.GR_ERR_INVALID_ARG

@@ -24,10 +24,10 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run(G, src, direction=0, loop=0, n=None, layout=0, filt=0, delta=0, relax=0):
+def run(G, src, direction=0, loop=0, n=None, layout=0, filt=0, delta=0, relax=0, hops=0):
     dist = torch.full((n or G.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
     st = gr.gr_sssp_ex(G.handle, int(src), dist, direction=direction, loop=loop, layout=layout, filter=filt,
-                       delta=delta, relax_filter=relax)
+                       delta=delta, relax_filter=relax, local_hops=hops)
     torch.cuda.synchronize()
     return dist.cpu().numpy().view(np.uint32), st
 
@@ -167,17 +167,23 @@ def test_persistent_loop_stats_match_host_loop():
     try:
         a = run(G, 0, DIRS["push"], loop=LOOPS["host"])[1]
         for lp, filt in (("persistent", 0), ("queued", 0), ("queued", 3), ("queued", 3)):
-            # queued twice with small rounds: the second starts from a predicted chunk
-            b = run(G, 0, DIRS["push"], loop=LOOPS[lp], filt=filt)[1]
+            # queued twice with small rounds: the second starts from a predicted chunk;
+            # one hop per round, so that every round is one level of the path
+            b = run(G, 0, DIRS["push"], loop=LOOPS[lp], filt=filt, hops=1)[1]
             assert a["iterations"] == b["iterations"] == L, lp
             assert a["edges_pushed"] == b["edges_pushed"] == L, lp
             assert a["frontier_sum"] == b["frontier_sum"] == L, lp
             assert a["push_frontier_sum"] == b["push_frontier_sum"] == L, lp
             if filt == 3:  # one improved vertex per round: rounds after the first skip the filter
                 assert b["small_rounds"] >= L - 2
+        # four local hops per small round: the path takes a quarter of the rounds,
+        # every arc still relaxed once
+        c = run(G, 0, DIRS["push"], loop=LOOPS["queued"], filt=3, hops=4)[1]
+        assert c["edges_pushed"] == L
+        assert L // 4 <= c["iterations"] <= L // 4 + 4, c["iterations"]
         dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
         for lp in ("host", "persistent", "queued"):
-            st = gr.gr_sssp_ex(G.handle, 0, dist, loop=LOOPS[lp], timing=1)
+            st = gr.gr_sssp_ex(G.handle, 0, dist, loop=LOOPS[lp], timing=1, local_hops=1)
             torch.cuda.synchronize()
             assert st["push_us"] > 0 and st["iterations"] == L, lp
     finally:
@@ -499,10 +505,50 @@ def test_small_rounds_candidate_overflow():
     G = gr.Graph.from_csr(g)
     try:
         want = oracle.dijkstra(g, 0)
-        got, st = run(G, 0, DIRS["push"], loop=LOOPS["queued"], filt=3)
+        got, st = run(G, 0, DIRS["push"], loop=LOOPS["queued"], filt=3, hops=1)
         assert_same(got, want, "tree overflow")
+        got4, _ = run(G, 0, DIRS["push"], loop=LOOPS["queued"], filt=3, hops=4)
+        assert_same(got4, want, "tree overflow, local hops")
         ref = run(G, 0, DIRS["push"], loop=LOOPS["host"])[1]
         assert st["iterations"] == ref["iterations"] and st["edges_pushed"] == ref["edges_pushed"]
         assert st["small_rounds"] >= 1
+    finally:
+        G.close()
+
+
+@pytest.mark.parametrize("hops", [2, 5, 16])
+def test_small_rounds_local_hops(hops):
+    """Small rounds with local hops (a block expands the vertices it improved
+    again, with the improving distance, before the next round): oracle
+    distances on bounded-degree graphs (grids with and without shortcuts,
+    directed graphs with zero weights, binary32), fewer rounds than without."""
+    cases = [("grid96", gg.grid(96, 51, whi=1000)),
+             ("road256", gg.grid(256, 52, whi=1000, shortcuts=65, sseed=53)),
+             ("uniform", gg.uniform(5000, 15000, 54, 55, wlo=0, whi=4)),
+             ("grid80 f32", gg.grid(80, 56, wtype=gg.W_F32))]
+    for tag, g in cases:
+        G = gr.Graph.from_csr(g)
+        try:
+            for s in [0] + [int(x) for x in gg.pick_sources(g, 57, 2)]:
+                want = oracle.dijkstra(g, s)
+                say("local hops %d: %s src=%d" % (hops, tag, s))
+                got1, st1 = run(G, s, DIRS["push"], loop=LOOPS["queued"], filt=3, hops=1)
+                dist = torch.full((g.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+                st = gr.gr_sssp_ex(G.handle, s, dist, loop=LOOPS["queued"], direction=DIRS["push"], filter=3,
+                                   local_hops=hops)
+                torch.cuda.synchronize()
+                assert_same(dist.cpu().numpy().view(np.uint32), want, "%s src %d hops %d" % (tag, s, hops))
+                assert_same(got1, want, "%s src %d hops 1" % (tag, s))
+                if tag.startswith("grid") and s == 0:
+                    assert st["iterations"] < st1["iterations"], (st["iterations"], st1["iterations"])
+        finally:
+            G.close()
+    g = gg.grid(8, 3)
+    G = gr.Graph.from_csr(g)
+    try:
+        dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_ex(G.handle, 0, dist, local_hops=65)
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
     finally:
         G.close()
