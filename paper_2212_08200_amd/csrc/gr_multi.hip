@@ -510,55 +510,62 @@ __global__ __launch_bounds__(kBlk) void k_mq_batch_push(MqBufs b, uint32_t *__re
         const int32_t share = (span + (kBlk / 64) - 1) / (kBlk / 64);
         const int32_t r0 = e + wid * share;
         const int32_t r1 = min(wend, r0 + share);
-        for (int32_t x0 = r0; x0 < r1; x0 += kBatchArcs) {
-            int32_t pos[kBatchArcs];
-            uint2 arc[kBatchArcs];
-            uint64_t msk[kBatchArcs];
-            uint32_t du[kBatchArcs], dv[kBatchArcs];
+        // 64 ranks at a time: lane l finds the entry of rank x0 + l and loads
+        // that arc and its tail's mask (one search, one arc load and one mask
+        // load per 64 arcs); the wave then walks the 64 arcs, taking each
+        // one's fields from the lane that staged it (register broadcasts, no
+        // per-arc search or uniform loads).
+        for (int32_t x0 = r0; x0 < r1; x0 += 64) {
+            const int32_t cntj = min(64, r1 - x0);
+            const int32_t xl = min(x0 + lane, r1 - 1);
+            int32_t p = 0;
 #pragma unroll
-            for (int it = 0; it < kBatchArcs; ++it) {
-                const int32_t x = min(x0 + it, r1 - 1);  // clamped ranks repeat the last arc
-                int32_t p = 0;
+            for (int bb = kWin / 2; bb >= 1; bb >>= 1) p = (sS[p + bb] <= xl) ? p + bb : p;
+            const uint32_t ul = sU[p];
+            const uint2 al = load_arc(adj + sRow[p] + (uint32_t)(xl - sS[p]));
+            const uint64_t ml = mcur[ul];
+            const uint32_t mlo = (uint32_t)ml, mhi = (uint32_t)(ml >> 32);
+            for (int32_t j = 0; j < cntj; j += kBatchArcs) {
+                uint32_t uu[kBatchArcs], vv[kBatchArcs], ww[kBatchArcs], du[kBatchArcs], dv[kBatchArcs];
+                bool act[kBatchArcs];
 #pragma unroll
-                for (int bb = kWin / 2; bb >= 1; bb >>= 1) p = (sS[p + bb] <= x) ? p + bb : p;
-                pos[it] = p;
-            }
+                for (int it = 0; it < kBatchArcs; ++it) {
+                    const int jj = min(j + it, cntj - 1);  // clamped: repeats the last arc, masked below
+                    uu[it] = (uint32_t)__builtin_amdgcn_readlane((int)ul, jj);
+                    vv[it] = (uint32_t)__builtin_amdgcn_readlane((int)al.x, jj);
+                    ww[it] = (uint32_t)__builtin_amdgcn_readlane((int)al.y, jj);
+                    const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, jj) << 32) |
+                                       (uint32_t)__builtin_amdgcn_readlane((int)mlo, jj);
+                    act[it] = (j + it < cntj) && ((m >> lane) & 1ull) != 0ull;
+                }
+                // Every lane loads: an inactive lane reads its entry of u's row
+                // (read for du anyway) instead of v's, so no line of v's row that
+                // no active lane needs is fetched, and the loads stay
+                // unpredicated (a predicated load with a default value costs a
+                // wait for every load in flight on the path that writes it).
 #pragma unroll
-            for (int it = 0; it < kBatchArcs; ++it) {
-                const int32_t x = min(x0 + it, r1 - 1);
-                arc[it] = load_arc(adj + sRow[pos[it]] + (uint32_t)(x - sS[pos[it]]));
-                msk[it] = mcur[sU[pos[it]]];
-            }
-            // Every lane loads: an inactive lane reads its entry of u's row (being
-            // read for du anyway) instead of v's, so no line of v's row that no
-            // active lane needs is fetched, and the loads stay unpredicated (a
-            // predicated load with a default value costs a wait for every load
-            // in flight on the path that writes the default).
+                for (int it = 0; it < kBatchArcs; ++it) {
+                    uint32_t w = act[it] ? vv[it] : uu[it];
+                    asm volatile("" : "+v"(w));  // keeps the select: no load-or-copy branch
+                    du[it] = D[(int64_t)uu[it] * kBatchLanes + lane];
+                    dv[it] = D[(int64_t)w * kBatchLanes + lane];
+                }
 #pragma unroll
-            for (int it = 0; it < kBatchArcs; ++it) {
-                const bool act = (msk[it] & lanebit) != 0ull;
-                const uint32_t u = sU[pos[it]];
-                uint32_t w = act ? arc[it].x : u;
-                asm volatile("" : "+v"(w));  // keeps the select: no load-or-copy branch
-                du[it] = D[(int64_t)u * kBatchLanes + lane];
-                dv[it] = D[(int64_t)w * kBatchLanes + lane];
-            }
-#pragma unroll
-            for (int it = 0; it < kBatchArcs; ++it) {
-                const bool act = (x0 + it < r1) && ((msk[it] & lanebit) != 0ull);
-                pairs += act ? 1u : 0u;
-                const uint32_t nd = plus<WT>(du[it], arc[it].y);
-                const bool better = act && nd < dv[it];
-                if (better)
-                    __hip_atomic_fetch_min(D + (int64_t)arc[it].x * kBatchLanes + lane, nd, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t won = __ballot(better);
-                if (won && lane == 0) {
-                    const uint32_t v = arc[it].x;
-                    __hip_atomic_fetch_or(reinterpret_cast<unsigned long long *>(mnext + v), won, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-                    nfl[v] = 1;
-                    ndirty[v >> kGroupShift] = 1;
+                for (int it = 0; it < kBatchArcs; ++it) {
+                    pairs += act[it] ? 1u : 0u;
+                    const uint32_t nd = plus<WT>(du[it], ww[it]);
+                    const bool better = act[it] && nd < dv[it];
+                    if (better)
+                        __hip_atomic_fetch_min(D + (int64_t)vv[it] * kBatchLanes + lane, nd, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t won = __ballot(better);
+                    if (won && lane == 0) {
+                        const uint32_t v = vv[it];
+                        __hip_atomic_fetch_or(reinterpret_cast<unsigned long long *>(mnext + v), won,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        nfl[v] = 1;
+                        ndirty[v >> kGroupShift] = 1;
+                    }
                 }
             }
         }
