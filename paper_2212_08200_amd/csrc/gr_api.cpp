@@ -585,10 +585,10 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
     if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
     const DevGraph &dg = *rc.dg;
     void *ws = nullptr;
-    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
+    const WsParts parts{rc.delta != 0, rc.bound};
+    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg, parts), st));
     Frontier f;
-    frontier_carve(f, ws, dg);
-    if (!rc.bound) f.bound = nullptr;
+    frontier_carve(f, ws, dg, parts);
     gr_sssp_stats local{};
     local.loop = GR_LOOP_HOST;
     local.layout = rc.layout;
@@ -698,10 +698,10 @@ static gr_status run_persistent(const gr_graph *g, int32_t src, uint32_t *dist, 
     unsigned long long *hp = pinned_slot();
     if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
     void *ws = nullptr;
-    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
+    const WsParts parts{rc.delta != 0, rc.bound};
+    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg, parts), st));
     Frontier f;
-    frontier_carve(f, ws, dg);
-    if (!rc.bound) f.bound = nullptr;
+    frontier_carve(f, ws, dg, parts);
     hipEvent_t ev[2] = {nullptr, nullptr};
     const bool timed = rc.timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
     hipError_t e = launch_init(dg, dist, src, f, rc.delta ? next_threshold(0u, rc.delta, dg.wt) : kInfU32,
@@ -780,10 +780,10 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
     cfg.small = rc.small && rc.delta == 0 && g->max_degree <= kSmallMaxDegree &&
                 (rc.direction == GR_DIR_PUSH || (rc.direction == GR_DIR_AUTO && rc.alpha_x16 == 0));
     void *ws = nullptr;
-    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
+    const WsParts parts{rc.delta != 0, rc.bound};
+    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg, parts), st));
     Frontier f;
-    frontier_carve(f, ws, dg);
-    if (!rc.bound) f.bound = nullptr;
+    frontier_carve(f, ws, dg, parts);
     int8_t *plog = nullptr;
     hipEvent_t evc[2] = {nullptr, nullptr};
     hipError_t e = hipSuccess;
@@ -899,7 +899,9 @@ static gr_status run_async(const gr_graph *g, int32_t src, uint32_t *dist, hipSt
     unsigned long long *hp = pinned_slot();
     if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
     void *ws = nullptr, *aws = nullptr;
-    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg), st));
+    // the asynchronous loop uses the flag arrays only (in-queue bytes, spill marks)
+    const WsParts parts{false, false};
+    HIP_TRY(hipMallocAsync(&ws, frontier_bytes(dg, parts), st));
     // GR_ASYNC_LIST_CAP (entries, >= 1) lowers the list's capacity: a test
     // hook for the overflow path
     int64_t cap = async_capacity(dg.n);
@@ -913,7 +915,7 @@ static gr_status run_async(const gr_graph *g, int32_t src, uint32_t *dist, hipSt
         return hip_fail(e, "hipMallocAsync");
     }
     Frontier f;
-    frontier_carve(f, ws, dg);
+    frontier_carve(f, ws, dg, parts);
     unsigned long long *ctl = async_ctl(cap, aws);
     const int blocks = g->auto_async_blocks > 0 ? g->auto_async_blocks : async_blocks(dg, di.num_cu);
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1026,8 +1028,7 @@ static gr_status run_queued_fixed(const gr_graph *g, int32_t src, uint32_t *dist
     cfg.small = rc.small && g->max_degree <= kSmallMaxDegree &&
                 (rc.direction == GR_DIR_PUSH || (rc.direction == GR_DIR_AUTO && rc.alpha_x16 == 0));
     Frontier f;
-    frontier_carve(f, ws, dg);
-    if (!rc.bound) f.bound = nullptr;
+    frontier_carve(f, ws, dg, WsParts{false, rc.bound});
     // k_init clears every flag, counter and control word the loop reads
     hipError_t e = launch_init(dg, dist, src, f, kInfU32, false, st);
     int64_t issued = 0;
@@ -1066,7 +1067,7 @@ extern "C" gr_status gr_sssp_noalloc(const gr_graph *g, int32_t src, void *dist_
     rc.dg = &g->plain;
     rc.layout = GR_LAYOUT_PLAIN;
     rc.delta = 0;
-    const size_t need = frontier_bytes(g->plain);
+    const size_t need = frontier_bytes(g->plain, WsParts{false, rc.bound});
     if (need > kNoAllocScratchBytes)
         return fail(GR_ERR_NO_CAPACITY, "the query needs %zu bytes of workspace, the fixed scratch holds %zu", need,
                     kNoAllocScratchBytes);

@@ -131,8 +131,15 @@ constexpr int kStatEdges = 4 * kCandRegions;
 constexpr int kStatWords = 5 * kCandRegions;
 static_assert(kCtlSlots * kSlotWords <= kLoopStateWord, "counter slots fit below the loop state");
 
-size_t frontier_bytes(const DevGraph &g);
-void frontier_carve(Frontier &f, void *base, const DevGraph &g);
+// Optional parts of a query's workspace: the held-back flags of the near-far
+// split and the bound array of the relaxation filter (absent parts take no
+// space and their pointers are NULL).
+struct WsParts {
+    bool far;
+    bool bound;
+};
+size_t frontier_bytes(const DevGraph &g, WsParts w);
+void frontier_carve(Frontier &f, void *base, const DevGraph &g, WsParts w);
 
 // Totals of one frontier as read back from the counters.
 struct FrontierCounts {

@@ -830,24 +830,33 @@ __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t v
     const int64_t lo = a.off[k] + j * kDenseChunk;
     const int64_t hi = min((int64_t)a.off[k + 1], lo + kDenseChunk);
     if (lo >= hi) return;  // uniform per block
-    // thread t takes members lo + t*kDenseItems ... (consecutive, vertex order)
-    const int64_t m0 = lo + (int64_t)threadIdx.x * kDenseItems;
+    // item it of thread t is member lo + it*kBlk + t: consecutive lanes read
+    // consecutive members (and nearby flag bytes), one cache line per 32 lanes
     int32_t u[kDenseItems];
     uint2 sd[kDenseItems];
     bool on[kDenseItems];
 #pragma unroll
     for (int it = 0; it < kDenseItems; ++it) {
-        const int64_t m = min(m0 + it, hi - 1);
+        const int64_t m = min(lo + (int64_t)it * kBlk + threadIdx.x, hi - 1);
         u[it] = a.mem_u[m];
     }
     int32_t x[2] = {0, 0}, tot[2];
     uint32_t du[kDenseItems];
+    // the flag bytes of all items are loaded before any is tested (a test
+    // between the loads made each load wait for the previous one)
+    uint32_t fl[kDenseItems];
 #pragma unroll
-    for (int it = 0; it < kDenseItems; ++it)
-        on[it] = (m0 + it < hi) && (nflags[u[it]] != 0 || (far_cur && far_cur[u[it]] != 0));
+    for (int it = 0; it < kDenseItems; ++it) fl[it] = nflags[u[it]];
+    if (far_cur) {
+#pragma unroll
+        for (int it = 0; it < kDenseItems; ++it) fl[it] |= far_cur[u[it]];
+    }
+#pragma unroll
+    for (int it = 0; it < kDenseItems; ++it) on[it] = (lo + (int64_t)it * kBlk + threadIdx.x < hi) && fl[it] != 0u;
     // arc ranges only of the members in the frontier (R-MAT 20: 2.25 -> 2.17 ms)
 #pragma unroll
-    for (int it = 0; it < kDenseItems; ++it) sd[it] = on[it] ? a.mem_sd[min(m0 + it, hi - 1)] : make_uint2(0u, 0u);
+    for (int it = 0; it < kDenseItems; ++it)
+        sd[it] = on[it] ? a.mem_sd[min(lo + (int64_t)it * kBlk + threadIdx.x, hi - 1)] : make_uint2(0u, 0u);
 #pragma unroll
     for (int it = 0; it < kDenseItems; ++it) {
         if (far_cur) {
@@ -2245,15 +2254,15 @@ static inline int32_t cand_capacity(int32_t n) {
     return kCandRegions * std::max(1, std::min(n, 1 << 18) / kCandRegions);
 }
 
-size_t frontier_bytes(const DevGraph &g) {
+size_t frontier_bytes(const DevGraph &g, WsParts w) {
     const int64_t ng = groups_for(g.n);
     size_t b = 0;
-    b += 4 * align256((size_t)ng * kGroupVerts);  // flags, held-back flags
-    b += align256((size_t)ng * kGroupVerts / 8);   // frontier bitmap
+    b += (w.far ? 4 : 2) * align256((size_t)ng * kGroupVerts);  // flags, held-back flags
+    b += align256((size_t)ng * kGroupVerts / 8);                 // frontier bitmap
     b += 2 * align256(sizeof(int32_t) * (size_t)cand_capacity(g.n));
     b += align256(sizeof(unsigned long long) * 3 * kCandRegions);
     b += align256(sizeof(unsigned long long) * kStatWords);
-    b += align256(sizeof(uint32_t) * (size_t)std::max(g.n, 1));  // bound
+    if (w.bound) b += align256(sizeof(uint32_t) * (size_t)std::max(g.n, 1));
     for (int k = 0; k < g.np; ++k) {
         const size_t c = (size_t)(g.cap[k] > 0 ? g.cap[k] : 1);
         b += align256(c * 8) + align256(c * 4);
@@ -2262,7 +2271,7 @@ size_t frontier_bytes(const DevGraph &g) {
     return b;
 }
 
-void frontier_carve(Frontier &f, void *base, const DevGraph &g) {
+void frontier_carve(Frontier &f, void *base, const DevGraph &g, WsParts w) {
     const int64_t ng = groups_for(g.n);
     f.ngroups = (int32_t)ng;
     f.nflag = ng * kGroupVerts;
@@ -2273,8 +2282,8 @@ void frontier_carve(Frontier &f, void *base, const DevGraph &g) {
         p += align256((size_t)f.nflag);
     }
     for (int i = 0; i < 2; ++i) {
-        f.far[i] = reinterpret_cast<uint8_t *>(p);
-        p += align256((size_t)f.nflag);
+        f.far[i] = w.far ? reinterpret_cast<uint8_t *>(p) : nullptr;
+        if (w.far) p += align256((size_t)f.nflag);
     }
     f.bits = reinterpret_cast<uint32_t *>(p);
     p += align256((size_t)f.nflag / 8);
@@ -2287,8 +2296,8 @@ void frontier_carve(Frontier &f, void *base, const DevGraph &g) {
     p += align256(sizeof(unsigned long long) * 3 * kCandRegions);
     f.rstat = reinterpret_cast<unsigned long long *>(p);
     p += align256(sizeof(unsigned long long) * kStatWords);
-    f.bound = reinterpret_cast<uint32_t *>(p);
-    p += align256(sizeof(uint32_t) * (size_t)std::max(g.n, 1));
+    f.bound = w.bound ? reinterpret_cast<uint32_t *>(p) : nullptr;
+    if (w.bound) p += align256(sizeof(uint32_t) * (size_t)std::max(g.n, 1));
     for (int k = 0; k < kMaxParts; ++k) {
         f.qse[k] = nullptr;
         f.qs[k] = nullptr;

@@ -55,7 +55,7 @@ def test_noalloc_matches_gr_sssp_twice_then_smaller():
 
 
 def test_noalloc_refuses_a_graph_too_large_for_the_array():
-    # a directed path of 8M vertices: its workspace (about 20 bytes per vertex) exceeds 96 MiB
+    # a directed path of 8M vertices: its workspace (about 15 bytes per vertex) exceeds 96 MiB
     n = 8 << 20
     ro = np.arange(n + 1, dtype=np.int32)
     ro[-1] = n - 1
