@@ -80,28 +80,32 @@ __device__ __forceinline__ unsigned long long ld_acq(unsigned long long *p) {
 template <int WT, bool O32, int N>
 __device__ __forceinline__ void relax_async(const AsyncArgs &a, const uint2 (&arc)[N], const uint32_t (&du)[N],
                                             const bool (&valid)[N], bool (&take)[N]) {
+    // No default values on the loads and atomics below: a guarded load or
+    // atomic whose result gets a default on the other path made each item
+    // wait for the one before.  Invalid items read vertex 0 (arc (0, 0) or a
+    // valid clamped arc), and old / was are read only where they were set.
     uint32_t nd[N], cur[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         nd[i] = plus<WT>(du[i], arc[i].y);
-        cur[i] = valid[i] ? *elem<O32>(a.dist, arc[i].x) : 0u;
+        cur[i] = *elem<O32>(a.dist, arc[i].x);
     }
     uint32_t old[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         take[i] = valid[i] && nd[i] < cur[i];
-        old[i] = take[i] ? __hip_atomic_fetch_min(elem<O32>(a.dist, arc[i].x), nd[i], __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT)
-                         : 0u;
+        if (take[i])
+            old[i] = __hip_atomic_fetch_min(elem<O32>(a.dist, arc[i].x), nd[i], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
     }
     uint32_t was[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         take[i] = take[i] && nd[i] < old[i];
         const uint32_t v = arc[i].x;
-        was[i] = take[i] ? __hip_atomic_fetch_or(elem<O32>(a.inq, v >> 2), 1u << ((v & 3u) * 8u), __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT)
-                         : 0u;
+        if (take[i])
+            was[i] = __hip_atomic_fetch_or(elem<O32>(a.inq, v >> 2), 1u << ((v & 3u) * 8u), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) take[i] = take[i] && ((was[i] >> ((arc[i].x & 3u) * 8u)) & 0xFFu) == 0u;

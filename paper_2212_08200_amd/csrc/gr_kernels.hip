@@ -1196,7 +1196,9 @@ __device__ __forceinline__ void expand_light(const PersistArgs &a, uint8_t *nf, 
 #pragma unroll
     for (int it = 0; it < kLight; ++it) {
         nd[it] = plus<WT>(du, arc[it].y);
-        cur[it] = (on && it < deg) ? *elem<O32>(a.bound ? a.bound : a.dist, arc[it].x) : 0u;
+        // unguarded: an item past the degree reads vertex 0 (its arc is (0, 0));
+        // a guarded load with a default value made each item wait for the last
+        cur[it] = *elem<O32>(a.bound ? a.bound : a.dist, arc[it].x);
     }
 #pragma unroll
     for (int it = 0; it < kLight; ++it) {

@@ -19,6 +19,25 @@
 
 namespace gr {
 
+// Global-memory pointers.  Pointers read from LDS or from the control block
+// are otherwise generic, and generic (flat) loads and atomics share the wait
+// counter of LDS reads: every LDS read of a push loop would then wait for all
+// memory operations in flight.
+template <class T>
+using gptr = T __attribute__((address_space(1))) *;
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(T *p) {
+    return (gptr<T>)p;
+}
+
+__device__ __forceinline__ uint2 load_arc(gptr<const uint2> p) {
+    const unsigned long long x = __builtin_nontemporal_load(reinterpret_cast<gptr<const unsigned long long>>(p));
+    return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+}
+
 constexpr int kMqItems = 8;                    // arcs in flight per lane
 constexpr int32_t kMqChunk = kBlk * kMqItems;  // smallest arc range of a block
 
@@ -114,14 +133,14 @@ __device__ __forceinline__ bool local_keep(uint32_t v, uint32_t nd, int sl, uint
 
 __global__ __launch_bounds__(kBlk) void k_mq_push(MqBufs b) {
     __shared__ int32_t sS[kWin + 1];
-    __shared__ const uint2 *sArc[kWin];
+    __shared__ gptr<const uint2> sArc[kWin];
     __shared__ uint32_t sDu[kWin];
     __shared__ uint8_t sSl[kWin];
-    __shared__ uint32_t *tDist[kMqSlots];
-    __shared__ uint8_t *tFl[kMqSlots];
-    __shared__ uint8_t *tDirty[kMqSlots];
-    __shared__ const uint2 *tAdj[kMqSlots];
-    __shared__ const int32_t *tRo[kMqSlots];
+    __shared__ gptr<uint32_t> tDist[kMqSlots];
+    __shared__ gptr<uint8_t> tFl[kMqSlots];
+    __shared__ gptr<uint8_t> tDirty[kMqSlots];
+    __shared__ gptr<const uint2> tAdj[kMqSlots];
+    __shared__ gptr<const int32_t> tRo[kMqSlots];
     __shared__ int32_t tWt[kMqSlots];
     __shared__ int32_t tLight[kMqSlots];
     __shared__ uint32_t lV[2][kMqLocalCap], lD[2][kMqLocalCap];
@@ -152,11 +171,11 @@ __global__ __launch_bounds__(kBlk) void k_mq_push(MqBufs b) {
     }
     if (threadIdx.x < kMqSlots) {
         const MqSlot &s = ctl->slot[threadIdx.x];
-        tDist[threadIdx.x] = s.dist;
-        tFl[threadIdx.x] = s.flags + (size_t)nxt * s.nflag;
-        tDirty[threadIdx.x] = s.dirty + (size_t)nxt * s.ngroups;
-        tAdj[threadIdx.x] = s.adj;
-        tRo[threadIdx.x] = s.ro;
+        tDist[threadIdx.x] = to_global(s.dist);
+        tFl[threadIdx.x] = to_global(s.flags + (size_t)nxt * s.nflag);
+        tDirty[threadIdx.x] = to_global(s.dirty + (size_t)nxt * s.ngroups);
+        tAdj[threadIdx.x] = to_global(s.adj);
+        tRo[threadIdx.x] = to_global(s.ro);
         tWt[threadIdx.x] = s.wt;
         tLight[threadIdx.x] = s.light;
     }
@@ -258,7 +277,10 @@ __global__ __launch_bounds__(kBlk) void k_mq_push(MqBufs b) {
 #pragma unroll
             for (int it = 0; it < kMqLight; ++it) {
                 nd[it] = plus_wt(tWt[sl], c, arc[it].y);
-                cur[it] = it < deg ? tDist[sl][arc[it].x] : 0u;
+                // unguarded: an item past the degree reads vertex 0 (its arc is
+                // (0, 0)); a guarded load with a default value made each item
+                // wait for the previous one
+                cur[it] = tDist[sl][arc[it].x];
             }
             st_v += deg > 0 ? 1u : 0u;
             st_e += (uint32_t)deg;
@@ -337,7 +359,7 @@ __global__ __launch_bounds__(kBlk) void k_mq_filter(MqBufs b) {
             for (int bb = kMqSlots / 2; bb >= 1; bb >>= 1) j = (j + bb < nlive && sGpre[j + bb] <= x) ? j + bb : j;
             const MqSlot &s = ctl->slot[sLive[j]];
             const int32_t g = (int32_t)(x - sGpre[j]);
-            if (s.dirty[(size_t)nxt * s.ngroups + g]) sList[atomicAdd(&sCount, 1)] = (int32_t)x;
+            if (to_global(s.dirty)[(size_t)nxt * s.ngroups + g]) sList[atomicAdd(&sCount, 1)] = (int32_t)x;
         }
         __syncthreads();
         const int nd = sCount;
@@ -349,26 +371,27 @@ __global__ __launch_bounds__(kBlk) void k_mq_filter(MqBufs b) {
             const int sl = sLive[j];
             const MqSlot &s = ctl->slot[sl];
             const int64_t g = xg - sGpre[j];
-            uint8_t *fl = s.flags + (size_t)nxt * s.nflag;
+            gptr<uint8_t> fl = to_global(s.flags + (size_t)nxt * s.nflag);
+            gptr<const int32_t> ro = to_global(s.ro);
             const int64_t base = g * kGroupVerts + threadIdx.x * 16;
-            const uint4 w = reinterpret_cast<const uint4 *>(fl)[base >> 4];
+            const u32x4 w = reinterpret_cast<gptr<const u32x4>>(fl)[base >> 4];
             uint32_t m = 0;
 #pragma unroll
             for (int bt = 0; bt < 16; ++bt) {
                 const uint32_t word = bt < 4 ? w.x : bt < 8 ? w.y : bt < 12 ? w.z : w.w;
                 m |= (((word >> ((bt & 3) * 8)) & 0xFFu) != 0u ? 1u : 0u) << bt;
             }
-            if (m) reinterpret_cast<uint4 *>(fl)[base >> 4] = make_uint4(0u, 0u, 0u, 0u);
+            if (m) reinterpret_cast<gptr<u32x4>>(fl)[base >> 4] = u32x4{0u, 0u, 0u, 0u};
             int32_t xx[2] = {0, 0}, tot[2];
             for (uint32_t mm = m; mm; mm &= mm - 1) {
                 const int64_t u = base + __builtin_ctz(mm);
-                const int32_t d = s.ro[u + 1] - s.ro[u];
+                const int32_t d = ro[u + 1] - ro[u];
                 xx[0] += d > 0 ? 1 : 0;
                 xx[1] += d;
             }
             block_scan<2>(xx, tot);
             if (threadIdx.x == 0) {
-                s.dirty[(size_t)nxt * s.ngroups + g] = 0;
+                to_global(s.dirty)[(size_t)nxt * s.ngroups + g] = 0;
                 sBase = tot[0] ? atomicAdd(ncnt, (unsigned long long)tot[0] | ((unsigned long long)tot[1] << 32)) : 0ull;
                 if (tot[0]) atomicAdd(&ctl->slot_cnt[(r + 1) % 3][sl], (unsigned long long)tot[0]);
             }
@@ -377,8 +400,8 @@ __global__ __launch_bounds__(kBlk) void k_mq_filter(MqBufs b) {
             int32_t spos = (int32_t)(sBase >> 32) + xx[1];
             for (uint32_t mm = m; mm; mm &= mm - 1) {
                 const int64_t u = base + __builtin_ctz(mm);
-                const int32_t f = s.ro[u];
-                const int32_t d = s.ro[u + 1] - f;
+                const int32_t f = ro[u];
+                const int32_t d = ro[u + 1] - f;
                 if (d > 0) {
                     b.qse[nxt][pos] = make_uint2((uint32_t)f, (uint32_t)u);
                     b.qs[nxt][pos] = spos;
