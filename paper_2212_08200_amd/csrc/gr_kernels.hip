@@ -610,18 +610,27 @@ __device__ __forceinline__ uint4 bytes_of_bits(uint32_t m) {
 
 // Near-far split of 16 consecutive vertices from base: of the candidates
 // (bits of cand), those at or above the threshold are held back (returned).
+// The 16 distances are loaded before any is tested, each non-candidate slot
+// reading the first candidate's (a vertex below n): loads guarded one by one
+// ran one round trip at a time.
 __device__ __forceinline__ uint32_t held_back(const uint32_t *__restrict__ dist, int64_t base, uint32_t cand,
                                               uint32_t T, uint32_t *cnt, uint32_t *inv) {
+    if (cand == 0u) return 0u;
+    const uint32_t b0 = (uint32_t)__builtin_ctz(cand);
+    uint32_t d[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        uint32_t o = ((cand >> b) & 1u) ? (uint32_t)b : b0;
+        asm volatile("" : "+v"(o));  // keeps the select: no load-or-copy branch
+        d[b] = dist[base + o];
+    }
     uint32_t held = 0;
 #pragma unroll
     for (int b = 0; b < 16; ++b) {
-        if ((cand >> b) & 1u) {
-            const uint32_t du = dist[base + b];
-            if (du >= T) {
-                held |= 1u << b;
-                *cnt += 1u;
-                *inv = max(*inv, ~du);
-            }
+        if (((cand >> b) & 1u) && d[b] >= T) {
+            held |= 1u << b;
+            *cnt += 1u;
+            *inv = max(*inv, ~d[b]);
         }
     }
     return held;
@@ -657,6 +666,8 @@ __device__ __forceinline__ void arc_rows(const int32_t *__restrict__ pro, int64_
 // a: the iteration-independent arguments (kernel-argument resident); the
 // flags, held-back flags, threshold and counter slots of the iteration are
 // passed separately.
+constexpr int kFilterBatch = 4;
+
 template <int NP>
 __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t g, const uint8_t *__restrict__ nflags,
                                              uint8_t *__restrict__ cflags, unsigned long long *ctl_next,
@@ -698,19 +709,33 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t g, con
     if (a.nbits) a.nbits[base >> 4] = (uint16_t)mask16;
     if (!__syncthreads_or(mask16 != 0)) return;  // uniform per block
 
-    // x[k] = entries of partition k, x[NP + k] = their arcs
+    // x[k] = entries of partition k, x[NP + k] = their arcs.  The offset rows
+    // of up to kFilterBatch flagged vertices are loaded together (a slot past
+    // the last flagged vertex repeats its row and is not counted): one row at
+    // a time made a chain of round trips per thread.
     int32_t x[2 * NP], tot[2 * NP];
 #pragma unroll
     for (int i = 0; i < 2 * NP; ++i) x[i] = 0;
-    for (uint32_t mm = mask16; mm; mm &= mm - 1) {
-        const int64_t u = base + __builtin_ctz(mm);
-        int32_t f[NP], e[NP];
-        arc_rows<NP>(a.pro, u, f, e);
+    for (uint32_t mm = mask16; mm;) {
+        int b[kFilterBatch];
+        bool on[kFilterBatch];
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int32_t d = e[k] - f[k];
-            x[k] += d > 0 ? 1 : 0;
-            x[NP + k] += d;
+        for (int q = 0; q < kFilterBatch; ++q) {
+            on[q] = mm != 0u;
+            b[q] = on[q] ? __builtin_ctz(mm) : b[q > 0 ? q - 1 : 0];
+            mm = on[q] ? (mm & (mm - 1)) : mm;
+        }
+        int32_t f[kFilterBatch][NP], e[kFilterBatch][NP];
+#pragma unroll
+        for (int q = 0; q < kFilterBatch; ++q) arc_rows<NP>(a.pro, base + b[q], f[q], e[q]);
+#pragma unroll
+        for (int q = 0; q < kFilterBatch; ++q) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const int32_t d = on[q] ? e[q][k] - f[q][k] : 0;
+                x[k] += d > 0 ? 1 : 0;
+                x[NP + k] += d;
+            }
         }
     }
     block_scan<2 * NP>(x, tot);
@@ -727,18 +752,29 @@ __device__ __forceinline__ void filter_group(const FilterArgs &a, int64_t g, con
         pos[k] = (int32_t)(sh_base[k] & 0xFFFFFFFFull) + x[k];
         spos[k] = (int32_t)(sh_base[k] >> 32) + x[NP + k];
     }
-    for (uint32_t mm = mask16; mm; mm &= mm - 1) {
-        const int64_t u = base + __builtin_ctz(mm);
-        int32_t f[NP], e[NP];
-        arc_rows<NP>(a.pro, u, f, e);
+    for (uint32_t mm = mask16; mm;) {
+        int b[kFilterBatch];
+        bool on[kFilterBatch];
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int32_t d = e[k] - f[k];
-            if (d > 0) {
-                a.qse[k][pos[k]] = make_uint2((uint32_t)f[k], (uint32_t)u);
-                a.qs[k][pos[k]] = spos[k];
-                ++pos[k];
-                spos[k] += d;
+        for (int q = 0; q < kFilterBatch; ++q) {
+            on[q] = mm != 0u;
+            b[q] = on[q] ? __builtin_ctz(mm) : b[q > 0 ? q - 1 : 0];
+            mm = on[q] ? (mm & (mm - 1)) : mm;
+        }
+        int32_t f[kFilterBatch][NP], e[kFilterBatch][NP];
+#pragma unroll
+        for (int q = 0; q < kFilterBatch; ++q) arc_rows<NP>(a.pro, base + b[q], f[q], e[q]);
+#pragma unroll
+        for (int q = 0; q < kFilterBatch; ++q) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const int32_t d = e[q][k] - f[q][k];
+                if (on[q] && d > 0) {
+                    a.qse[k][pos[k]] = make_uint2((uint32_t)f[q][k], (uint32_t)(base + b[q]));
+                    a.qs[k][pos[k]] = spos[k];
+                    ++pos[k];
+                    spos[k] += d;
+                }
             }
         }
     }
@@ -860,7 +896,7 @@ __device__ __forceinline__ void filter_dense(const DenseFilterArgs &a, int64_t v
 #pragma unroll
     for (int it = 0; it < kDenseItems; ++it) {
         if (far_cur) {
-            du[it] = on[it] ? a.dist[u[it]] : 0u;
+            du[it] = a.dist[u[it]];  // u[it] is a member (a vertex below n) even when off
             on[it] = on[it] && du[it] < T;
         }
         if (on[it]) {
