@@ -225,7 +225,7 @@ typedef struct {
                              the vertices it improved again, with the distance that improved
                              them, for up to local_hops - 1 further hops before handing the
                              rest to the next round (1 = every improvement waits for the next
-                             round).  0 = the graph's default (4, unless gr_graph_tune chose
+                             round).  0 = the graph's default (6, unless gr_graph_tune chose
                              another); at most 64. */
 } gr_sssp_opts;
 

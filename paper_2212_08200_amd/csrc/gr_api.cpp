@@ -138,9 +138,9 @@ static constexpr int32_t kSmallMaxDegree = 64;
 static constexpr int32_t kDefaultBeta = 24;
 // Small rounds expand the vertices a block improved for this many hops
 // before the next round takes the rest (measured on the 2048^2 road-like
-// graph: 8.4 ms with 1, 5.9 with 2, 5.7 with 4, 5.9 with 8; plain grid
-// 2048^2: 121 / 72 / 55 / 55 ms).
-static constexpr int32_t kDefaultLocalHops = 4;
+// graph: 5.6 ms with 2, 5.35 with 4, 5.4 with 6, 5.6 with 8, 6.1 with 12;
+// plain grid 2048^2: 69 / 51 / 42 / 48 / 53 ms).
+static constexpr int32_t kDefaultLocalHops = 6;
 static constexpr int32_t kAsyncDefaultMaxN = 1 << 16;  // see graph_build
 
 struct gr_graph {
@@ -2085,7 +2085,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
     if (g->max_degree <= kSmallMaxDegree) knobs.push_back({5, {0, 1}});
     knobs.push_back({6, {GR_RELAX_DIST, GR_RELAX_BOUND}});
     knobs.push_back({7, {64, 128, 256, 512, 1024}});  // asynchronous loop only
-    if (g->max_degree <= kSmallMaxDegree) knobs.push_back({8, {1, 2, 4, 8, 16}});  // small rounds only
+    if (g->max_degree <= kSmallMaxDegree) knobs.push_back({8, {1, 2, 4, 6, 8, 16}});  // small rounds only
     for (const auto &kv : knobs) {
         for (int32_t v : kv.second) {
             if (status != GR_OK) break;
