@@ -633,7 +633,9 @@ static gr_status run_host_loop(const gr_graph *g, int32_t src, uint32_t *dist, h
         if (timed) (void)hipEventRecord(ev[0], st);
         if (idle) {
         } else if (pull) {
-            e = launch_pull(dg, dist, f, iter, st);
+            // breadth-first search: every round of this loop is one level, so
+            // the frontier's vertices all have depth iter
+            e = launch_pull(dg, dist, f, iter, st, dg.wt == 2 ? (uint32_t)iter : kInfU32);
             local.pull_iterations++;
             local.arcs_pulled += dg.m;
         } else {

@@ -167,7 +167,11 @@ hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int
 // Pull over the partitioned layout when the graph is symmetric (arcs into a
 // destination range from sources in partition k are read by blocks on XCD k),
 // else over the transposed copy.
-hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st);
+// level (breadth-first search): the depth of every vertex of the frontier
+// when the caller knows it (the pull then reads no source depth), else
+// kInfU32.
+hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st,
+                       uint32_t level = kInfU32);
 // The pull that launch_pull runs: 1 partitioned, 0 over the transposed copy.
 bool pull_partitioned(const DevGraph &g);
 // zmask: optional per-vertex 64-bit masks (batched queries) cleared by the filter.

@@ -412,7 +412,7 @@ __device__ __forceinline__ void pull_block(int32_t n, const int32_t *__restrict_
 __device__ __forceinline__ void pull_block_bfs(int32_t n, const int32_t *__restrict__ ro_in,
                                                const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
                                                const uint32_t *__restrict__ cbits, uint8_t *__restrict__ nflags,
-                                               uint32_t *__restrict__ bound, int64_t vb) {
+                                               uint32_t *__restrict__ bound, int64_t vb, uint32_t level) {
     __shared__ int32_t sPre[kBlk + 1];
     __shared__ int32_t sStart[kBlk];
     __shared__ uint32_t sMin[kBlk];
@@ -454,9 +454,17 @@ __device__ __forceinline__ void pull_block_bfs(int32_t n, const int32_t *__restr
         bool fl[kPullItems];
 #pragma unroll
         for (int it = 0; it < kPullItems; ++it) fl[it] = in_frontier(cbits, arc[it].x);
+        // level: the depth of every frontier vertex when the caller knows it
+        // (level-synchronous rounds of the host-driven loop), so no source
+        // depth is read; else kInfU32 and each active source's depth is read
         uint32_t du[kPullItems];
+        if (level != kInfU32) {
 #pragma unroll
-        for (int it = 0; it < kPullItems; ++it) du[it] = fl[it] ? dist[arc[it].x] : kInfU32;
+            for (int it = 0; it < kPullItems; ++it) du[it] = fl[it] ? level : kInfU32;
+        } else {
+#pragma unroll
+            for (int it = 0; it < kPullItems; ++it) du[it] = fl[it] ? dist[arc[it].x] : kInfU32;
+        }
 #pragma unroll
         for (int it = 0; it < kPullItems; ++it)
             if (x0b + t + it * kBlk < H && du[it] != kInfU32) atomicMin(&sMin[pos[it]], du[it] + 1u);
@@ -545,8 +553,8 @@ template <int WT>
 __global__ __launch_bounds__(kBlk) void k_pull(int32_t n, const int32_t *__restrict__ ro_in,
                                                const uint2 *__restrict__ adj_in, uint32_t *__restrict__ dist,
                                                const uint32_t *__restrict__ cbits, uint8_t *__restrict__ nflags,
-                                               uint32_t *__restrict__ bound) {
-    if constexpr (WT == 2) pull_block_bfs(n, ro_in, adj_in, dist, cbits, nflags, bound, blockIdx.x);
+                                               uint32_t *__restrict__ bound, uint32_t level) {
+    if constexpr (WT == 2) pull_block_bfs(n, ro_in, adj_in, dist, cbits, nflags, bound, blockIdx.x, level);
     else pull_block<WT>(n, ro_in, adj_in, dist, cbits, nflags, bound, blockIdx.x);
 }
 
@@ -1053,7 +1061,7 @@ __device__ __forceinline__ bool pick_pull(const PersistArgs &a, int64_t iter, in
 template <int WT, int NP>
 __device__ __forceinline__ void pull_share(const PersistArgs &a, uint8_t *nf, int64_t vb) {
     if constexpr (WT == 2) {
-        pull_block_bfs(a.n, a.ro_in, a.adj_in, a.dist, a.bits, nf, a.bound, vb);
+        pull_block_bfs(a.n, a.ro_in, a.adj_in, a.dist, a.bits, nf, a.bound, vb, kInfU32);
     } else if constexpr (NP == kMaxParts) {
         if (a.part_pull) pull_part_block<WT>(a.n, a.fg.pro, a.padj, a.dist, a.bits, nf, a.bound, vb);
         else pull_block<WT>(a.n, a.ro_in, a.adj_in, a.dist, a.bits, nf, a.bound, vb);
@@ -1965,7 +1973,8 @@ hipError_t launch_push(const DevGraph &g, uint32_t *dist, const Frontier &f, int
 bool pull_partitioned(const DevGraph &g) { return g.np == kMaxParts && g.ro_in == g.ro && g.adj_in == g.adj; }
 
 template <int WT>
-static void pull_dispatch(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st) {
+static void pull_dispatch(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, uint32_t level,
+                          hipStream_t st) {
     const int p = (int)(iter & 1), np1 = p ^ 1;
     const int64_t chunks = (g.n + kBlk - 1) / kBlk;
     if (WT != 2 && pull_partitioned(g))
@@ -1973,14 +1982,15 @@ static void pull_dispatch(const DevGraph &g, uint32_t *dist, const Frontier &f, 
                            g.padj, dist, f.bits, f.flags[np1], f.bound);
     else
         hipLaunchKernelGGL(k_pull<WT>, dim3((unsigned)chunks), dim3(kBlk), 0, st, g.n, g.ro_in, g.adj_in, dist, f.bits,
-                           f.flags[np1], f.bound);
+                           f.flags[np1], f.bound, level);
     (void)p;
 }
 
-hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st) {
-    if (g.wt == 1) pull_dispatch<1>(g, dist, f, iter, st);
-    else if (g.wt == 2) pull_dispatch<2>(g, dist, f, iter, st);
-    else pull_dispatch<0>(g, dist, f, iter, st);
+hipError_t launch_pull(const DevGraph &g, uint32_t *dist, const Frontier &f, int64_t iter, hipStream_t st,
+                       uint32_t level) {
+    if (g.wt == 1) pull_dispatch<1>(g, dist, f, iter, level, st);
+    else if (g.wt == 2) pull_dispatch<2>(g, dist, f, iter, level, st);
+    else pull_dispatch<0>(g, dist, f, iter, level, st);
     return hipGetLastError();
 }
 
