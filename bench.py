@@ -93,7 +93,7 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=8000, help="open-loop queries per load level")
     ap.add_argument("--serve-fifo-queries", type=int, default=1000,
                     help="queries of each level's trace replayed through the one-at-a-time FIFO")
-    ap.add_argument("--serve-executors", type=int, default=1,
+    ap.add_argument("--serve-executors", type=int, default=3,
                     help="server: executors (each a stream with its own multi-query session)")
     ap.add_argument("--serve-slots", type=int, default=64, help="server: live queries per executor")
     ap.add_argument("--serve-local-hops", type=int, default=0, help="server: local hops (0: the library's default)")
@@ -545,8 +545,8 @@ def measure_serving(args, torch, np, gr, gg, dev):
     inf = gr.GR_DIST_INF_U32
     edges_of = {}
 
-    def serve(lo, hi, arrivals_ns, max_batch):
-        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=args.serve_executors,
+    def serve(lo, hi, arrivals_ns, max_batch, executors):
+        srv = gr.gr_server_create(64 << 30, max_batch=max_batch, num_streams=executors,
                                   local_hops=args.serve_local_hops)
         try:
             gids = [gr.gr_server_add_graph(srv, G.handle) for G in Gs]
@@ -640,8 +640,8 @@ def measure_serving(args, torch, np, gr, gg, dev):
         qps = frac * qstar
         gaps = rng.exponential(1.0 / qps, size=nq)
         arr = (np.cumsum(gaps) * 1e9).astype(np.int64)
-        lat, span, res = serve(300, 300 + nq, arr, args.serve_slots)
-        lat1, _, _ = serve(300, 300 + nfifo, arr[:nfifo], 1)
+        lat, span, res = serve(300, 300 + nq, arr, args.serve_slots, args.serve_executors)
+        lat1, _, _ = serve(300, 300 + nfifo, arr[:nfifo], 1, 1)  # one query at a time, in arrival order
         edges = sum(m_reached(*mix[q]) for q in range(300, 300 + nq))
         sizes = np.array([r["batch_size"] for r in res])
         hist = {}

@@ -377,7 +377,7 @@ gr_status gr_sssp_multi(const gr_graph *const *graphs, const int32_t *srcs, int3
 
 typedef struct {
     int32_t max_batch;      /* queries one executor runs together, 1..64 (0 = 64) */
-    int32_t num_streams;    /* executors, each with its own stream, 1..8 (0 = 1) */
+    int32_t num_streams;    /* executors, each with its own stream, 1..8 (0 = 3) */
     int32_t max_wait_us;    /* unused: queries join a running executor at its next chunk of
                                rounds, so none waits for company (must be >= 0) */
     int32_t local_hops;     /* push blocks expand the vertices they improved on graphs of degree
