@@ -134,10 +134,11 @@ gr_status gr_sssp(const gr_graph *g, int32_t src, void *dist_out, void *stream);
  * hipFree, pool allocation or pinned-memory allocation, and creates no event.
  *   - Workspace: a fixed array of 96 MiB (GR_NOALLOC_SCRATCH_BYTES) that the
  *     library holds on every GPU it runs on until the process ends.  A query
- *     needs about 20 bytes per vertex plus 2 MiB (the plain CSR layout, one
+ *     needs about 14 bytes per vertex (18 when the graph's default uses the
+ *     bound relaxation filter) plus 2 MiB (the plain CSR layout, one
  *     frontier queue); a graph whose workspace exceeds the array returns
  *     GR_ERR_NO_CAPACITY before anything is enqueued.  Graphs of up to about
- *     four million vertices fit.
+ *     five to seven million vertices fit.
  *   - Schedule: the queued (device-driven) loop over the plain CSR layout,
  *     without a near-far split; the direction, filter and relaxation-filter
  *     defaults are the graph's.  The call waits for `stream` once per chunk
