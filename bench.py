@@ -226,7 +226,7 @@ def main():
     if launches and push_us > 0:
         achieved = alg_bytes / (push_us * 1e-6) / 1e9
         kern = {2: "k_persistent", 3: "k_step", 4: "k_async"}.get(stats_last["loop"], "k_push")
-        loop_name = {1: "host", 2: "persistent", 3: "queued", 4: "async"}.get(stats_last["loop"], "?")
+        loop_name = {1: "host", 2: "persistent", 3: "queued", 4: "async", 5: "lds"}.get(stats_last["loop"], "?")
         layout_name = {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?")
         relax_name = {1: "dist", 2: "bound"}.get(stats_last["relax_filter"], "?")
         traffic = counter_traffic(kern, args.workload, loop_name, layout_name, relax_name)
@@ -286,7 +286,7 @@ def main():
         "data": "synthetic (seeded generator)",
         "config": {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m,
                    "layout": {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?") if stats_last else None,
-                   "loop": {1: "host", 2: "persistent", 3: "queued", 4: "async"}.get(stats_last["loop"], "?")
+                   "loop": {1: "host", 2: "persistent", 3: "queued", 4: "async", 5: "lds"}.get(stats_last["loop"], "?")
                    if stats_last else None,
                    "delta": args.delta or None,
                    "relax_filter": {1: "dist", 2: "bound"}.get(stats_last["relax_filter"]) if stats_last else None,
@@ -380,7 +380,7 @@ def kernel_roofline(stats_list, wall_s, q_bytes):
     if not launches or push_us <= 0:
         return None
     achieved = alg / (push_us * 1e-6) / 1e9
-    kern = {2: "k_persistent", 3: "k_step", 4: "k_async"}.get(last["loop"], "k_push")
+    kern = {2: "k_persistent", 3: "k_step", 4: "k_async", 5: "k_lds"}.get(last["loop"], "k_push")
     return {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": int(alg / launches),
             "avg_launch_us": round(push_us / launches, 2), "launches": launches,
@@ -416,7 +416,7 @@ def measure_config(name, steps, torch, np, gr, gg, dev):
     G.close()
     last = stats[-1]
     return {"workload": WORKLOADS[name], "n": g.n, "m": g.m, "src": s,
-            "loop": {1: "host", 2: "persistent", 3: "queued", 4: "async"}.get(last["loop"], "?"),
+            "loop": {1: "host", 2: "persistent", 3: "queued", 4: "async", 5: "lds"}.get(last["loop"], "?"),
             "ms_per_query": round(1e3 * wall / steps, 4), "queries": steps,
             "gteps": round(reached * steps / wall / 1e9, 4),
             "rounds": last["iterations"], "relaxations": last["edges_pushed"],

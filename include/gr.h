@@ -155,16 +155,17 @@ gr_status gr_sssp_noalloc(const gr_graph *g, int32_t src, void *dist_out, void *
 /* Loop schedule of gr_sssp_ex (Section III-A: execution policies). */
 typedef enum {
     GR_LOOP_AUTO = 0,       /* the library's choice: gr_graph_tune's if run, else the
-                               asynchronous loop for graphs of maximum out-degree <= 64
-                               and n <= 65,536 (the queued loop when the request needs
-                               pull or a near-far split), the host-driven loop for graphs
-                               of maximum out-degree > 64 and m >= 2^26, the queued loop
-                               otherwise */
+                               single-workgroup loop for graphs of maximum out-degree <= 64
+                               that fit it (GR_LOOP_LDS), the asynchronous loop for other
+                               graphs of maximum out-degree <= 64 and n <= 65,536 (the
+                               queued loop when the request needs pull or a near-far
+                               split), the host-driven loop for graphs of maximum
+                               out-degree > 64 and m >= 2^26, the queued loop otherwise */
     GR_LOOP_HOST = 1,       /* one launch per operator, host reads the frontier size */
     GR_LOOP_PERSISTENT = 2, /* one cooperative launch, device-side grid barrier */
     GR_LOOP_QUEUED = 3,     /* launches enqueued ahead in chunks; each reads the frontier
                                size from device memory; the host checks once per chunk */
-    GR_LOOP_ASYNC = 4       /* asynchronous (Section III-A without the per-advance barrier,
+    GR_LOOP_ASYNC = 4,      /* asynchronous (Section III-A without the per-advance barrier,
                                III-B frontier as a message queue): one persistent kernel
                                drains a device worklist of improved vertices; no rounds.
                                Push only over the plain CSR (direction PULL / ALTERNATE and
@@ -175,6 +176,18 @@ typedef enum {
                                The call waits for the stream after each phase.  The
                                environment variable GR_ASYNC_LIST_CAP (entries, >= 1)
                                lowers the list capacity, to test the overflow path. */
+    GR_LOOP_LDS = 5         /* single workgroup (Section III-A's loop with a workgroup
+                               barrier per round): one launch of one 1024-thread workgroup
+                               copies the distances, row offsets and arcs (a 16-bit head and
+                               a 16-bit weight each) into LDS and runs every round there.
+                               Graphs with 3 n + m + n / 32 <= 39,900 or so (about 156 KiB
+                               of LDS; a 64 x 64 grid fits) and, for SSSP, uint32 weights
+                               below 65,536; else GR_ERR_INVALID_ARG.  Push only (direction
+                               PULL / ALTERNATE and an explicit delta are
+                               GR_ERR_INVALID_ARG; layout, filter and relax_filter are
+                               ignored).  AUTO picks it for such graphs of maximum
+                               out-degree <= 64.  stats: iterations = rounds,
+                               frontier_sum = vertex expansions, launches = 1. */
 } gr_loop_mode;
 
 /* Traversal direction policy (Section III-C: push vs pull). */

@@ -54,6 +54,7 @@ GR_LOOP_HOST = 1
 GR_LOOP_PERSISTENT = 2
 GR_LOOP_QUEUED = 3
 GR_LOOP_ASYNC = 4
+GR_LOOP_LDS = 5
 GR_DELTA_OFF = 0xFFFFFFFF
 GR_RELAX_DIST = 1
 GR_RELAX_BOUND = 2

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgr.so")
-SOURCES = ["gr_api.cpp", "gr_kernels.hip", "gr_async.hip", "gr_multi.hip", "gr_noalloc.hip"]
+SOURCES = ["gr_api.cpp", "gr_kernels.hip", "gr_async.hip", "gr_multi.hip", "gr_noalloc.hip", "gr_lds.hip"]
 ARCH = os.environ.get("GR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "gr_internal.h"
+#include "gr_lds.h"
 #include "gr_multi.h"
 #include "gr_noalloc.h"
 #include "gr_sched.h"
@@ -171,6 +172,10 @@ struct gr_graph {
     int32_t auto_relax = GR_RELAX_DIST;  // push's relaxation filter
     int32_t auto_async_blocks = 0;       // asynchronous loop's block count (0: async_blocks())
     int32_t auto_local_hops = kDefaultLocalHops;  // small rounds' local hops
+    // single-workgroup loop: the graph fits one workgroup's LDS (lds_fit), and
+    // every weight is below 2^16 (lds_w16: weighted queries can pack arcs)
+    bool lds_fit = false;
+    bool lds_w16 = false;
     // iterations of the last completed queued-loop query (first chunk size)
     mutable std::atomic<int32_t> last_iters{0};
     double locality = 1.0;  // fraction of arcs with |u - v| < locality_span(n)
@@ -353,6 +358,19 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
     // (grid 64^2: 0.9 ms against 2.0 ms queued; 128^2: 1.9 against 4.8 ms;
     // 256^2 even; larger grids and every R-MAT graph favour the queued loop).
     if (g->max_degree <= kSmallMaxDegree && n <= kAsyncDefaultMaxN) g->auto_loop = GR_LOOP_ASYNC;
+    // Graphs that fit one workgroup's LDS: the single-workgroup loop (a round
+    // is a workgroup barrier: grid 64^2 0.18 ms against 0.85 asynchronous).
+    g->lds_fit = lds_fits(n, m);
+    if (g->lds_fit && wt == GR_W_U32) {
+        std::vector<uint2> h((size_t)std::max(m, 1));
+        BUILD_TRY(hipMemcpyAsync(h.data(), g->d_adj, sizeof(uint2) * (size_t)m, hipMemcpyDeviceToHost, st),
+                  "copy arcs");
+        BUILD_TRY(hipStreamSynchronize(st), "copy arcs");
+        uint32_t wmax = 0;
+        for (int32_t e = 0; e < m; ++e) wmax = std::max(wmax, h[(size_t)e].y);
+        g->lds_w16 = wmax < 65536u;
+    }
+    if (g->lds_fit && g->lds_w16 && g->max_degree <= kSmallMaxDegree) g->auto_loop = GR_LOOP_LDS;
     // Large skewed graphs: few, heavy rounds, where the host-driven loop's
     // push grid of 16 blocks per CU beats the step kernel (R-MAT 22: 3.48 ms
     // against 3.63); smaller ones keep the queued loop (no host round trip
@@ -507,7 +525,7 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
     rc->max_iters_given = o && o->max_iters > 0;
     const int layout = o ? o->layout : GR_LAYOUT_AUTO;
     if (!g->pull) rc->alpha_x16 = 0;  // the device-side AUTO rule must never pick pull then
-    if (rc->loop < GR_LOOP_AUTO || rc->loop > GR_LOOP_ASYNC)
+    if (rc->loop < GR_LOOP_AUTO || rc->loop > GR_LOOP_LDS)
         return fail(GR_ERR_INVALID_ARG, "unknown loop mode %d", rc->loop);
     if (rc->direction < GR_DIR_AUTO || rc->direction > GR_DIR_ALTERNATE)
         return fail(GR_ERR_INVALID_ARG, "unknown direction %d", rc->direction);
@@ -540,6 +558,16 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
         float x;
         std::memcpy(&x, &d, 4);
         if (!(x > 0.f && x <= FLT_MAX)) return fail(GR_ERR_INVALID_ARG, "delta must be a positive finite binary32");
+    }
+    if (rc->loop == GR_LOOP_LDS) {
+        if (!g->lds_fit)
+            return fail(GR_ERR_INVALID_ARG, "the single-workgroup loop needs a graph that fits one workgroup's LDS "
+                                            "(n = %d, m = %d do not)", g->plain.n, g->plain.m);
+        if (rc->direction == GR_DIR_PULL || rc->direction == GR_DIR_ALTERNATE)
+            return fail(GR_ERR_INVALID_ARG, "the single-workgroup loop runs push only");
+        if (o && o->delta && o->delta != GR_DELTA_OFF)
+            return fail(GR_ERR_INVALID_ARG, "the single-workgroup loop has no near-far split");
+        d = 0;
     }
     if (rc->loop == GR_LOOP_ASYNC) {
         if (rc->direction == GR_DIR_PULL || rc->direction == GR_DIR_ALTERNATE)
@@ -891,6 +919,49 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
 // gr_async.hip) per phase; a phase ends early only when the list overflowed,
 // and the next one starts from the spilled vertices.  The host waits for
 // each phase (phases beyond the first are rare: the list holds 4 n entries).
+// Single-workgroup loop (gr_lds.hip): one launch runs the whole query in one
+// workgroup's LDS; the host reads its four statistics words.
+static gr_status run_lds(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
+                         gr_sssp_stats *stats) {
+    const DevGraph &dg = g->plain;
+    const int wt = rc.dg->wt == 2 ? 2 : dg.wt;
+    if (!g->lds_fit) return fail(GR_ERR_INVALID_ARG, "the graph does not fit the single-workgroup loop");
+    if (wt != 2 && !(dg.wt == GR_W_U32 && g->lds_w16))
+        return fail(GR_ERR_INVALID_ARG, "the single-workgroup loop packs weights in 16 bits: uint32 weights "
+                                        "below 65,536 only");
+    // the kernel writes its statistics straight into the thread's pinned
+    // buffer (mapped host memory): no workspace, no copy
+    unsigned long long *hp = pinned_slot();
+    if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
+    for (int i = 0; i < kLdsStatWords; ++i) hp[i] = 0ull;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool timed = rc.timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
+    if (timed) (void)hipEventRecord(ev[0], st);
+    hipError_t e = launch_lds(dg.n, dg.m, wt, dg.ro, dg.adj, src, dist, rc.max_iters, hp, st);
+    if (timed) (void)hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    float us = 0.f;
+    if (timed && e == hipSuccess) (void)hipEventElapsedTime(&us, ev[0], ev[1]);
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(e, "single-workgroup loop");
+    if (hp[1] == 0ull) return fail(GR_ERR_HIP, "single-workgroup loop wrote no result");
+    if (hp[1] == 2ull) return fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)rc.max_iters);
+    if (stats) {
+        gr_sssp_stats local{};
+        local.loop = GR_LOOP_LDS;
+        local.layout = GR_LAYOUT_PLAIN;
+        local.relax_filter = GR_RELAX_DIST;
+        local.iterations = (int32_t)std::min<unsigned long long>(hp[0], INT32_MAX);
+        local.edges_pushed = (int64_t)hp[2];
+        local.push_frontier_sum = local.frontier_sum = (int64_t)hp[3];
+        local.push_launches = local.launches = 1;
+        local.push_us = 1e3 * us;
+        *stats = local;
+    }
+    return GR_OK;
+}
+
 static gr_status run_async(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
                            gr_sssp_stats *stats) {
     DeviceInfo di;
@@ -989,10 +1060,14 @@ extern "C" gr_status gr_sssp_ex(const gr_graph *g, int32_t src, void *dist_out, 
     int loop = rc.loop;
     if (loop == GR_LOOP_AUTO) {
         loop = g->auto_loop;
-        // the asynchronous loop is push-only and has no near-far split
-        if (loop == GR_LOOP_ASYNC && (rc.direction == GR_DIR_PULL || rc.direction == GR_DIR_ALTERNATE || rc.delta))
+        // the asynchronous and single-workgroup loops are push-only and have
+        // no near-far split
+        if ((loop == GR_LOOP_ASYNC || loop == GR_LOOP_LDS) &&
+            (rc.direction == GR_DIR_PULL || rc.direction == GR_DIR_ALTERNATE || rc.delta))
             loop = GR_LOOP_QUEUED;
     }
+    if (loop == GR_LOOP_LDS)
+        return run_lds(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
     if (loop == GR_LOOP_ASYNC)
         return run_async(g, src, static_cast<uint32_t *>(dist_out), static_cast<hipStream_t>(stream), rc, stats);
     if (loop == GR_LOOP_QUEUED)
@@ -1108,7 +1183,9 @@ extern "C" gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, 
     // optimising: R-MAT 22 1.23 ms against 1.34 queued), the queued loop on
     // bounded-degree ones (thousands of rounds: grid 2048^2 39 ms against 172)
     int loop = rc.loop;
-    if (loop == GR_LOOP_AUTO) loop = g->max_degree > kSmallMaxDegree ? GR_LOOP_HOST : GR_LOOP_QUEUED;
+    // (graphs that fit one workgroup's LDS: the single-workgroup loop)
+    if (loop == GR_LOOP_AUTO)
+        loop = g->max_degree > kSmallMaxDegree ? GR_LOOP_HOST : g->lds_fit ? GR_LOOP_LDS : GR_LOOP_QUEUED;
     if (loop == GR_LOOP_PERSISTENT)
         return fail(GR_ERR_INVALID_ARG, "the device-driven persistent loop runs weighted queries only");
     DevGraph unit = *rc.dg;
@@ -1117,6 +1194,7 @@ extern "C" gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, 
     uint32_t *d = static_cast<uint32_t *>(depth_out);
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (loop == GR_LOOP_ASYNC) return run_async(g, src, d, st, rc, stats);
+    if (loop == GR_LOOP_LDS) return run_lds(g, src, d, st, rc, stats);
     return loop == GR_LOOP_QUEUED ? run_queued(g, src, d, st, rc, stats) : run_host_loop(g, src, d, st, rc, stats);
 }
 
@@ -1136,6 +1214,7 @@ static gr_status run_single_auto(const gr_graph *g, int32_t src, uint32_t *dist,
     const int loop = g->auto_loop;
     gr_sssp_stats one{};
     if (loop == GR_LOOP_ASYNC) s = run_async(g, src, dist, st, rc, &one);
+    else if (loop == GR_LOOP_LDS) s = run_lds(g, src, dist, st, rc, &one);
     else if (loop == GR_LOOP_QUEUED) s = run_queued(g, src, dist, st, rc, &one);
     else if (loop == GR_LOOP_PERSISTENT) s = run_persistent(g, src, dist, st, rc, &one);
     else s = run_host_loop(g, src, dist, st, rc, &one);
@@ -2036,8 +2115,8 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         o.layout = c.layout;
         o.alpha_x16 = c.alpha_x16 > 0 ? c.alpha_x16 : 0;
         o.direction = c.alpha_x16 > 0 ? GR_DIR_AUTO : GR_DIR_PUSH;
-        o.delta = (c.delta && c.loop != GR_LOOP_ASYNC) ? c.delta : GR_DELTA_OFF;
-        if (c.loop == GR_LOOP_ASYNC) o.direction = GR_DIR_PUSH;
+        o.delta = (c.delta && c.loop != GR_LOOP_ASYNC && c.loop != GR_LOOP_LDS) ? c.delta : GR_DELTA_OFF;
+        if (c.loop == GR_LOOP_ASYNC || c.loop == GR_LOOP_LDS) o.direction = GR_DIR_PUSH;
         o.filter = c.small ? 3 : 0;
         o.relax_filter = c.relax;
         o.local_hops = c.local_hops;
@@ -2077,8 +2156,11 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         DeviceInfo di;
         const bool coop = device_info(g->device, &di) == GR_OK && di.coop &&
                           persistent_grid(g->plain, di.num_cu) >= kMaxParts;
-        knobs.push_back({1, coop ? std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_PERSISTENT, GR_LOOP_ASYNC}
-                                 : std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_ASYNC}});
+        std::vector<int32_t> loops = coop ? std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_PERSISTENT,
+                                                                 GR_LOOP_ASYNC}
+                                          : std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_ASYNC};
+        if (g->lds_fit && g->lds_w16) loops.push_back(GR_LOOP_LDS);
+        knobs.push_back({1, loops});
     }
     knobs.push_back({2, {8, 64, 512}});
     if (g->pull) knobs.push_back({3, {0, 8, 32}});
@@ -2096,6 +2178,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
             if (status != GR_OK) break;
             TuneCfg c = best;
             if (c.loop == GR_LOOP_ASYNC && kv.first != 1 && kv.first != 7) continue;  // the others do not apply
+            if (c.loop == GR_LOOP_LDS && kv.first != 1) continue;
             if (kv.first == 7 && c.loop != GR_LOOP_ASYNC) continue;
             if (kv.first == 4) {
                 if (c.delta == (uint32_t)v) continue;

@@ -144,7 +144,7 @@ def test_async_rejects_and_times_out():
             gr.gr_sssp_ex(G.handle, 0, dist, loop=gr.GR_LOOP_ASYNC, delta=50)
         assert ei.value.status == gr.GR_ERR_INVALID_ARG
         with pytest.raises(gr.GrError) as ei:
-            gr.gr_sssp_ex(G.handle, 0, dist, loop=5)
+            gr.gr_sssp_ex(G.handle, 0, dist, loop=6)  # past the last loop mode
         assert ei.value.status == gr.GR_ERR_INVALID_ARG
         # a 1 us bound on a worklist wait: idle blocks give up, the query
         # reports the failure, and the next query on the graph is exact
@@ -158,9 +158,10 @@ def test_async_rejects_and_times_out():
 
 
 def test_async_is_the_small_mesh_default():
-    # bounded degree and n <= 65,536: AUTO runs the asynchronous loop, except
-    # for requests it cannot serve (pull, near-far), which take the queued loop
-    g = gg.grid(64, wseed=2)
+    # bounded degree and n <= 65,536, too large for one workgroup's LDS: AUTO
+    # runs the asynchronous loop, except for requests it cannot serve (pull,
+    # near-far), which take the queued loop
+    g = gg.grid(128, wseed=2)
     want = oracle.dijkstra(g, 0)
     G = gr.Graph.from_csr(g)
     try:

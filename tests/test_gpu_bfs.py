@@ -105,11 +105,14 @@ def test_bfs_rmat20_rmat22_configs():
 
 
 def test_bfs_default_loop_on_a_mesh():
-    g = gg.grid(48, wseed=3)
-    G = gr.Graph.from_csr(g)
-    try:
-        got, st = bfs(G, g.n, 0)
-        assert np.array_equal(got, oracle.bfs(g, 0))
-        assert st["loop"] == gr.GR_LOOP_QUEUED  # bounded degree: the queued loop
-    finally:
-        G.close()
+    # bounded degree: the single-workgroup loop when the mesh fits one
+    # workgroup's LDS, else the queued loop
+    for side, loop in ((48, gr.GR_LOOP_LDS), (96, gr.GR_LOOP_QUEUED)):
+        g = gg.grid(side, wseed=3)
+        G = gr.Graph.from_csr(g)
+        try:
+            got, st = bfs(G, g.n, 0)
+            assert np.array_equal(got, oracle.bfs(g, 0))
+            assert st["loop"] == loop, side
+        finally:
+            G.close()

@@ -38,13 +38,16 @@ def test_golden_fixture_on_gpu(name):
         layouts = [gr.GR_LAYOUT_PLAIN] + ([gr.GR_LAYOUT_PARTITIONED] if info["partitions"] > 1 else [])
         dirs = [gr.GR_DIR_PUSH, gr.GR_DIR_AUTO] + (
             [gr.GR_DIR_PULL, gr.GR_DIR_ALTERNATE] if info["pull_enabled"] else [])
-        loops = (gr.GR_LOOP_HOST, gr.GR_LOOP_PERSISTENT, gr.GR_LOOP_QUEUED, gr.GR_LOOP_ASYNC)
+        # the single-workgroup loop packs uint32 weights below 2^16 (every fixture fits its LDS)
+        lds = g.wtype == gr.GR_W_U32 and (g.m == 0 or int(np.max(g.w)) < 65536)
+        loops = (gr.GR_LOOP_HOST, gr.GR_LOOP_PERSISTENT, gr.GR_LOOP_QUEUED, gr.GR_LOOP_ASYNC) + (
+            (gr.GR_LOOP_LDS,) if lds else ())
         for src, dist, hops in queries:
             for lay in layouts:
                 for d in dirs:
                     for lp in loops:
-                        if lp == gr.GR_LOOP_ASYNC and d not in (gr.GR_DIR_PUSH, gr.GR_DIR_AUTO):
-                            continue  # the asynchronous loop is push-only
+                        if lp in (gr.GR_LOOP_ASYNC, gr.GR_LOOP_LDS) and d not in (gr.GR_DIR_PUSH, gr.GR_DIR_AUTO):
+                            continue  # the asynchronous and single-workgroup loops are push-only
                         for rf in (gr.GR_RELAX_DIST, gr.GR_RELAX_BOUND):
                             tag = "%s src=%d layout=%d dir=%d loop=%d relax=%d" % (name, src, lay, d, lp, rf)
                             say("golden " + tag)
@@ -53,7 +56,7 @@ def test_golden_fixture_on_gpu(name):
                             gr.gr_sssp_ex(G.handle, src, out, loop=lp, direction=d, layout=lay, relax_filter=rf,
                                           **kw)
                             np.testing.assert_array_equal(host(out), dist, err_msg=tag)
-            for lp in (gr.GR_LOOP_HOST, gr.GR_LOOP_QUEUED, gr.GR_LOOP_ASYNC):
+            for lp in (gr.GR_LOOP_HOST, gr.GR_LOOP_QUEUED, gr.GR_LOOP_ASYNC, gr.GR_LOOP_LDS):
                 say("golden bfs %s src=%d loop=%d" % (name, src, lp))
                 out = fresh(g.n)
                 kw = dict(barrier_timeout_us=5_000_000) if lp != gr.GR_LOOP_HOST else {}

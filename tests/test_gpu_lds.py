@@ -1,0 +1,153 @@
+"""GPU parity of the single-workgroup loop (GR_LOOP_LDS): one 1024-thread
+workgroup holds the distances, row offsets, arcs and frontier lists of a small
+graph in LDS and runs every round there.  Distances are compared with the CPU
+oracle element by element (tolerance 0: the fixed point is unique), for SSSP
+and for BFS, on the small-mesh configuration, on skewed and directed graphs,
+on the degenerate cases (one vertex, isolated source, unreachable parts), at
+the 16-bit weight limit and at the LDS size limit, and for the argument
+errors and the round cap."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+gr = pytest.importorskip("paper_2212_08200_amd")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run(G, n, src, bfs=False, **kw):
+    d = torch.full((n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+    f = gr.gr_bfs_ex if bfs else gr.gr_sssp_ex
+    st = f(G.handle, int(src), d, loop=gr.GR_LOOP_LDS, **kw)
+    torch.cuda.synchronize()
+    return d.cpu().numpy().view(np.uint32), st
+
+
+def check(g, srcs, bfs=True):
+    G = gr.Graph.from_csr(g)
+    try:
+        for s in srcs:
+            say("lds %s n=%d m=%d src=%d" % (g.name, g.n, g.m, s))
+            got, st = run(G, g.n, s)
+            np.testing.assert_array_equal(got, oracle.dijkstra(g, int(s)), err_msg="%s src=%d" % (g.name, s))
+            assert st["loop"] == gr.GR_LOOP_LDS and st["launches"] == 1 and st["iterations"] >= 1
+            code, v = oracle.certify(g, int(s), got)
+            assert code == 0, (code, v)
+            if bfs:
+                got, st = run(G, g.n, s, bfs=True)
+                np.testing.assert_array_equal(got, oracle.bfs(g, int(s)), err_msg="bfs %s src=%d" % (g.name, s))
+    finally:
+        G.close()
+
+
+def test_lds_small_mesh_config():
+    g, srcs = gg.workload("grid64")
+    check(g, list(srcs) + [4095, 2080])
+
+
+def test_lds_road_like_and_random():
+    check(gg.grid(60, 5, whi=1000, shortcuts=4, sseed=9, name="road60"), [0, 1234, 3599])
+    g = gg.uniform(3000, 9000, gseed=3, wseed=4, whi=500, name="uniform3000")  # directed, with unreachable vertices
+    check(g, [int(x) for x in gg.pick_sources(g, 5, 3)])
+
+
+def test_lds_skewed_graph_explicit():
+    # hubs: a thread expands a hub's arcs alone (correct, not fast); AUTO does not pick the loop here
+    g = gg.rmat(11, 8, gseed=41, pseed=42, wseed=43, name="rmat11")
+    check(g, [int(x) for x in gg.pick_sources(g, 44, 3)])
+
+
+def test_lds_degenerate_graphs():
+    check(gg.from_arcs(1, [], name="one"), [0])
+    check(gg.from_arcs(5, [(0, 1, 7), (1, 2, 65535), (3, 4, 1)], name="parts"), [0, 2, 3, 4])
+    # isolated source, self-loops and parallel arcs kept as given
+    check(gg.from_arcs(4, [(1, 1, 3), (1, 2, 9), (1, 2, 4), (2, 3, 1)], name="loops"), [0, 1])
+
+
+def test_lds_weight_limit():
+    g = gg.grid(40, 6, wlo=60000, whi=65535, name="grid40w")  # weights up to 2^16 - 1 pack
+    check(g, [0, 799])
+    g = gg.from_arcs(3, [(0, 1, 65535), (1, 2, 65536)], name="w17")  # a weight of 2^16 does not
+    G = gr.Graph.from_csr(g)
+    try:
+        with pytest.raises(gr.GrError) as ei:
+            run(G, g.n, 0)
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
+        got, _ = run(G, g.n, 0, bfs=True)  # unit steps ignore the weights
+        np.testing.assert_array_equal(got, oracle.bfs(g, 0))
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        st = gr.gr_sssp_ex(G.handle, 0, d)  # AUTO: another loop
+        torch.cuda.synchronize()
+        assert st["loop"] != gr.GR_LOOP_LDS
+        np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), oracle.dijkstra(g, 0))
+    finally:
+        G.close()
+
+
+def test_lds_size_limit():
+    # 3 n + m + n / 32 + 1 words must fit 39,936: a 75 x 75 grid does, 76 x 76 does not
+    fits, over = gg.grid(75, 7, name="grid75"), gg.grid(76, 7, name="grid76")
+    check(fits, [0, fits.n - 1], bfs=False)
+    G = gr.Graph.from_csr(over)
+    try:
+        with pytest.raises(gr.GrError) as ei:
+            run(G, over.n, 0)
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
+        d = torch.empty(over.n, dtype=torch.int32, device="cuda")
+        st = gr.gr_sssp_ex(G.handle, 0, d)  # AUTO takes another loop
+        torch.cuda.synchronize()
+        assert st["loop"] != gr.GR_LOOP_LDS
+        np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), oracle.dijkstra(over, 0))
+    finally:
+        G.close()
+
+
+def test_lds_is_the_small_mesh_default_and_errors():
+    g = gg.grid(64, wseed=2)
+    want = oracle.dijkstra(g, 0)
+    G = gr.Graph.from_csr(g)
+    try:
+        for kw, loop in ((dict(), gr.GR_LOOP_LDS), (dict(direction=gr.GR_DIR_ALTERNATE), gr.GR_LOOP_QUEUED),
+                         (dict(delta=50), gr.GR_LOOP_QUEUED)):
+            d = torch.full((g.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+            st = gr.gr_sssp_ex(G.handle, 0, d, **kw)
+            torch.cuda.synchronize()
+            assert st["loop"] == loop, kw
+            np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), want, err_msg=str(kw))
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        st = gr.gr_bfs_ex(G.handle, 0, d)
+        torch.cuda.synchronize()
+        assert st["loop"] == gr.GR_LOOP_LDS
+        np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), oracle.bfs(g, 0))
+        for kw in (dict(direction=gr.GR_DIR_PULL), dict(delta=50)):
+            with pytest.raises(gr.GrError) as ei:
+                gr.gr_sssp_ex(G.handle, 0, d, loop=gr.GR_LOOP_LDS, **kw)
+            assert ei.value.status == gr.GR_ERR_INVALID_ARG
+        # the round cap ends the query with an error
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_ex(G.handle, 0, d, loop=gr.GR_LOOP_LDS, max_iters=3)
+        assert ei.value.status == gr.GR_ERR_ITER_LIMIT
+    finally:
+        G.close()
+    gf = gg.grid(32, 3, wtype=gg.W_F32, name="grid32f")  # binary32 weights do not pack
+    G = gr.Graph.from_csr(gf)
+    try:
+        d = torch.empty(gf.n, dtype=torch.int32, device="cuda")
+        with pytest.raises(gr.GrError) as ei:
+            gr.gr_sssp_ex(G.handle, 0, d, loop=gr.GR_LOOP_LDS)
+        assert ei.value.status == gr.GR_ERR_INVALID_ARG
+        st = gr.gr_sssp_ex(G.handle, 0, d)  # AUTO: another loop
+        torch.cuda.synchronize()
+        assert st["loop"] != gr.GR_LOOP_LDS
+        np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), oracle.dijkstra(gf, 0))
+    finally:
+        G.close()

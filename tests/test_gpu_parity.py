@@ -253,7 +253,7 @@ def test_errors_on_gpu():
                 gr.gr_sssp_ex(G.handle, 0, dist, max_iters=3, loop=lp)
             assert ei.value.status == gr.GR_ERR_ITER_LIMIT
         with pytest.raises(gr.GrError) as ei:
-            gr.gr_sssp_ex(G.handle, 0, dist, loop=5)
+            gr.gr_sssp_ex(G.handle, 0, dist, loop=6)  # past the last loop mode
         assert ei.value.status == gr.GR_ERR_INVALID_ARG
         for rf in (-1, 3):
             with pytest.raises(gr.GrError) as ei:

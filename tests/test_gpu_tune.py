@@ -39,7 +39,8 @@ def test_tune_then_query(flags, tmp_path, monkeypatch):
         assert r["layout"] in (gr.GR_LAYOUT_PLAIN, gr.GR_LAYOUT_PARTITIONED)
         if not G.info()["partitions"] > 1:
             assert r["layout"] == gr.GR_LAYOUT_PLAIN
-        assert r["loop"] in (gr.GR_LOOP_HOST, gr.GR_LOOP_PERSISTENT, gr.GR_LOOP_QUEUED, gr.GR_LOOP_ASYNC)
+        assert r["loop"] in (gr.GR_LOOP_HOST, gr.GR_LOOP_PERSISTENT, gr.GR_LOOP_QUEUED, gr.GR_LOOP_ASYNC,
+                             gr.GR_LOOP_LDS)
         assert r["dense_ratio"] in (8, 64, 512) and r["alpha_x16"] in (0, 8, 32)
         assert r["relax_filter"] in (gr.GR_RELAX_DIST, gr.GR_RELAX_BOUND)
         assert 0 < r["best_ms"] <= r["default_ms"]
