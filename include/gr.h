@@ -180,9 +180,9 @@ typedef enum {
                                barrier per round): one launch of one 1024-thread workgroup
                                copies the distances, row offsets and arcs (a 16-bit head and
                                a 16-bit weight each) into LDS and runs every round there.
-                               Graphs with 3 n + m + n / 32 <= 39,900 or so (about 156 KiB
-                               of LDS; a 64 x 64 grid fits) and, for SSSP, uint32 weights
-                               below 65,536; else GR_ERR_INVALID_ARG.  Push only (direction
+                               Graphs with 3 n + m <= 39,900 or so (about 156 KiB of LDS;
+                               a 64 x 64 grid fits) and, for SSSP, uint32 weights below
+                               65,536; else GR_ERR_INVALID_ARG.  Push only (direction
                                PULL / ALTERNATE and an explicit delta are
                                GR_ERR_INVALID_ARG; layout, filter and relax_filter are
                                ignored).  AUTO picks it for such graphs of maximum

@@ -9,12 +9,16 @@
 namespace gr {
 
 // LDS budget of the loop (words of 4 bytes) and its layout for n vertices and
-// m arcs: distances (n), row offsets (n + 1), packed arcs (m: head << 16 |
-// weight, or the head alone for unit steps), next-list membership bits
-// (ceil(n / 32)), two frontier lists of 16-bit vertex ids (n each).
+// m arcs: distances with a free bit each (n), row offsets (n + 1), packed
+// arcs (m: head << 16 | weight, or the head alone for unit steps), two
+// frontier lists of 16-bit vertex ids (n each).
 constexpr int kLdsWords = 39936;  // 156 KiB of the 160 KiB of a compute unit
 constexpr int32_t kLdsMaxN = 65536;
 int64_t lds_words(int32_t n, int32_t m);
+// Distances are kept in 31 bits: a graph that fits has n < kLdsWords / 3
+// vertices, so every path, and every offer one arc beyond one, stays below
+// 2^31 - 1 with 16-bit weights.
+static_assert((int64_t)(kLdsWords / 3) * 65535 < 0x7FFFFFFF, "31-bit distances");
 inline bool lds_fits(int32_t n, int32_t m) { return n >= 1 && n <= kLdsMaxN && lds_words(n, m) <= kLdsWords; }
 
 // Statistics words the kernel writes to stat[0..3]: rounds, status (1 done,

@@ -7,16 +7,22 @@
 // workgroup of 1024 threads copies the distances, row offsets and arcs into
 // LDS (arcs packed as a 16-bit head and a 16-bit weight), keeps the frontier
 // as a list of vertex ids in LDS, and runs the bulk-synchronous rounds with
-// workgroup barriers and LDS atomics: a round is a few hundred cycles.
+// workgroup barriers and LDS atomics: a round is well under a microsecond.
 //
-// Round r: every vertex u of list r is expanded by one thread: for each arc
-// (u, v, w), new = dist[u] (+) w; if new beats dist[v], an LDS atomic min;
-// when it lowered dist[v] and v is not yet in list r + 1 (a membership bit,
-// claimed with an atomic or), v is appended.  After a barrier, list r + 1's
-// membership bits are cleared.  dist[u] is read when u is expanded, so an
-// improvement found earlier in the same round is used (as the other loops
-// read dist[u] when staging their frontier).  The loop ends when a round
-// appends nothing; the fixed point is the same.
+// Round r: every vertex u of list r is expanded by a group of lanes: for each
+// arc (u, v, w), new = dist[u] + w, offered to v with an LDS atomic min.
+// Each vertex's LDS word holds its distance shifted left by one and a free
+// bit (set: not on the next list).  Expanding u sets u's free bit with an
+// atomic or, whose result is the distance the group uses; an offer writes
+// new << 1 (free bit clear), and the offer that took v's word from free to
+// queued appends v to list r + 1.  One word per vertex: an improvement that
+// lands after u's atomic or finds u free and queues it again, and one that
+// lands before is read by it.  dist[u] is thus read when u is expanded, so
+// an improvement found earlier in the same round is used (as the other
+// loops read dist[u] when staging their frontier).  One workgroup barrier
+// ends each round; the loop ends when a round appends nothing, at the same
+// fixed point.  Distances take 31 bits, which every graph that fits
+// allows (gr_lds.h).
 
 #include "gr_lds.h"
 
@@ -27,6 +33,7 @@ namespace gr {
 namespace {
 
 constexpr int kLdsThreads = 1024;
+constexpr int kCopy = 8;  // loads in flight per thread while copying the graph
 
 struct LdsArgs {
     int32_t n, m, src;
@@ -37,78 +44,104 @@ struct LdsArgs {
     unsigned long long *stat;
 };
 
-template <int WT>
+// WT: 0 uint32 weights, 2 unit steps; LG: log2 of the lanes per vertex.
+template <int WT, int LG>
 __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     __shared__ uint32_t sMem[kLdsWords];
-    __shared__ int32_t sCnt[2];
+    __shared__ int32_t sCnt[3];
     __shared__ unsigned long long sArcs, sExp;
     const int t = threadIdx.x;
     const int32_t n = a.n, m = a.m;
-    const int32_t nw = (n + 31) / 32;
-    uint32_t *sD = sMem;
+    uint32_t *sW = sMem;  // dist << 1 | free bit
     int32_t *sRo = reinterpret_cast<int32_t *>(sMem + n);
     uint32_t *sArc = sMem + 2 * n + 1;
-    uint32_t *sIn = sArc + m;
-    uint16_t *sL[2] = {reinterpret_cast<uint16_t *>(sIn + nw), reinterpret_cast<uint16_t *>(sIn + nw) + n};
-    const uint32_t inf = WT == 1 ? kInfF32 : kInfU32;
-    for (int32_t v = t; v < n; v += kLdsThreads) sD[v] = inf;
-    for (int32_t v = t; v <= n; v += kLdsThreads) sRo[v] = a.ro[v];
-    for (int32_t e = t; e < m; e += kLdsThreads) {
-        const uint2 x = a.adj[e];
-        sArc[e] = WT == 2 ? x.x : (x.x << 16) | x.y;
+    // the two lists, as one array indexed from list 0 (an offset, not a
+    // pointer chosen at run time, keeps the accesses LDS instructions)
+    uint16_t *sL = reinterpret_cast<uint16_t *>(sArc + m);
+    for (int32_t v = t; v < n; v += kLdsThreads) sW[v] = kInfU32;  // unreached and free
+    // the copies issue kCopy loads before the first LDS store (indexes past
+    // the end read the last element again)
+    for (int32_t v0 = t; v0 <= n; v0 += kLdsThreads * kCopy) {
+        int32_t x[kCopy];
+#pragma unroll
+        for (int k = 0; k < kCopy; ++k) x[k] = a.ro[min(v0 + k * kLdsThreads, n)];
+#pragma unroll
+        for (int k = 0; k < kCopy; ++k)
+            if (v0 + k * kLdsThreads <= n) sRo[v0 + k * kLdsThreads] = x[k];
     }
-    for (int32_t w = t; w < nw; w += kLdsThreads) sIn[w] = 0u;
+    for (int32_t e0 = t; e0 < m; e0 += kLdsThreads * kCopy) {
+        uint2 x[kCopy];
+#pragma unroll
+        for (int k = 0; k < kCopy; ++k) x[k] = a.adj[min(e0 + k * kLdsThreads, m - 1)];
+#pragma unroll
+        for (int k = 0; k < kCopy; ++k)
+            if (e0 + k * kLdsThreads < m) sArc[e0 + k * kLdsThreads] = WT == 2 ? x[k].x : (x[k].x << 16) | x[k].y;
+    }
     if (t == 0) {
-        sD[a.src] = 0u;
-        sL[0][0] = (uint16_t)a.src;
         sCnt[0] = 1;
         sCnt[1] = 0;
+        sCnt[2] = 0;
         sArcs = 0ull;
         sExp = 0ull;
     }
     __syncthreads();
+    if (t == 0) {
+        sW[a.src] = 0u;  // distance 0, queued
+        sL[0] = (uint16_t)a.src;
+    }
+    __syncthreads();
     uint32_t arcs = 0, expanded = 0;
+    constexpr int32_t lg = LG;
+    const int slot = t & ((1 << lg) - 1), lead = (t & 63) - slot;
     int64_t r = 0;
+    // List r's length is sCnt[kr] (kr = r mod 3), list r + 1 is counted in
+    // sCnt[kn], and sCnt[kz] (last read in round r - 1) is cleared for round
+    // r + 1's appends: one barrier per round.
+    int kr = 0, kn = 1, kz = 2;
     for (; r < a.max_rounds; ++r) {
-        const int c = (int)(r & 1);
-        const int32_t cnt = sCnt[c];
+        const int32_t lc = (int32_t)(r & 1) * n, ln = n - lc;  // list r, list r + 1
+        const int32_t cnt = sCnt[kr];
         if (cnt == 0) break;  // uniform: read after a barrier
-        for (int32_t i = t; i < cnt; i += kLdsThreads) {
-            const uint32_t u = sL[c][i];
-            const uint32_t du = sD[u];
+        if (t == 0) sCnt[kz] = 0;
+        // G = 2^lg lanes of one wave expand a vertex together: the group's
+        // first lane frees u and reads dist[u] in one atomic, the distance is
+        // broadcast across the group, and lane s of the group takes the arcs
+        // e0 + s, e0 + s + G, ...
+        for (int32_t i = t; i < (cnt << lg); i += kLdsThreads) {
+            const uint32_t u = sL[lc + (i >> lg)];
             const int32_t e0 = sRo[u], e1 = sRo[u + 1];
-            arcs += (uint32_t)(e1 - e0);
-            expanded += e1 > e0 ? 1u : 0u;
-            for (int32_t e = e0; e < e1; ++e) {
+            uint32_t du = 0u;
+            if (slot == 0) du = __hip_atomic_fetch_or(&sW[u], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 1;
+            // broadcast from the group's first lane (a DPP move within quads
+            // measured no faster than this permute for groups of 2 and 4)
+            if constexpr (LG > 0) du = (uint32_t)__builtin_amdgcn_ds_bpermute(lead << 2, (int)du);
+            expanded += slot == 0 && e1 > e0 ? 1u : 0u;
+            for (int32_t e = e0 + slot; e < e1; e += 1 << lg) {
+                ++arcs;
                 const uint32_t x = sArc[e];
                 const uint32_t v = WT == 2 ? x : x >> 16;
-                const uint32_t nd = plus<WT>(du, WT == 2 ? 1u : (x & 0xFFFFu));
-                if (nd < sD[v]) {
-                    const uint32_t old = atomicMin(&sD[v], nd);
-                    if (nd < old) {
-                        const uint32_t bit = 1u << (v & 31u);
-                        if (!(atomicOr(&sIn[v >> 5], bit) & bit)) sL[c ^ 1][atomicAdd(&sCnt[c ^ 1], 1)] = (uint16_t)v;
-                    }
-                }
+                const uint32_t nw = (du + (WT == 2 ? 1u : (x & 0xFFFFu))) << 1;  // queued
+                const uint32_t old = __hip_atomic_fetch_min(&sW[v], nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                // the atomic took v from free to queued: v goes on list r + 1
+                if (nw < old && (old & 1u)) sL[ln + atomicAdd(&sCnt[kn], 1)] = (uint16_t)v;
             }
         }
         __syncthreads();
-        // list r + 1 is complete: clear its membership bits and list r's count
-        const int32_t nc = sCnt[c ^ 1];
-        for (int32_t i = t; i < nc; i += kLdsThreads) {
-            const uint32_t v = sL[c ^ 1][i];
-            atomicAnd(&sIn[v >> 5], ~(1u << (v & 31u)));
-        }
-        if (t == 0) sCnt[c] = 0;
-        __syncthreads();
+        const int k = kr;
+        kr = kn;
+        kn = kz;
+        kz = k;
     }
-    for (int32_t v = t; v < n; v += kLdsThreads) a.dist[v] = sD[v];
+    for (int32_t v = t; v < n; v += kLdsThreads) {
+        const uint32_t d = sW[v] >> 1;
+        a.dist[v] = d == (kInfU32 >> 1) ? kInfU32 : d;
+    }
     if (arcs) atomicAdd(&sArcs, (unsigned long long)arcs);
     if (expanded) atomicAdd(&sExp, (unsigned long long)expanded);
     __syncthreads();
     if (t == 0) {  // system scope: stat may be host memory
         __hip_atomic_store(a.stat + 0, (unsigned long long)r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(a.stat + 1, sCnt[r & 1] == 0 ? 1ull : 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(a.stat + 1, sCnt[kr] == 0 ? 1ull : 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(a.stat + 2, sArcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(a.stat + 3, sExp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
@@ -117,15 +150,35 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
 }  // namespace
 
 int64_t lds_words(int32_t n, int32_t m) {
-    return 2 * (int64_t)n + 1 + m + (n + 31) / 32 + (n + 1) / 2 * 2;
+    return 2 * (int64_t)n + 1 + m + (n + 1) / 2 * 2;
 }
 
 hipError_t launch_lds(int32_t n, int32_t m, int wt, const int32_t *ro, const uint2 *adj, int32_t src,
                       uint32_t *dist_out, int64_t max_rounds, unsigned long long *stat, hipStream_t st) {
     if (!lds_fits(n, m) || src < 0 || src >= n || wt == 1) return hipErrorInvalidValue;
+    // lanes per expanded vertex: the average degree rounded up to a power of
+    // two, at most 16
+    int32_t lg = 0;
+    while (lg < 4 && ((int64_t)n << lg) < m) ++lg;
     LdsArgs a{n, m, src, max_rounds, ro, adj, dist_out, stat};
-    if (wt == 2) hipLaunchKernelGGL(k_lds<2>, dim3(1), dim3(kLdsThreads), 0, st, a);
-    else hipLaunchKernelGGL(k_lds<0>, dim3(1), dim3(kLdsThreads), 0, st, a);
+    const dim3 grid(1), block(kLdsThreads);
+    if (wt == 2) {
+        switch (lg) {
+            case 0: hipLaunchKernelGGL((k_lds<2, 0>), grid, block, 0, st, a); break;
+            case 1: hipLaunchKernelGGL((k_lds<2, 1>), grid, block, 0, st, a); break;
+            case 2: hipLaunchKernelGGL((k_lds<2, 2>), grid, block, 0, st, a); break;
+            case 3: hipLaunchKernelGGL((k_lds<2, 3>), grid, block, 0, st, a); break;
+            default: hipLaunchKernelGGL((k_lds<2, 4>), grid, block, 0, st, a); break;
+        }
+    } else {
+        switch (lg) {
+            case 0: hipLaunchKernelGGL((k_lds<0, 0>), grid, block, 0, st, a); break;
+            case 1: hipLaunchKernelGGL((k_lds<0, 1>), grid, block, 0, st, a); break;
+            case 2: hipLaunchKernelGGL((k_lds<0, 2>), grid, block, 0, st, a); break;
+            case 3: hipLaunchKernelGGL((k_lds<0, 3>), grid, block, 0, st, a); break;
+            default: hipLaunchKernelGGL((k_lds<0, 4>), grid, block, 0, st, a); break;
+        }
+    }
     return hipGetLastError();
 }
 

@@ -61,7 +61,7 @@ def test_lds_road_like_and_random():
 
 
 def test_lds_skewed_graph_explicit():
-    # hubs: a thread expands a hub's arcs alone (correct, not fast); AUTO does not pick the loop here
+    # hubs: a group of 16 lanes expands a hub's arcs (correct, not fast); AUTO does not pick the loop here
     g = gg.rmat(11, 8, gseed=41, pseed=42, wseed=43, name="rmat11")
     check(g, [int(x) for x in gg.pick_sources(g, 44, 3)])
 
@@ -93,8 +93,16 @@ def test_lds_weight_limit():
         G.close()
 
 
+def test_lds_long_path_distances():
+    # distances are kept in 31 bits: a 9,000-vertex chain of 65,535-weight arcs
+    # (the longest that fits) reaches 589,749,465 = (n - 1) * (2^16 - 1)
+    n = 9000
+    g = gg.from_arcs(n, [(i, i + 1, 65535) for i in range(n - 1)], name="chain9000")
+    check(g, [0, 4321, n - 1])
+
+
 def test_lds_size_limit():
-    # 3 n + m + n / 32 + 1 words must fit 39,936: a 75 x 75 grid does, 76 x 76 does not
+    # 3 n + m + 1 words must fit 39,936: a 75 x 75 grid does, 76 x 76 does not
     fits, over = gg.grid(75, 7, name="grid75"), gg.grid(76, 7, name="grid76")
     check(fits, [0, fits.n - 1], bfs=False)
     G = gr.Graph.from_csr(over)
