@@ -331,7 +331,8 @@ gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, void *strea
 /* Statistics of gr_sssp_batch_ex and gr_sssp_multi. */
 typedef struct {
     int32_t rounds;             /* rounds in which some query's frontier was not empty */
-    int32_t replays;            /* replays of the captured chunk of rounds (one host wait each) */
+    int32_t replays;            /* replays of the captured chunk of rounds (one host wait each); 0 when
+                                   none runs (k = 1, or the single-workgroup loop) */
     int64_t edges_pushed;       /* arcs expanded (a batched arc serves every source active at its tail) */
     int64_t frontier_sum;       /* frontier entries expanded */
     int64_t source_relaxations; /* (arc, query) relaxations: for gr_sssp_batch_ex the (arc, active source)
@@ -354,7 +355,10 @@ typedef struct {
  * the call returns when the result is complete.  Workspace, stream-ordered
  * from the device pool and returned before the call ends: 256 bytes per
  * vertex (distances) + 16 (masks) + about 28 (frontier marks and two queues).
- * k = 1 runs gr_sssp's schedule.  The current device must be the graph's.
+ * k = 1 runs gr_sssp's schedule.  A graph whose AUTO loop is the single-
+ * workgroup loop (GR_LOOP_LDS) runs that loop for every source instead, one
+ * workgroup per source in one launch, with no workspace.  The current device
+ * must be the graph's.
  */
 gr_status gr_sssp_batch(const gr_graph *g, const int32_t *srcs, int32_t k, void *dist_out, void *stream);
 /* gr_sssp_batch with statistics (stats may be NULL). */

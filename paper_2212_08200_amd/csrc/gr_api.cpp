@@ -920,7 +920,38 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
 // and the next one starts from the spilled vertices.  The host waits for
 // each phase (phases beyond the first are rare: the list holds 4 n entries).
 // Single-workgroup loop (gr_lds.hip): one launch runs the whole query in one
-// workgroup's LDS; the host reads its four statistics words.
+// workgroup's LDS (k queries: k workgroups); the host reads each workgroup's
+// four statistics words.
+static gr_status lds_launch_wait(const gr_graph *g, const int32_t *srcs, int32_t k, uint32_t *dist, hipStream_t st,
+                                 int wt, int64_t max_rounds, bool timing, unsigned long long **stat_out,
+                                 float *us_out) {
+    const DevGraph &dg = g->plain;
+    // the kernel writes its statistics straight into the thread's pinned
+    // buffer (mapped host memory): no workspace, no copy
+    unsigned long long *hp = pinned_slot();
+    if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
+    for (int i = 0; i < k * kLdsStatWords; ++i) hp[i] = 0ull;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool timed = timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
+    if (timed) (void)hipEventRecord(ev[0], st);
+    hipError_t e = launch_lds(dg.n, dg.m, wt, dg.ro, dg.adj, srcs, k, dist, max_rounds, hp, st);
+    if (timed) (void)hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    float us = 0.f;
+    if (timed && e == hipSuccess) (void)hipEventElapsedTime(&us, ev[0], ev[1]);
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(e, "single-workgroup loop");
+    for (int32_t b = 0; b < k; ++b) {
+        const unsigned long long code = hp[b * kLdsStatWords + 1];
+        if (code == 0ull) return fail(GR_ERR_HIP, "single-workgroup loop wrote no result");
+        if (code == 2ull) return fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)max_rounds);
+    }
+    *stat_out = hp;
+    *us_out = us;
+    return GR_OK;
+}
+
 static gr_status run_lds(const gr_graph *g, int32_t src, uint32_t *dist, hipStream_t st, const RunCfg &rc,
                          gr_sssp_stats *stats) {
     const DevGraph &dg = g->plain;
@@ -929,24 +960,10 @@ static gr_status run_lds(const gr_graph *g, int32_t src, uint32_t *dist, hipStre
     if (wt != 2 && !(dg.wt == GR_W_U32 && g->lds_w16))
         return fail(GR_ERR_INVALID_ARG, "the single-workgroup loop packs weights in 16 bits: uint32 weights "
                                         "below 65,536 only");
-    // the kernel writes its statistics straight into the thread's pinned
-    // buffer (mapped host memory): no workspace, no copy
-    unsigned long long *hp = pinned_slot();
-    if (!hp) return fail(GR_ERR_OUT_OF_MEMORY, "pinned host buffer");
-    for (int i = 0; i < kLdsStatWords; ++i) hp[i] = 0ull;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    const bool timed = rc.timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
-    if (timed) (void)hipEventRecord(ev[0], st);
-    hipError_t e = launch_lds(dg.n, dg.m, wt, dg.ro, dg.adj, src, dist, rc.max_iters, hp, st);
-    if (timed) (void)hipEventRecord(ev[1], st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    unsigned long long *hp = nullptr;
     float us = 0.f;
-    if (timed && e == hipSuccess) (void)hipEventElapsedTime(&us, ev[0], ev[1]);
-    for (auto &x : ev)
-        if (x) (void)hipEventDestroy(x);
-    if (e != hipSuccess) return hip_fail(e, "single-workgroup loop");
-    if (hp[1] == 0ull) return fail(GR_ERR_HIP, "single-workgroup loop wrote no result");
-    if (hp[1] == 2ull) return fail(GR_ERR_ITER_LIMIT, "iteration cap %lld reached", (long long)rc.max_iters);
+    gr_status s = lds_launch_wait(g, &src, 1, dist, st, wt, rc.max_iters, rc.timing, &hp, &us);
+    if (s != GR_OK) return s;
     if (stats) {
         gr_sssp_stats local{};
         local.loop = GR_LOOP_LDS;
@@ -957,6 +974,31 @@ static gr_status run_lds(const gr_graph *g, int32_t src, uint32_t *dist, hipStre
         local.push_frontier_sum = local.frontier_sum = (int64_t)hp[3];
         local.push_launches = local.launches = 1;
         local.push_us = 1e3 * us;
+        *stats = local;
+    }
+    return GR_OK;
+}
+
+// Batched queries on a graph whose default is the single-workgroup loop: one
+// workgroup per source, all in one launch (no shared work between sources:
+// each workgroup holds its own copy of the graph in its compute unit's LDS).
+static_assert(kLdsMaxBatch >= kBatchLanes, "a batch fits one launch of the single-workgroup loop");
+static gr_status run_lds_batch(const gr_graph *g, const int32_t *srcs, int32_t k, uint32_t *dist, hipStream_t st,
+                               gr_multi_stats *stats) {
+    unsigned long long *hp = nullptr;
+    float us = 0.f;
+    gr_status s = lds_launch_wait(g, srcs, k, dist, st, g->plain.wt, (int64_t)g->plain.n + 1, false, &hp, &us);
+    if (s != GR_OK) return s;
+    if (stats) {
+        gr_multi_stats local{};
+        for (int32_t b = 0; b < k; ++b) {
+            const unsigned long long *x = hp + b * kLdsStatWords;
+            local.rounds = std::max(local.rounds, (int32_t)std::min<unsigned long long>(x[0], INT32_MAX));
+            local.edges_pushed += (int64_t)x[2];
+            local.frontier_sum += (int64_t)x[3];
+        }
+        local.replays = 0;  // no captured chunk: one launch, one wait
+        local.source_relaxations = local.edges_pushed;
         *stats = local;
     }
     return GR_OK;
@@ -1622,6 +1664,7 @@ extern "C" gr_status gr_sssp_batch_ex(const gr_graph *g, const int32_t *srcs, in
     if (s != GR_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (k == 1) return run_single_auto(g, srcs[0], static_cast<uint32_t *>(dist_out), st, stats);
+    if (g->auto_loop == GR_LOOP_LDS) return run_lds_batch(g, srcs, k, static_cast<uint32_t *>(dist_out), st, stats);
     std::vector<uint32_t *> rows((size_t)k);
     for (int32_t i = 0; i < k; ++i) rows[i] = static_cast<uint32_t *>(dist_out) + (size_t)i * g->plain.n;
     return run_batch_dev(g, srcs, k, rows.data(), st, stats);

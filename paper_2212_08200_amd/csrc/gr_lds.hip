@@ -8,6 +8,7 @@
 // LDS (arcs packed as a 16-bit head and a 16-bit weight), keeps the frontier
 // as a list of vertex ids in LDS, and runs the bulk-synchronous rounds with
 // workgroup barriers and LDS atomics: a round is well under a microsecond.
+// A batch of sources runs one such workgroup per source in one launch.
 //
 // Round r: every vertex u of list r is expanded by a group of lanes: for each
 // arc (u, v, w), new = dist[u] + w, offered to v with an LDS atomic min.
@@ -36,12 +37,13 @@ constexpr int kLdsThreads = 1024;
 constexpr int kCopy = 8;  // loads in flight per thread while copying the graph
 
 struct LdsArgs {
-    int32_t n, m, src;
+    int32_t n, m;
     int64_t max_rounds;
     const int32_t *ro;
     const uint2 *adj;
-    uint32_t *dist;
-    unsigned long long *stat;
+    uint32_t *dist;             // k x n
+    unsigned long long *stat;   // k x kLdsStatWords
+    int32_t src[kLdsMaxBatch];  // workgroup b runs src[b]
 };
 
 // WT: 0 uint32 weights, 2 unit steps; LG: log2 of the lanes per vertex.
@@ -52,6 +54,9 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     __shared__ unsigned long long sArcs, sExp;
     const int t = threadIdx.x;
     const int32_t n = a.n, m = a.m;
+    const int32_t src = a.src[blockIdx.x];
+    uint32_t *const dist = a.dist + (size_t)blockIdx.x * (size_t)n;
+    unsigned long long *const stat = a.stat + (size_t)blockIdx.x * kLdsStatWords;
     uint32_t *sW = sMem;  // dist << 1 | free bit
     int32_t *sRo = reinterpret_cast<int32_t *>(sMem + n);
     uint32_t *sArc = sMem + 2 * n + 1;
@@ -86,8 +91,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     }
     __syncthreads();
     if (t == 0) {
-        sW[a.src] = 0u;  // distance 0, queued
-        sL[0] = (uint16_t)a.src;
+        sW[src] = 0u;  // distance 0, queued
+        sL[0] = (uint16_t)src;
     }
     __syncthreads();
     uint32_t arcs = 0, expanded = 0;
@@ -134,16 +139,16 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     }
     for (int32_t v = t; v < n; v += kLdsThreads) {
         const uint32_t d = sW[v] >> 1;
-        a.dist[v] = d == (kInfU32 >> 1) ? kInfU32 : d;
+        dist[v] = d == (kInfU32 >> 1) ? kInfU32 : d;
     }
     if (arcs) atomicAdd(&sArcs, (unsigned long long)arcs);
     if (expanded) atomicAdd(&sExp, (unsigned long long)expanded);
     __syncthreads();
     if (t == 0) {  // system scope: stat may be host memory
-        __hip_atomic_store(a.stat + 0, (unsigned long long)r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(a.stat + 1, sCnt[kr] == 0 ? 1ull : 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(a.stat + 2, sArcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(a.stat + 3, sExp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(stat + 0, (unsigned long long)r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(stat + 1, sCnt[kr] == 0 ? 1ull : 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(stat + 2, sArcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(stat + 3, sExp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -153,15 +158,19 @@ int64_t lds_words(int32_t n, int32_t m) {
     return 2 * (int64_t)n + 1 + m + (n + 1) / 2 * 2;
 }
 
-hipError_t launch_lds(int32_t n, int32_t m, int wt, const int32_t *ro, const uint2 *adj, int32_t src,
-                      uint32_t *dist_out, int64_t max_rounds, unsigned long long *stat, hipStream_t st) {
-    if (!lds_fits(n, m) || src < 0 || src >= n || wt == 1) return hipErrorInvalidValue;
+hipError_t launch_lds(int32_t n, int32_t m, int wt, const int32_t *ro, const uint2 *adj, const int32_t *srcs,
+                      int32_t k, uint32_t *dist_out, int64_t max_rounds, unsigned long long *stat, hipStream_t st) {
+    if (!lds_fits(n, m) || wt == 1 || !srcs || k < 1 || k > kLdsMaxBatch) return hipErrorInvalidValue;
+    LdsArgs a{n, m, max_rounds, ro, adj, dist_out, stat, {}};
+    for (int32_t b = 0; b < k; ++b) {
+        if (srcs[b] < 0 || srcs[b] >= n) return hipErrorInvalidValue;
+        a.src[b] = srcs[b];
+    }
     // lanes per expanded vertex: the average degree rounded up to a power of
     // two, at most 16
     int32_t lg = 0;
     while (lg < 4 && ((int64_t)n << lg) < m) ++lg;
-    LdsArgs a{n, m, src, max_rounds, ro, adj, dist_out, stat};
-    const dim3 grid(1), block(kLdsThreads);
+    const dim3 grid((unsigned)k), block(kLdsThreads);
     if (wt == 2) {
         switch (lg) {
             case 0: hipLaunchKernelGGL((k_lds<2, 0>), grid, block, 0, st, a); break;

@@ -4,8 +4,8 @@ graph in LDS and runs every round there.  Distances are compared with the CPU
 oracle element by element (tolerance 0: the fixed point is unique), for SSSP
 and for BFS, on the small-mesh configuration, on skewed and directed graphs,
 on the degenerate cases (one vertex, isolated source, unreachable parts), at
-the 16-bit weight limit and at the LDS size limit, and for the argument
-errors and the round cap."""
+the 16-bit weight limit and at the LDS size limit, for the argument errors
+and the round cap, and for batches (one workgroup per source)."""
 import sys
 
 import numpy as np
@@ -159,3 +159,29 @@ def test_lds_is_the_small_mesh_default_and_errors():
         np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), oracle.dijkstra(gf, 0))
     finally:
         G.close()
+
+
+def test_lds_batch_one_workgroup_per_source():
+    # gr_sssp_batch on a graph whose default is this loop: one workgroup per
+    # source in one launch; every row certified, two compared in full
+    for g in (gg.workload("grid64")[0], gg.grid(60, 5, whi=1000, shortcuts=4, sseed=9, name="road60")):
+        G = gr.Graph.from_csr(g)
+        try:
+            for k in (2, 17, 64):
+                srcs = np.asarray(gg.pick_sources(g, 90 + k, k), np.int32)
+                if k == 64:
+                    srcs[10] = srcs[3]  # a duplicate source
+                out = torch.full((k, g.n), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+                say("lds batch %s k=%d" % (g.name, k))
+                st = gr.gr_sssp_batch_ex(G.handle, srcs, out)
+                torch.cuda.synchronize()
+                rows = out.cpu().numpy().view(np.uint32)
+                for i, s in enumerate(srcs):
+                    code, v = oracle.certify(g, int(s), rows[i])
+                    assert code == 0, (g.name, k, i, code, v)
+                for i in (0, k - 1):
+                    np.testing.assert_array_equal(rows[i], oracle.dijkstra(g, int(srcs[i])))
+                assert st["replays"] == 0 and st["rounds"] >= 1
+                assert st["source_relaxations"] == st["edges_pushed"] > 0
+        finally:
+            G.close()
