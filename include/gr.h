@@ -386,7 +386,10 @@ gr_status gr_sssp_batch_ex(const gr_graph *g, const int32_t *srcs, int32_t k, vo
  * call waits for the stream once per replay and returns when every query is
  * done.  Workspace: 26 bytes per vertex summed over the queries (two union
  * queues) + 2 bytes per vertex of each query (frontier marks), stream-ordered
- * from the device pool and returned before the call ends.
+ * from the device pool and returned before the call ends.  When every
+ * graph's AUTO loop is the single-workgroup loop (GR_LOOP_LDS), each query
+ * runs that loop in a workgroup of its own, all in one launch, with no
+ * workspace (stats->replays = 0).
  */
 gr_status gr_sssp_multi(const gr_graph *const *graphs, const int32_t *srcs, int32_t k, void *const *dist_out,
                         void *stream, gr_multi_stats *stats, int32_t *iterations);

@@ -922,10 +922,8 @@ static gr_status run_queued(const gr_graph *g, int32_t src, uint32_t *dist, hipS
 // Single-workgroup loop (gr_lds.hip): one launch runs the whole query in one
 // workgroup's LDS (k queries: k workgroups); the host reads each workgroup's
 // four statistics words.
-static gr_status lds_launch_wait(const gr_graph *g, const int32_t *srcs, int32_t k, uint32_t *dist, hipStream_t st,
-                                 int wt, int64_t max_rounds, bool timing, unsigned long long **stat_out,
-                                 float *us_out) {
-    const DevGraph &dg = g->plain;
+static gr_status lds_launch_wait(const LdsJob *jobs, int32_t k, hipStream_t st, int wt, int64_t max_rounds,
+                                 bool timing, unsigned long long **stat_out, float *us_out) {
     // the kernel writes its statistics straight into the thread's pinned
     // buffer (mapped host memory): no workspace, no copy
     unsigned long long *hp = pinned_slot();
@@ -934,7 +932,7 @@ static gr_status lds_launch_wait(const gr_graph *g, const int32_t *srcs, int32_t
     hipEvent_t ev[2] = {nullptr, nullptr};
     const bool timed = timing && hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
     if (timed) (void)hipEventRecord(ev[0], st);
-    hipError_t e = launch_lds(dg.n, dg.m, wt, dg.ro, dg.adj, srcs, k, dist, max_rounds, hp, st);
+    hipError_t e = launch_lds(jobs, k, wt, max_rounds, hp, st);
     if (timed) (void)hipEventRecord(ev[1], st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     float us = 0.f;
@@ -962,7 +960,8 @@ static gr_status run_lds(const gr_graph *g, int32_t src, uint32_t *dist, hipStre
                                         "below 65,536 only");
     unsigned long long *hp = nullptr;
     float us = 0.f;
-    gr_status s = lds_launch_wait(g, &src, 1, dist, st, wt, rc.max_iters, rc.timing, &hp, &us);
+    const LdsJob job{dg.ro, dg.adj, dist, dg.n, dg.m, src};
+    gr_status s = lds_launch_wait(&job, 1, st, wt, rc.max_iters, rc.timing, &hp, &us);
     if (s != GR_OK) return s;
     if (stats) {
         gr_sssp_stats local{};
@@ -979,15 +978,23 @@ static gr_status run_lds(const gr_graph *g, int32_t src, uint32_t *dist, hipStre
     return GR_OK;
 }
 
-// Batched queries on a graph whose default is the single-workgroup loop: one
-// workgroup per source, all in one launch (no shared work between sources:
-// each workgroup holds its own copy of the graph in its compute unit's LDS).
+// Batched queries on graphs whose default is the single-workgroup loop: one
+// workgroup per query, all in one launch (no shared work between queries:
+// each workgroup holds its own copy of its graph in its compute unit's LDS).
+// rows[i] receives query i's distances; iterations (optional) its rounds.
 static_assert(kLdsMaxBatch >= kBatchLanes, "a batch fits one launch of the single-workgroup loop");
-static gr_status run_lds_batch(const gr_graph *g, const int32_t *srcs, int32_t k, uint32_t *dist, hipStream_t st,
-                               gr_multi_stats *stats) {
+static gr_status run_lds_batch(const gr_graph *const *graphs, const int32_t *srcs, int32_t k, uint32_t *const *rows,
+                               hipStream_t st, gr_multi_stats *stats, int32_t *iterations) {
+    LdsJob jobs[kLdsMaxBatch];
+    int64_t max_rounds = 1;
+    for (int32_t i = 0; i < k; ++i) {
+        const DevGraph &dg = graphs[i]->plain;
+        jobs[i] = LdsJob{dg.ro, dg.adj, rows[i], dg.n, dg.m, srcs[i]};
+        max_rounds = std::max<int64_t>(max_rounds, (int64_t)dg.n + 1);
+    }
     unsigned long long *hp = nullptr;
     float us = 0.f;
-    gr_status s = lds_launch_wait(g, srcs, k, dist, st, g->plain.wt, (int64_t)g->plain.n + 1, false, &hp, &us);
+    gr_status s = lds_launch_wait(jobs, k, st, GR_W_U32, max_rounds, false, &hp, &us);
     if (s != GR_OK) return s;
     if (stats) {
         gr_multi_stats local{};
@@ -1001,6 +1008,9 @@ static gr_status run_lds_batch(const gr_graph *g, const int32_t *srcs, int32_t k
         local.source_relaxations = local.edges_pushed;
         *stats = local;
     }
+    if (iterations)
+        for (int32_t b = 0; b < k; ++b)
+            iterations[b] = (int32_t)std::min<unsigned long long>(hp[b * kLdsStatWords], INT32_MAX);
     return GR_OK;
 }
 
@@ -1520,6 +1530,14 @@ extern "C" gr_status gr_sssp_multi(const gr_graph *const *graphs, const int32_t 
         return fail(GR_ERR_INVALID_ARG, "the queries' graphs hold %lld arcs together, more than 2^31 - 1",
                     (long long)sum_m);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // every graph's default is the single-workgroup loop: one workgroup per query
+    bool all_lds = k <= kLdsMaxBatch;
+    for (int32_t i = 0; i < k && all_lds; ++i) all_lds = graphs[i]->auto_loop == GR_LOOP_LDS;
+    if (all_lds) {
+        std::vector<uint32_t *> rows((size_t)k);
+        for (int32_t i = 0; i < k; ++i) rows[i] = static_cast<uint32_t *>(dist_out[i]);
+        return run_lds_batch(graphs, srcs, k, rows.data(), st, stats, iterations);
+    }
     MqSession ses;
     MqMode mode;
     for (int32_t i = 0; i < k; ++i) mode.local_hops = std::max(mode.local_hops, graphs[i]->auto_local_hops);
@@ -1664,9 +1682,12 @@ extern "C" gr_status gr_sssp_batch_ex(const gr_graph *g, const int32_t *srcs, in
     if (s != GR_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (k == 1) return run_single_auto(g, srcs[0], static_cast<uint32_t *>(dist_out), st, stats);
-    if (g->auto_loop == GR_LOOP_LDS) return run_lds_batch(g, srcs, k, static_cast<uint32_t *>(dist_out), st, stats);
     std::vector<uint32_t *> rows((size_t)k);
     for (int32_t i = 0; i < k; ++i) rows[i] = static_cast<uint32_t *>(dist_out) + (size_t)i * g->plain.n;
+    if (g->auto_loop == GR_LOOP_LDS) {
+        std::vector<const gr_graph *> gs((size_t)k, g);
+        return run_lds_batch(gs.data(), srcs, k, rows.data(), st, stats, nullptr);
+    }
     return run_batch_dev(g, srcs, k, rows.data(), st, stats);
 }
 

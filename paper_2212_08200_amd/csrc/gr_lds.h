@@ -25,16 +25,24 @@ inline bool lds_fits(int32_t n, int32_t m) { return n >= 1 && n <= kLdsMaxN && l
 // 2 round cap reached), arcs relaxed, vertex expansions.
 constexpr int kLdsStatWords = 4;
 
-// One workgroup per source, up to kLdsMaxBatch sources in one launch.
+// One workgroup per query, up to kLdsMaxBatch queries in one launch.
 constexpr int kLdsMaxBatch = 64;
 
-// wt: 0 uint32 weights (every weight below 2^16), 2 unit steps.  The graph's
-// CSR (ro, adj as (head, weight bits)) stays in device memory; it is copied
-// into LDS by each workgroup.  srcs: host array of k sources, 1 <= k <=
-// kLdsMaxBatch; workgroup b writes row b of dist_out (k x n, row-major) and
-// stat[4 b .. 4 b + 3] (device memory or pinned host memory: written with
-// system-scope stores).
-hipError_t launch_lds(int32_t n, int32_t m, int wt, const int32_t *ro, const uint2 *adj, const int32_t *srcs,
-                      int32_t k, uint32_t *dist_out, int64_t max_rounds, unsigned long long *stat, hipStream_t st);
+// A query: its graph's CSR in device memory (ro[n + 1], adj[m] as (head,
+// weight bits)), its source and its output row dist[n] (device memory).
+struct LdsJob {
+    const int32_t *ro;
+    const uint2 *adj;
+    uint32_t *dist;
+    int32_t n, m, src;
+};
+
+// wt: 0 uint32 weights (every weight below 2^16), 2 unit steps, for every
+// job.  jobs: host array of k jobs, 1 <= k <= kLdsMaxBatch, each graph
+// fitting (lds_fits); workgroup b copies job b's graph into its LDS, writes
+// its dist row and stat[4 b .. 4 b + 3] (device memory or pinned host
+// memory: written with system-scope stores).
+hipError_t launch_lds(const LdsJob *jobs, int32_t k, int wt, int64_t max_rounds, unsigned long long *stat,
+                      hipStream_t st);
 
 }  // namespace gr

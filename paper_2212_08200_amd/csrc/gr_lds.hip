@@ -37,13 +37,9 @@ constexpr int kLdsThreads = 1024;
 constexpr int kCopy = 8;  // loads in flight per thread while copying the graph
 
 struct LdsArgs {
-    int32_t n, m;
     int64_t max_rounds;
-    const int32_t *ro;
-    const uint2 *adj;
-    uint32_t *dist;             // k x n
-    unsigned long long *stat;   // k x kLdsStatWords
-    int32_t src[kLdsMaxBatch];  // workgroup b runs src[b]
+    unsigned long long *stat;    // k x kLdsStatWords
+    LdsJob job[kLdsMaxBatch];    // workgroup b runs job[b]
 };
 
 // WT: 0 uint32 weights, 2 unit steps; LG: log2 of the lanes per vertex.
@@ -53,9 +49,11 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     __shared__ int32_t sCnt[3];
     __shared__ unsigned long long sArcs, sExp;
     const int t = threadIdx.x;
-    const int32_t n = a.n, m = a.m;
-    const int32_t src = a.src[blockIdx.x];
-    uint32_t *const dist = a.dist + (size_t)blockIdx.x * (size_t)n;
+    const LdsJob &job = a.job[blockIdx.x];
+    const int32_t n = job.n, m = job.m, src = job.src;
+    const int32_t *const ro = job.ro;
+    const uint2 *const adj = job.adj;
+    uint32_t *const dist = job.dist;
     unsigned long long *const stat = a.stat + (size_t)blockIdx.x * kLdsStatWords;
     uint32_t *sW = sMem;  // dist << 1 | free bit
     int32_t *sRo = reinterpret_cast<int32_t *>(sMem + n);
@@ -69,7 +67,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     for (int32_t v0 = t; v0 <= n; v0 += kLdsThreads * kCopy) {
         int32_t x[kCopy];
 #pragma unroll
-        for (int k = 0; k < kCopy; ++k) x[k] = a.ro[min(v0 + k * kLdsThreads, n)];
+        for (int k = 0; k < kCopy; ++k) x[k] = ro[min(v0 + k * kLdsThreads, n)];
 #pragma unroll
         for (int k = 0; k < kCopy; ++k)
             if (v0 + k * kLdsThreads <= n) sRo[v0 + k * kLdsThreads] = x[k];
@@ -77,7 +75,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     for (int32_t e0 = t; e0 < m; e0 += kLdsThreads * kCopy) {
         uint2 x[kCopy];
 #pragma unroll
-        for (int k = 0; k < kCopy; ++k) x[k] = a.adj[min(e0 + k * kLdsThreads, m - 1)];
+        for (int k = 0; k < kCopy; ++k) x[k] = adj[min(e0 + k * kLdsThreads, m - 1)];
 #pragma unroll
         for (int k = 0; k < kCopy; ++k)
             if (e0 + k * kLdsThreads < m) sArc[e0 + k * kLdsThreads] = WT == 2 ? x[k].x : (x[k].x << 16) | x[k].y;
@@ -158,18 +156,21 @@ int64_t lds_words(int32_t n, int32_t m) {
     return 2 * (int64_t)n + 1 + m + (n + 1) / 2 * 2;
 }
 
-hipError_t launch_lds(int32_t n, int32_t m, int wt, const int32_t *ro, const uint2 *adj, const int32_t *srcs,
-                      int32_t k, uint32_t *dist_out, int64_t max_rounds, unsigned long long *stat, hipStream_t st) {
-    if (!lds_fits(n, m) || wt == 1 || !srcs || k < 1 || k > kLdsMaxBatch) return hipErrorInvalidValue;
-    LdsArgs a{n, m, max_rounds, ro, adj, dist_out, stat, {}};
-    for (int32_t b = 0; b < k; ++b) {
-        if (srcs[b] < 0 || srcs[b] >= n) return hipErrorInvalidValue;
-        a.src[b] = srcs[b];
-    }
+hipError_t launch_lds(const LdsJob *jobs, int32_t k, int wt, int64_t max_rounds, unsigned long long *stat,
+                      hipStream_t st) {
+    if (wt == 1 || !jobs || k < 1 || k > kLdsMaxBatch) return hipErrorInvalidValue;
+    LdsArgs a{max_rounds, stat, {}};
     // lanes per expanded vertex: the average degree rounded up to a power of
-    // two, at most 16
+    // two, at most 16 (the largest over the jobs: more lanes than a vertex
+    // has arcs only idle)
     int32_t lg = 0;
-    while (lg < 4 && ((int64_t)n << lg) < m) ++lg;
+    for (int32_t b = 0; b < k; ++b) {
+        const LdsJob &j = jobs[b];
+        if (!lds_fits(j.n, j.m) || j.src < 0 || j.src >= j.n || !j.ro || !j.dist || (j.m > 0 && !j.adj))
+            return hipErrorInvalidValue;
+        a.job[b] = j;
+        while (lg < 4 && ((int64_t)j.n << lg) < j.m) ++lg;
+    }
     const dim3 grid((unsigned)k), block(kLdsThreads);
     if (wt == 2) {
         switch (lg) {

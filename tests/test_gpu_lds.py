@@ -185,3 +185,30 @@ def test_lds_batch_one_workgroup_per_source():
                 assert st["source_relaxations"] == st["edges_pushed"] > 0
         finally:
             G.close()
+
+
+def test_lds_multi_graph_batch():
+    # gr_sssp_multi over graphs that all default to this loop (different sizes,
+    # weights and group sizes): one workgroup per query; every result
+    # certified, iterations reported per query
+    gs = [gg.workload("grid64")[0], gg.grid(60, 5, whi=1000, shortcuts=4, sseed=9, name="road60"),
+          gg.grid(20, 3, name="grid20"), gg.from_arcs(1, [], name="one"),
+          gg.uniform(2000, 8000, 11, 12, symmetric=True, name="uni2000")]
+    Gs = [gr.Graph.from_csr(g) for g in gs]
+    try:
+        idx = [i % len(gs) for i in range(23)]
+        srcs = [int(gg.pick_sources(gs[i], 200 + j, 1)[0]) if gs[i].n > 1 else 0 for j, i in enumerate(idx)]
+        outs = [torch.full((gs[i].n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda") for i in idx]
+        say("lds multi k=%d" % len(idx))
+        st = gr.gr_sssp_multi([Gs[i].handle for i in idx], srcs, outs)
+        torch.cuda.synchronize()
+        iters = st["iterations"]
+        for j, i in enumerate(idx):
+            d = outs[j].cpu().numpy().view(np.uint32)
+            np.testing.assert_array_equal(d, oracle.dijkstra(gs[i], srcs[j]), err_msg="%s src=%d" % (gs[i].name, srcs[j]))
+            assert iters[j] >= 1
+        assert st["replays"] == 0 and st["rounds"] == max(iters)
+    finally:
+        for G in Gs:
+            G.close()
+
