@@ -225,7 +225,7 @@ def main():
     roof = None
     if launches and push_us > 0:
         achieved = alg_bytes / (push_us * 1e-6) / 1e9
-        kern = {2: "k_persistent", 3: "k_step", 4: "k_async"}.get(stats_last["loop"], "k_push")
+        kern = {2: "k_persistent", 3: "k_step", 4: "k_async", 5: "k_lds"}.get(stats_last["loop"], "k_push")
         loop_name = {1: "host", 2: "persistent", 3: "queued", 4: "async", 5: "lds"}.get(stats_last["loop"], "?")
         layout_name = {1: "plain", 2: "partitioned"}.get(stats_last["layout"], "?")
         relax_name = {1: "dist", 2: "bound"}.get(stats_last["relax_filter"], "?")
@@ -239,6 +239,8 @@ def main():
                 # whole query: algorithmic bytes of all rounds over the timed wall clock
                 "query_gbs": round(q_bytes / t_total / 1e9, 1),
                 "query_frac": round(q_bytes / t_total / 1e9 / HBM_PEAK_GBS, 4)}
+        if kern == "k_lds":
+            roof["limiter"] = "LDS latency (one workgroup, one round per barrier)"
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -381,11 +383,16 @@ def kernel_roofline(stats_list, wall_s, q_bytes):
         return None
     achieved = alg / (push_us * 1e-6) / 1e9
     kern = {2: "k_persistent", 3: "k_step", 4: "k_async", 5: "k_lds"}.get(last["loop"], "k_push")
-    return {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    roof = {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": int(alg / launches),
             "avg_launch_us": round(push_us / launches, 2), "launches": launches,
             "query_gbs": round(q_bytes / wall_s / 1e9, 1),
             "query_frac": round(q_bytes / wall_s / 1e9 / HBM_PEAK_GBS, 4)}
+    if kern == "k_lds":
+        # the whole query runs in one workgroup's LDS: its limit is the chain of
+        # dependent LDS accesses per round, not HBM; the HBM figure is context
+        roof["limiter"] = "LDS latency (one workgroup, one round per barrier)"
+    return roof
 
 
 def measure_config(name, steps, torch, np, gr, gg, dev):
