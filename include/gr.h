@@ -428,7 +428,11 @@ typedef struct {
  * of frontier marks + 26 bytes per vertex of the executor's union queues) must
  * fit hbm_budget_bytes next to every query already admitted.  A query is
  * complete when a chunk ends with its frontier empty; its distances are then
- * final in its dist_out.  cfg may be NULL. */
+ * final in its dist_out.  Queries on graphs whose AUTO loop is the single-
+ * workgroup loop (GR_LOOP_LDS) take no slot: an executor takes up to 64 of
+ * them from anywhere in the FIFO (they hold nothing the head waits for) and
+ * runs them as one launch, one workgroup per query, on a stream of its own;
+ * batch_size is then that launch's query count.  cfg may be NULL. */
 gr_status gr_server_create(gr_server **out, size_t hbm_budget_bytes, const gr_server_config *cfg);
 /* Registers a graph (not copied; it must outlive the server). */
 gr_status gr_server_add_graph(gr_server *s, const gr_graph *g, int32_t *graph_id);

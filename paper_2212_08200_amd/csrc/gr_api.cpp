@@ -1748,8 +1748,12 @@ struct LiveQuery {
 
 static void server_worker(gr_server *s, int exec_id) {
     (void)hipSetDevice(s->device);
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr, st_direct = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    // queries on graphs whose default is the single-workgroup loop run outside
+    // the session: one workgroup per query, one launch per batch, on a stream
+    // of their own (without it they join the session like the others)
+    if (hipStreamCreateWithFlags(&st_direct, hipStreamNonBlocking) != hipSuccess) st_direct = nullptr;
     const int nslots = s->cfg.max_batch;
     MqSession ses;
     bool have_ses = false;
@@ -1767,6 +1771,43 @@ static void server_worker(gr_server *s, int exec_id) {
     if (!st) broken = fail(GR_ERR_HIP, "query server: no stream for an executor");
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
+        // 0. direct queries: taken from anywhere in the FIFO, run and completed
+        // here (the session's replays already queued keep the device busy)
+        if (broken == GR_OK && st_direct) {
+            const std::vector<SchedQuery> dq = s->policy->take_direct(kLdsMaxBatch);
+            if (!dq.empty()) {
+                const int64_t t_start = now_ns();
+                for (const SchedQuery &q : dq) {
+                    Ticket &t = s->tickets[q.ticket];
+                    t.state = kRunning;
+                    t.res.t_start_ns = t_start;
+                }
+                lk.unlock();
+                LdsJob jobs[kLdsMaxBatch];
+                int64_t max_rounds = 1;
+                for (size_t b = 0; b < dq.size(); ++b) {
+                    const DevGraph &dg = s->graphs[dq[b].graph]->plain;
+                    jobs[b] = LdsJob{dg.ro, dg.adj, static_cast<uint32_t *>(dq[b].dst), dg.n, dg.m, dq[b].src};
+                    max_rounds = std::max<int64_t>(max_rounds, (int64_t)dg.n + 1);
+                }
+                unsigned long long *hp = nullptr;
+                float us = 0.f;
+                const gr_status ds =
+                    lds_launch_wait(jobs, (int32_t)dq.size(), st_direct, GR_W_U32, max_rounds, false, &hp, &us);
+                const int64_t t_done = now_ns();
+                lk.lock();
+                for (size_t b = 0; b < dq.size(); ++b) {
+                    Ticket &t = s->tickets[dq[b].ticket];
+                    t.state = kDone;
+                    t.res.status = ds;
+                    t.res.t_done_ns = t_done;
+                    t.res.batch_size = (int32_t)dq.size();
+                    t.res.iterations =
+                        ds == GR_OK ? (int32_t)std::min<unsigned long long>(hp[b * kLdsStatWords], INT32_MAX) : 0;
+                }
+                s->cv.notify_all();
+            }
+        }
         // 1. admissions
         std::vector<SchedQuery> adm;
         if (broken == GR_OK && st) {
@@ -1847,7 +1888,8 @@ static void server_worker(gr_server *s, int exec_id) {
         const bool any_live = nused > 0;
         if (!any_live && outstanding < 0) {
             if (s->stopping && s->policy->pending() == 0) break;
-            s->cv.wait(lk);
+            // direct queries that arrived while the lock was released above
+            if (!(st_direct && s->policy->has_direct())) s->cv.wait(lk);
             continue;
         }
         lk.unlock();
@@ -1931,6 +1973,7 @@ static void server_worker(gr_server *s, int exec_id) {
     if (st) (void)hipStreamSynchronize(st);
     if (have_ses) mq_destroy(&ses);
     if (st) (void)hipStreamDestroy(st);
+    if (st_direct) (void)hipStreamDestroy(st_direct);
     (void)exec_id;
 }
 
@@ -1994,7 +2037,9 @@ extern "C" gr_status gr_serve_submit(gr_server *s, int32_t graph_id, int32_t src
     tk.res.graph_id = graph_id;
     tk.res.src = src;
     tk.res.t_submit_ns = t;
-    s->policy->push(SchedQuery{id, graph_id, src, dist_out, t});
+    // queries on graphs that run the single-workgroup loop by default are
+    // run outside the executors' sessions
+    s->policy->push(SchedQuery{id, graph_id, src, dist_out, t, g->auto_loop == GR_LOOP_LDS});
     s->cv.notify_all();
     *ticket = id;
     return GR_OK;

@@ -68,6 +68,38 @@ int main() {
     a = p.admit(SessionRoom{8, 1000, 1000}, &in_flight);
     CHECK(a.size() == 2 && a[0].ticket == 20 && a[1].ticket == 21);
 
+    // direct queries leave the FIFO wherever they stand, in arrival order, up
+    // to the maximum, and charge nothing; the rest keep their order
+    in_flight = 0;
+    auto qd = [](uint64_t t, int32_t g, bool d) {
+        SchedQuery x = q(t, g);
+        x.direct = d;
+        return x;
+    };
+    CHECK(!p.has_direct());
+    p.push(qd(30, 1, false));
+    p.push(qd(31, 0, true));
+    p.push(qd(32, 0, false));
+    p.push(qd(33, 0, true));
+    p.push(qd(34, 0, true));
+    CHECK(p.has_direct());
+    a = p.take_direct(2);
+    CHECK(a.size() == 2 && a[0].ticket == 31 && a[1].ticket == 33 && in_flight == 0);
+    CHECK(p.pending() == 3 && p.head()->ticket == 30);
+    a = p.take_direct(64);
+    CHECK(a.size() == 1 && a[0].ticket == 34 && p.pending() == 2);
+    CHECK(p.take_direct(64).empty() && !p.has_direct());
+    a = p.admit(SessionRoom{8, 1000, 1000}, &in_flight);
+    CHECK(a.size() == 2 && a[0].ticket == 30 && a[1].ticket == 32);
+    // a direct query admitted into a session (from the head) is no longer counted
+    in_flight = 0;
+    p.push(qd(40, 0, true));
+    a = p.admit(SessionRoom{8, 1000, 1000}, &in_flight);
+    CHECK(a.size() == 1 && a[0].ticket == 40 && !p.has_direct());
+    // and take_all forgets them too
+    p.push(qd(41, 0, true));
+    CHECK(p.take_all().size() == 1 && !p.has_direct());
+
     std::printf("ok\n");
     return 0;
 }

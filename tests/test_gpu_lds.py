@@ -5,8 +5,10 @@ oracle element by element (tolerance 0: the fixed point is unique), for SSSP
 and for BFS, on the small-mesh configuration, on skewed and directed graphs,
 on the degenerate cases (one vertex, isolated source, unreachable parts), at
 the 16-bit weight limit and at the LDS size limit, for the argument errors
-and the round cap, and for batches (one workgroup per source)."""
+and the round cap, and for batches and served queries (one workgroup per
+query)."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -208,6 +210,67 @@ def test_lds_multi_graph_batch():
             np.testing.assert_array_equal(d, oracle.dijkstra(gs[i], srcs[j]), err_msg="%s src=%d" % (gs[i].name, srcs[j]))
             assert iters[j] >= 1
         assert st["replays"] == 0 and st["rounds"] == max(iters)
+    finally:
+        for G in Gs:
+            G.close()
+
+
+def poll_all(server, tickets, timeout=60.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                r = gr.gr_serve_poll(server, t)
+                if r is not None:
+                    done[t] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError("%d of %d queries pending" % (len(tickets) - len(done), len(tickets)))
+        time.sleep(0.0005)
+    return done
+
+
+def test_lds_served_queries_beside_the_session():
+    # a server holding graphs that fit one workgroup's LDS (run directly, one
+    # workgroup per query) and graphs that do not (the multi-query session):
+    # every result equals the oracle's, and the direct ones were batched
+    graphs = [gg.workload("grid64")[0], gg.grid(60, 5, whi=1000, shortcuts=4, sseed=9, name="road60"),
+              gg.rmat(12, 16, gseed=7, pseed=8, wseed=9, name="rmat12"), gg.grid(96, 5, name="grid96")]
+    Gs = [gr.Graph.from_csr(g) for g in graphs]
+    server = gr.gr_server_create(4 << 30, max_batch=16, num_streams=2, max_wait_us=300)
+    late, outs = [], []
+    try:
+        gids = [gr.gr_server_add_graph(server, G.handle) for G in Gs]
+        rng = np.random.default_rng(17)
+        reqs = []
+        for i in range(160):
+            gi = int(rng.integers(0, len(graphs)))
+            s = int(gg.pick_sources(graphs[gi], 500 + i, 1)[0])
+            reqs.append((gi, s, torch.full((graphs[gi].n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")))
+        say("lds server: 160 queries over 4 graphs (2 direct)")
+        tickets = [gr.gr_serve_submit(server, gids[gi], s, out) for gi, s, out in reqs]
+        res = poll_all(server, tickets)
+        direct_sizes = []
+        for t, (gi, s, out) in zip(tickets, reqs):
+            r = res[t]
+            assert r["status"] == gr.GR_OK and r["src"] == s and r["iterations"] >= 1
+            assert r["t_submit_ns"] <= r["t_start_ns"] <= r["t_done_ns"]
+            got = out.cpu().numpy().view(np.uint32)
+            np.testing.assert_array_equal(got, oracle.dijkstra(graphs[gi], s), err_msg="%s src=%d" % (graphs[gi].name, s))
+            if gi < 2:
+                direct_sizes.append(r["batch_size"])
+        assert direct_sizes and max(direct_sizes) > 1, "no direct batch held two queries"
+        # queries still queued when the server is destroyed are run first
+        late += [(0, 5), (1, 7), (2, 3), (0, 9)]
+        outs += [torch.full((graphs[gi].n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda") for gi, _ in late]
+        for (gi, s), out in zip(late, outs):
+            gr.gr_serve_submit(server, gids[gi], s, out)
+    finally:
+        gr.gr_server_destroy(server)
+    try:
+        torch.cuda.synchronize()
+        for (gi, s), out in zip(late, outs):
+            np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), oracle.dijkstra(graphs[gi], s))
     finally:
         for G in Gs:
             G.close()
