@@ -176,6 +176,10 @@ struct gr_graph {
     // every weight is below 2^16 (lds_w16: weighted queries can pack arcs)
     bool lds_fit = false;
     bool lds_w16 = false;
+    // the arcs padded to 2^ell_lg per vertex (lds_ell_words), for the
+    // single-workgroup loop's padded layout; nullptr when it does not fit
+    uint32_t *d_ell = nullptr;
+    int32_t ell_lg = 0;
     // iterations of the last completed queued-loop query (first chunk size)
     mutable std::atomic<int32_t> last_iters{0};
     double locality = 1.0;  // fraction of arcs with |u - v| < locality_span(n)
@@ -208,6 +212,7 @@ static void graph_free(gr_graph *g) {
     if (g->d_adj_in && g->d_adj_in != g->d_adj) (void)hipFree(g->d_adj_in);
     if (g->d_ro) (void)hipFree(g->d_ro);
     if (g->d_adj) (void)hipFree(g->d_adj);
+    if (g->d_ell) (void)hipFree(g->d_ell);
     if (g->d_pro) (void)hipFree(g->d_pro);
     if (g->d_padj) (void)hipFree(g->d_padj);
     for (int i = 0; i < 2; ++i) {
@@ -369,6 +374,21 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
         uint32_t wmax = 0;
         for (int32_t e = 0; e < m; ++e) wmax = std::max(wmax, h[(size_t)e].y);
         g->lds_w16 = wmax < 65536u;
+        // padded layout: every vertex's arcs in 2^lg slots (lg from the
+        // maximum degree), so a lane finds its arc without the row offsets
+        int32_t lg = 0;
+        while (lg < kLdsEllMaxLg && (1 << lg) < g->max_degree) ++lg;
+        if (g->lds_w16 && (1 << lg) >= g->max_degree && lds_ell_fits(n, lg)) {
+            std::vector<uint32_t> ell((size_t)n << lg, kLdsNoArc);
+            for (int32_t v = 0; v < n; ++v)
+                for (int32_t e = g->h_ro[v]; e < g->h_ro[v + 1]; ++e)
+                    ell[((size_t)v << lg) + (size_t)(e - g->h_ro[v])] = (h[(size_t)e].x << 16) | h[(size_t)e].y;
+            BUILD_TRY(hipMalloc(&g->d_ell, sizeof(uint32_t) * ell.size()), "hipMalloc(padded arcs)");
+            BUILD_TRY(hipMemcpy(g->d_ell, ell.data(), sizeof(uint32_t) * ell.size(), hipMemcpyHostToDevice),
+                      "copy padded arcs");
+            g->ell_lg = lg;
+            g->dev_bytes += sizeof(uint32_t) * ell.size();
+        }
     }
     if (g->lds_fit && g->lds_w16 && g->max_degree <= kSmallMaxDegree) g->auto_loop = GR_LOOP_LDS;
     // Large skewed graphs: few, heavy rounds, where the host-driven loop's
@@ -960,7 +980,7 @@ static gr_status run_lds(const gr_graph *g, int32_t src, uint32_t *dist, hipStre
                                         "below 65,536 only");
     unsigned long long *hp = nullptr;
     float us = 0.f;
-    const LdsJob job{dg.ro, dg.adj, dist, dg.n, dg.m, src};
+    const LdsJob job{dg.ro, dg.adj, g->d_ell, dist, dg.n, dg.m, src, g->ell_lg};
     gr_status s = lds_launch_wait(&job, 1, st, wt, rc.max_iters, rc.timing, &hp, &us);
     if (s != GR_OK) return s;
     if (stats) {
@@ -989,7 +1009,7 @@ static gr_status run_lds_batch(const gr_graph *const *graphs, const int32_t *src
     int64_t max_rounds = 1;
     for (int32_t i = 0; i < k; ++i) {
         const DevGraph &dg = graphs[i]->plain;
-        jobs[i] = LdsJob{dg.ro, dg.adj, rows[i], dg.n, dg.m, srcs[i]};
+        jobs[i] = LdsJob{dg.ro, dg.adj, graphs[i]->d_ell, rows[i], dg.n, dg.m, srcs[i], graphs[i]->ell_lg};
         max_rounds = std::max<int64_t>(max_rounds, (int64_t)dg.n + 1);
     }
     unsigned long long *hp = nullptr;
@@ -1786,8 +1806,10 @@ static void server_worker(gr_server *s, int exec_id) {
                 LdsJob jobs[kLdsMaxBatch];
                 int64_t max_rounds = 1;
                 for (size_t b = 0; b < dq.size(); ++b) {
-                    const DevGraph &dg = s->graphs[dq[b].graph]->plain;
-                    jobs[b] = LdsJob{dg.ro, dg.adj, static_cast<uint32_t *>(dq[b].dst), dg.n, dg.m, dq[b].src};
+                    const gr_graph *g = s->graphs[dq[b].graph];
+                    const DevGraph &dg = g->plain;
+                    jobs[b] = LdsJob{dg.ro,  dg.adj, g->d_ell, static_cast<uint32_t *>(dq[b].dst),
+                                     dg.n,   dg.m,   dq[b].src, g->ell_lg};
                     max_rounds = std::max<int64_t>(max_rounds, (int64_t)dg.n + 1);
                 }
                 unsigned long long *hp = nullptr;

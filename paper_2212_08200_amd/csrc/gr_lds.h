@@ -30,12 +30,25 @@ constexpr int kLdsMaxBatch = 64;
 
 // A query: its graph's CSR in device memory (ro[n + 1], adj[m] as (head,
 // weight bits)), its source and its output row dist[n] (device memory).
+// ell (optional): the same arcs padded to 2^ell_lg slots per vertex, packed
+// head << 16 | weight, empty slots kLdsNoArc (see lds_ell_fits); when every
+// job of a launch has one with the same ell_lg, the launch uses it.
 struct LdsJob {
     const int32_t *ro;
     const uint2 *adj;
+    const uint32_t *ell;
     uint32_t *dist;
-    int32_t n, m, src;
+    int32_t n, m, src, ell_lg;
 };
+
+// Padded layout in LDS: distances (n), the padded arcs (n << lg), two lists
+// (n 16-bit ids each).  At most 16 slots per vertex.
+constexpr uint32_t kLdsNoArc = 0xFFFFFFFFu;
+constexpr int kLdsEllMaxLg = 4;
+inline int64_t lds_ell_words(int32_t n, int lg) { return (int64_t)n + ((int64_t)n << lg) + (n + 1) / 2 * 2; }
+inline bool lds_ell_fits(int32_t n, int lg) {
+    return n >= 1 && n <= kLdsMaxN && lg >= 0 && lg <= kLdsEllMaxLg && lds_ell_words(n, lg) <= kLdsWords;
+}
 
 // wt: 0 uint32 weights (every weight below 2^16), 2 unit steps, for every
 // job.  jobs: host array of k jobs, 1 <= k <= kLdsMaxBatch, each graph

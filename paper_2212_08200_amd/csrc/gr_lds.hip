@@ -42,8 +42,9 @@ struct LdsArgs {
     LdsJob job[kLdsMaxBatch];    // workgroup b runs job[b]
 };
 
-// WT: 0 uint32 weights, 2 unit steps; LG: log2 of the lanes per vertex.
-template <int WT, int LG>
+// WT: 0 uint32 weights, 2 unit steps; LG: log2 of the lanes per vertex;
+// ELL: the arcs come padded to 2^LG slots per vertex (no row offsets).
+template <int WT, int LG, bool ELL>
 __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     __shared__ uint32_t sMem[kLdsWords];
     __shared__ int32_t sCnt[3];
@@ -56,29 +57,42 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     uint32_t *const dist = job.dist;
     unsigned long long *const stat = a.stat + (size_t)blockIdx.x * kLdsStatWords;
     uint32_t *sW = sMem;  // dist << 1 | free bit
-    int32_t *sRo = reinterpret_cast<int32_t *>(sMem + n);
-    uint32_t *sArc = sMem + 2 * n + 1;
+    int32_t *sRo = reinterpret_cast<int32_t *>(sMem + n);  // row offsets (CSR layout only)
+    uint32_t *sArc = ELL ? sMem + n : sMem + 2 * n + 1;
+    const int32_t arc_words = ELL ? (n << LG) : m;
     // the two lists, as one array indexed from list 0 (an offset, not a
     // pointer chosen at run time, keeps the accesses LDS instructions)
-    uint16_t *sL = reinterpret_cast<uint16_t *>(sArc + m);
+    uint16_t *sL = reinterpret_cast<uint16_t *>(sArc + arc_words);
     for (int32_t v = t; v < n; v += kLdsThreads) sW[v] = kInfU32;  // unreached and free
     // the copies issue kCopy loads before the first LDS store (indexes past
     // the end read the last element again)
-    for (int32_t v0 = t; v0 <= n; v0 += kLdsThreads * kCopy) {
-        int32_t x[kCopy];
+    if constexpr (ELL) {
+        const uint32_t *const ell = job.ell;
+        for (int32_t e0 = t; e0 < arc_words; e0 += kLdsThreads * kCopy) {
+            uint32_t x[kCopy];
 #pragma unroll
-        for (int k = 0; k < kCopy; ++k) x[k] = ro[min(v0 + k * kLdsThreads, n)];
+            for (int k = 0; k < kCopy; ++k) x[k] = ell[min(e0 + k * kLdsThreads, arc_words - 1)];
 #pragma unroll
-        for (int k = 0; k < kCopy; ++k)
-            if (v0 + k * kLdsThreads <= n) sRo[v0 + k * kLdsThreads] = x[k];
-    }
-    for (int32_t e0 = t; e0 < m; e0 += kLdsThreads * kCopy) {
-        uint2 x[kCopy];
+            for (int k = 0; k < kCopy; ++k)
+                if (e0 + k * kLdsThreads < arc_words) sArc[e0 + k * kLdsThreads] = x[k];
+        }
+    } else {
+        for (int32_t v0 = t; v0 <= n; v0 += kLdsThreads * kCopy) {
+            int32_t x[kCopy];
 #pragma unroll
-        for (int k = 0; k < kCopy; ++k) x[k] = adj[min(e0 + k * kLdsThreads, m - 1)];
+            for (int k = 0; k < kCopy; ++k) x[k] = ro[min(v0 + k * kLdsThreads, n)];
 #pragma unroll
-        for (int k = 0; k < kCopy; ++k)
-            if (e0 + k * kLdsThreads < m) sArc[e0 + k * kLdsThreads] = WT == 2 ? x[k].x : (x[k].x << 16) | x[k].y;
+            for (int k = 0; k < kCopy; ++k)
+                if (v0 + k * kLdsThreads <= n) sRo[v0 + k * kLdsThreads] = x[k];
+        }
+        for (int32_t e0 = t; e0 < m; e0 += kLdsThreads * kCopy) {
+            uint2 x[kCopy];
+#pragma unroll
+            for (int k = 0; k < kCopy; ++k) x[k] = adj[min(e0 + k * kLdsThreads, m - 1)];
+#pragma unroll
+            for (int k = 0; k < kCopy; ++k)
+                if (e0 + k * kLdsThreads < m) sArc[e0 + k * kLdsThreads] = WT == 2 ? x[k].x : (x[k].x << 16) | x[k].y;
+        }
     }
     if (t == 0) {
         sCnt[0] = 1;
@@ -112,21 +126,42 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
         // e0 + s, e0 + s + G, ...
         for (int32_t i = t; i < (cnt << lg); i += kLdsThreads) {
             const uint32_t u = sL[lc + (i >> lg)];
-            const int32_t e0 = sRo[u], e1 = sRo[u + 1];
+            // CSR: the row's bounds; padded: the lane's slot
+            int32_t e0 = 0, e1 = 0;
+            uint32_t xe = kLdsNoArc;
+            if constexpr (ELL) xe = sArc[(u << lg) + slot];
+            else {
+                e0 = sRo[u];
+                e1 = sRo[u + 1];
+            }
             uint32_t du = 0u;
             if (slot == 0) du = __hip_atomic_fetch_or(&sW[u], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 1;
             // broadcast from the group's first lane (a DPP move within quads
             // measured no faster than this permute for groups of 2 and 4)
             if constexpr (LG > 0) du = (uint32_t)__builtin_amdgcn_ds_bpermute(lead << 2, (int)du);
-            expanded += slot == 0 && e1 > e0 ? 1u : 0u;
-            for (int32_t e = e0 + slot; e < e1; e += 1 << lg) {
-                ++arcs;
-                const uint32_t x = sArc[e];
-                const uint32_t v = WT == 2 ? x : x >> 16;
-                const uint32_t nw = (du + (WT == 2 ? 1u : (x & 0xFFFFu))) << 1;  // queued
-                const uint32_t old = __hip_atomic_fetch_min(&sW[v], nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                // the atomic took v from free to queued: v goes on list r + 1
-                if (nw < old && (old & 1u)) sL[ln + atomicAdd(&sCnt[kn], 1)] = (uint16_t)v;
+            if constexpr (ELL) {
+                // slots fill from the first: slot 0 holds an arc iff u has one
+                expanded += slot == 0 && xe != kLdsNoArc ? 1u : 0u;
+                if (xe != kLdsNoArc) {
+                    ++arcs;
+                    const uint32_t v = xe >> 16;
+                    const uint32_t nw = (du + (WT == 2 ? 1u : (xe & 0xFFFFu))) << 1;  // queued
+                    const uint32_t old =
+                        __hip_atomic_fetch_min(&sW[v], nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (nw < old && (old & 1u)) sL[ln + atomicAdd(&sCnt[kn], 1)] = (uint16_t)v;
+                }
+            } else {
+                expanded += slot == 0 && e1 > e0 ? 1u : 0u;
+                for (int32_t e = e0 + slot; e < e1; e += 1 << lg) {
+                    ++arcs;
+                    const uint32_t x = sArc[e];
+                    const uint32_t v = WT == 2 ? x : x >> 16;
+                    const uint32_t nw = (du + (WT == 2 ? 1u : (x & 0xFFFFu))) << 1;  // queued
+                    const uint32_t old =
+                        __hip_atomic_fetch_min(&sW[v], nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    // the atomic took v from free to queued: v goes on list r + 1
+                    if (nw < old && (old & 1u)) sL[ln + atomicAdd(&sCnt[kn], 1)] = (uint16_t)v;
+                }
             }
         }
         __syncthreads();
@@ -147,6 +182,17 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
         __hip_atomic_store(stat + 1, sCnt[kr] == 0 ? 1ull : 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(stat + 2, sArcs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(stat + 3, sExp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+template <int WT, bool ELL>
+void launch_lg(int lg, dim3 grid, dim3 block, hipStream_t st, const LdsArgs &a) {
+    switch (lg) {
+        case 0: hipLaunchKernelGGL((k_lds<WT, 0, ELL>), grid, block, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_lds<WT, 1, ELL>), grid, block, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_lds<WT, 2, ELL>), grid, block, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_lds<WT, 3, ELL>), grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_lds<WT, 4, ELL>), grid, block, 0, st, a); break;
     }
 }
 
@@ -171,23 +217,17 @@ hipError_t launch_lds(const LdsJob *jobs, int32_t k, int wt, int64_t max_rounds,
         a.job[b] = j;
         while (lg < 4 && ((int64_t)j.n << lg) < j.m) ++lg;
     }
+    // the padded layout when every job has it with the same slot count
+    bool ell = true;
+    for (int32_t b = 0; b < k && ell; ++b)
+        ell = jobs[b].ell && jobs[b].ell_lg == jobs[0].ell_lg && lds_ell_fits(jobs[b].n, jobs[b].ell_lg);
     const dim3 grid((unsigned)k), block(kLdsThreads);
-    if (wt == 2) {
-        switch (lg) {
-            case 0: hipLaunchKernelGGL((k_lds<2, 0>), grid, block, 0, st, a); break;
-            case 1: hipLaunchKernelGGL((k_lds<2, 1>), grid, block, 0, st, a); break;
-            case 2: hipLaunchKernelGGL((k_lds<2, 2>), grid, block, 0, st, a); break;
-            case 3: hipLaunchKernelGGL((k_lds<2, 3>), grid, block, 0, st, a); break;
-            default: hipLaunchKernelGGL((k_lds<2, 4>), grid, block, 0, st, a); break;
-        }
+    if (ell) {
+        if (wt == 2) launch_lg<2, true>(jobs[0].ell_lg, grid, block, st, a);
+        else launch_lg<0, true>(jobs[0].ell_lg, grid, block, st, a);
     } else {
-        switch (lg) {
-            case 0: hipLaunchKernelGGL((k_lds<0, 0>), grid, block, 0, st, a); break;
-            case 1: hipLaunchKernelGGL((k_lds<0, 1>), grid, block, 0, st, a); break;
-            case 2: hipLaunchKernelGGL((k_lds<0, 2>), grid, block, 0, st, a); break;
-            case 3: hipLaunchKernelGGL((k_lds<0, 3>), grid, block, 0, st, a); break;
-            default: hipLaunchKernelGGL((k_lds<0, 4>), grid, block, 0, st, a); break;
-        }
+        if (wt == 2) launch_lg<2, false>(lg, grid, block, st, a);
+        else launch_lg<0, false>(lg, grid, block, st, a);
     }
     return hipGetLastError();
 }
