@@ -118,6 +118,10 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
     for (; r < a.max_rounds; ++r) {
         const int32_t lc = (int32_t)(r & 1) * n, ln = n - lc;  // list r, list r + 1
         const int32_t cnt = sCnt[kr];
+        // the thread's first list entry is read beside the count (entries
+        // past the count are stale ids, or uninitialised, and go unused)
+        uint32_t u_first = sL[lc + min(t >> lg, n - 1)];
+        asm volatile("" : "+v"(u_first));  // keeps the read ahead of the test below
         if (cnt == 0) break;  // uniform: read after a barrier
         if (t == 0) sCnt[kz] = 0;
         // G = 2^lg lanes of one wave expand a vertex together: the group's
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds(LdsArgs a) {
         // broadcast across the group, and lane s of the group takes the arcs
         // e0 + s, e0 + s + G, ...
         for (int32_t i = t; i < (cnt << lg); i += kLdsThreads) {
-            const uint32_t u = sL[lc + (i >> lg)];
+            const uint32_t u = i == t ? u_first : sL[lc + (i >> lg)];
             // CSR: the row's bounds; padded: the lane's slot
             int32_t e0 = 0, e1 = 0;
             uint32_t xe = kLdsNoArc;
