@@ -101,6 +101,11 @@ def test_lds_long_path_distances():
     n = 9000
     g = gg.from_arcs(n, [(i, i + 1, 65535) for i in range(n - 1)], name="chain9000")
     check(g, [0, 4321, n - 1])
+    # both directions (groups of 2 lanes): 3,000 vertices, weights U[1, 1000]
+    rng = np.random.default_rng(23)
+    w = rng.integers(1, 1001, size=2999)
+    arcs = [(i, i + 1, int(w[i])) for i in range(2999)] + [(i + 1, i, int(w[i])) for i in range(2999)]
+    check(gg.from_arcs(3000, arcs, name="path3000"), [0, 1500, 2999])
 
 
 def test_lds_size_limit():
