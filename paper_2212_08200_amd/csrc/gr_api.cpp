@@ -1772,8 +1772,9 @@ static void server_worker(gr_server *s, int exec_id) {
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
     // queries on graphs whose default is the single-workgroup loop run outside
     // the session: one workgroup per query, one launch per batch, on a stream
-    // of their own (without it they join the session like the others)
-    if (hipStreamCreateWithFlags(&st_direct, hipStreamNonBlocking) != hipSuccess) st_direct = nullptr;
+    // of their own, created when the first such query waits (streams beyond
+    // the hardware queues share them; without it they join the session)
+    bool direct_tried = false;
     const int nslots = s->cfg.max_batch;
     MqSession ses;
     bool have_ses = false;
@@ -1793,6 +1794,12 @@ static void server_worker(gr_server *s, int exec_id) {
     for (;;) {
         // 0. direct queries: taken from anywhere in the FIFO, run and completed
         // here (the session's replays already queued keep the device busy)
+        if (broken == GR_OK && !direct_tried && s->policy->has_direct()) {
+            direct_tried = true;
+            lk.unlock();
+            if (hipStreamCreateWithFlags(&st_direct, hipStreamNonBlocking) != hipSuccess) st_direct = nullptr;
+            lk.lock();
+        }
         if (broken == GR_OK && st_direct) {
             const std::vector<SchedQuery> dq = s->policy->take_direct(kLdsMaxBatch);
             if (!dq.empty()) {
@@ -1911,7 +1918,7 @@ static void server_worker(gr_server *s, int exec_id) {
         if (!any_live && outstanding < 0) {
             if (s->stopping && s->policy->pending() == 0) break;
             // direct queries that arrived while the lock was released above
-            if (!(st_direct && s->policy->has_direct())) s->cv.wait(lk);
+            if (!((st_direct || !direct_tried) && s->policy->has_direct())) s->cv.wait(lk);
             continue;
         }
         lk.unlock();
