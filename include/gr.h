@@ -185,8 +185,8 @@ typedef enum {
                                65,536; else GR_ERR_INVALID_ARG.  Push only (direction
                                PULL / ALTERNATE and an explicit delta are
                                GR_ERR_INVALID_ARG; layout, filter and relax_filter are
-                               ignored).  AUTO picks it for such graphs of maximum
-                               out-degree <= 64.  stats: iterations = rounds,
+                               ignored).  AUTO picks it for every graph that fits
+                               (for SSSP, with such weights).  stats: iterations = rounds,
                                frontier_sum = vertex expansions, launches = 1. */
 } gr_loop_mode;
 
@@ -321,8 +321,10 @@ gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsrcs, int32_t
  * The default direction policy switches to pull when the frontier's out-edges
  * reach m / 14; pull then scans only the in-arcs of vertices without a depth.
  * opts as for gr_sssp_ex, except: delta must be 0 / GR_DELTA_OFF, the
- * persistent loop is GR_ERR_INVALID_ARG, and AUTO runs the host-driven loop
- * on graphs of maximum out-degree > 64 and the queued loop otherwise.
+ * persistent loop is GR_ERR_INVALID_ARG, and AUTO runs the single-workgroup
+ * loop (push only) on graphs that fit one workgroup's LDS unless pull or
+ * alternation is asked for, else the host-driven loop on graphs of maximum
+ * out-degree > 64 and the queued loop otherwise.
  */
 gr_status gr_bfs(const gr_graph *g, int32_t src, void *depth_out, void *stream);
 gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, void *stream, const gr_sssp_opts *opts,

@@ -390,7 +390,10 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
             g->dev_bytes += sizeof(uint32_t) * ell.size();
         }
     }
-    if (g->lds_fit && g->lds_w16 && g->max_degree <= kSmallMaxDegree) g->auto_loop = GR_LOOP_LDS;
+    // Also on skewed ones: a hub's arcs take many passes of one group of
+    // lanes, but R-MAT graphs of 1-4 K vertices still run 2.3-3.2x faster
+    // than with the queued loop (scale 10 to 12: 0.08-0.14 ms against 0.26-0.32).
+    if (g->lds_fit && g->lds_w16) g->auto_loop = GR_LOOP_LDS;
     // Large skewed graphs: few, heavy rounds, where the host-driven loop's
     // push grid of 16 blocks per CU beats the step kernel (R-MAT 22: 3.48 ms
     // against 3.63); smaller ones keep the queued loop (no host round trip
@@ -1251,13 +1254,19 @@ extern "C" gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, 
         rc.alpha_x16 = (g->pull && g->max_degree > kSmallMaxDegree) ? kBfsAlphaX16 : 0;
     // hop counts leave few redundant relaxations: dist unless asked otherwise
     if (!(opts && opts->relax_filter)) rc.bound = false;
-    // AUTO: the host-driven loop on skewed graphs (few rounds, direction-
-    // optimising: R-MAT 22 1.23 ms against 1.34 queued), the queued loop on
-    // bounded-degree ones (thousands of rounds: grid 2048^2 39 ms against 172)
+    // AUTO: the single-workgroup loop on graphs that fit one workgroup's LDS
+    // (push only: not when pull or alternation is asked for, nor with a
+    // near-far split); else the host-driven loop on skewed graphs (few
+    // rounds, direction-optimising: R-MAT 22 1.23 ms against 1.34 queued),
+    // the queued loop on bounded-degree ones (thousands of rounds: grid
+    // 2048^2 39 ms against 172)
     int loop = rc.loop;
-    // (graphs that fit one workgroup's LDS: the single-workgroup loop)
-    if (loop == GR_LOOP_AUTO)
-        loop = g->max_degree > kSmallMaxDegree ? GR_LOOP_HOST : g->lds_fit ? GR_LOOP_LDS : GR_LOOP_QUEUED;
+    if (loop == GR_LOOP_AUTO) {
+        const bool push_only = !(rc.direction == GR_DIR_PULL || rc.direction == GR_DIR_ALTERNATE || rc.delta);
+        loop = g->lds_fit && push_only                ? GR_LOOP_LDS
+               : g->max_degree > kSmallMaxDegree ? GR_LOOP_HOST
+                                                 : GR_LOOP_QUEUED;
+    }
     if (loop == GR_LOOP_PERSISTENT)
         return fail(GR_ERR_INVALID_ARG, "the device-driven persistent loop runs weighted queries only");
     DevGraph unit = *rc.dg;

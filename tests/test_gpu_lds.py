@@ -62,10 +62,20 @@ def test_lds_road_like_and_random():
     check(g, [int(x) for x in gg.pick_sources(g, 5, 3)])
 
 
-def test_lds_skewed_graph_explicit():
-    # hubs: a group of 16 lanes expands a hub's arcs (correct, not fast); AUTO does not pick the loop here
+def test_lds_skewed_graph():
+    # hubs: a group of 16 lanes walks a hub's arcs (the row-offset layout:
+    # degrees above 16 are not padded); AUTO picks the loop here too
     g = gg.rmat(11, 8, gseed=41, pseed=42, wseed=43, name="rmat11")
     check(g, [int(x) for x in gg.pick_sources(g, 44, 3)])
+    G = gr.Graph.from_csr(g)
+    try:
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        st = gr.gr_sssp_ex(G.handle, 7, d)
+        torch.cuda.synchronize()
+        assert st["loop"] == gr.GR_LOOP_LDS
+        np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), oracle.dijkstra(g, 7))
+    finally:
+        G.close()
 
 
 def test_lds_degenerate_graphs():
