@@ -4,11 +4,12 @@
 // Graphs of a few thousand vertices, such as small meshes, take one round per
 // hop of their diameter, and each round of the other loops costs a kernel
 // launch or a grid-wide barrier plus round trips to the L2.  Here one
-// workgroup of 1024 threads copies the distances, row offsets and arcs into
-// LDS (arcs packed as a 16-bit head and a 16-bit weight), keeps the frontier
-// as a list of vertex ids in LDS, and runs the bulk-synchronous rounds with
+// workgroup of 1024 threads copies the distances and arcs into LDS (arcs
+// packed as a 16-bit head and a 16-bit weight, either padded to a power-of-two
+// number of slots per vertex or behind row offsets), keeps the frontier as a
+// list of vertex ids in LDS, and runs the bulk-synchronous rounds with
 // workgroup barriers and LDS atomics: a round is well under a microsecond.
-// A batch of sources runs one such workgroup per source in one launch.
+// A batch of queries runs one such workgroup per query in one launch.
 //
 // Round r: every vertex u of list r is expanded by a group of lanes: for each
 // arc (u, v, w), new = dist[u] + w, offered to v with an LDS atomic min.
@@ -21,8 +22,8 @@
 // lands before is read by it.  dist[u] is thus read when u is expanded, so
 // an improvement found earlier in the same round is used (as the other
 // loops read dist[u] when staging their frontier).  One workgroup barrier
-// ends each round; the loop ends when a round appends nothing, at the same
-// fixed point.  Distances take 31 bits, which every graph that fits
+// ends each round (with row offsets, a second one precedes the hubs' arcs);
+// the loop ends when a round appends nothing, at the same fixed point.  Distances take 31 bits, which every graph that fits
 // allows (gr_lds.h).
 
 #include "gr_lds.h"
