@@ -181,7 +181,10 @@ typedef enum {
                                copies the distances, row offsets and arcs (a 16-bit head and
                                a 16-bit weight each) into LDS and runs every round there.
                                Graphs with 3 n + m <= 39,900 or so (about 156 KiB of LDS;
-                               a 64 x 64 grid fits) and, for SSSP, uint32 weights below
+                               a 75 x 75 grid fits), or, with uint32 weights below 65,536
+                               and maximum out-degree D <= 16, (2 + P) n <= 39,900 or so,
+                               P the power of two >= D (arcs padded to P slots per vertex:
+                               an 81 x 81 grid fits); and, for SSSP, uint32 weights below
                                65,536; else GR_ERR_INVALID_ARG.  Push only (direction
                                PULL / ALTERNATE and an explicit delta are
                                GR_ERR_INVALID_ARG; layout, filter and relax_filter are
@@ -389,8 +392,9 @@ gr_status gr_sssp_batch_ex(const gr_graph *g, const int32_t *srcs, int32_t k, vo
  * done.  Workspace: 26 bytes per vertex summed over the queries (two union
  * queues) + 2 bytes per vertex of each query (frontier marks), stream-ordered
  * from the device pool and returned before the call ends.  When every
- * graph's AUTO loop is the single-workgroup loop (GR_LOOP_LDS), each query
- * runs that loop in a workgroup of its own, all in one launch, with no
+ * graph's AUTO loop is the single-workgroup loop (GR_LOOP_LDS), and all fit
+ * one arc layout (row offsets, or arcs padded to the same slot count), each
+ * query runs that loop in a workgroup of its own, all in one launch, with no
  * workspace (stats->replays = 0).
  */
 gr_status gr_sssp_multi(const gr_graph *const *graphs, const int32_t *srcs, int32_t k, void *const *dist_out,
@@ -431,7 +435,7 @@ typedef struct {
  * fit hbm_budget_bytes next to every query already admitted.  A query is
  * complete when a chunk ends with its frontier empty; its distances are then
  * final in its dist_out.  Queries on graphs whose AUTO loop is the single-
- * workgroup loop (GR_LOOP_LDS) take no slot: an executor takes up to 64 of
+ * workgroup loop (GR_LOOP_LDS) and that fit its row-offset layout take no slot: an executor takes up to 64 of
  * them from anywhere in the FIFO (they hold nothing the head waits for) and
  * runs them as one launch, one workgroup per query, on a stream of its own;
  * batch_size is then that launch's query count.  cfg may be NULL. */

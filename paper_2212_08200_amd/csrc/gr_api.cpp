@@ -366,7 +366,10 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
     // Graphs that fit one workgroup's LDS: the single-workgroup loop (a round
     // is a workgroup barrier: grid 64^2 0.09 ms against 0.85 asynchronous).
     g->lds_fit = lds_fits(n, m);
-    if (g->lds_fit && wt == GR_W_U32) {
+    int32_t ell_lg = 0;
+    while (ell_lg < kLdsEllMaxLg && (1 << ell_lg) < g->max_degree) ++ell_lg;
+    const bool ell_shape = (1 << ell_lg) >= g->max_degree && lds_ell_fits(n, ell_lg);
+    if ((g->lds_fit || ell_shape) && wt == GR_W_U32) {
         std::vector<uint2> h((size_t)std::max(m, 1));
         BUILD_TRY(hipMemcpyAsync(h.data(), g->d_adj, sizeof(uint2) * (size_t)m, hipMemcpyDeviceToHost, st),
                   "copy arcs");
@@ -375,10 +378,11 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
         for (int32_t e = 0; e < m; ++e) wmax = std::max(wmax, h[(size_t)e].y);
         g->lds_w16 = wmax < 65536u;
         // padded layout: every vertex's arcs in 2^lg slots (lg from the
-        // maximum degree), so a lane finds its arc without the row offsets
-        int32_t lg = 0;
-        while (lg < kLdsEllMaxLg && (1 << lg) < g->max_degree) ++lg;
-        if (g->lds_w16 && (1 << lg) >= g->max_degree && lds_ell_fits(n, lg)) {
+        // maximum degree), so a lane finds its arc without the row offsets;
+        // it also fits meshes a little larger than the row-offset layout
+        // does (no offsets: a 81 x 81 grid against 75 x 75)
+        const int32_t lg = ell_lg;
+        if (g->lds_w16 && ell_shape) {
             std::vector<uint32_t> ell((size_t)n << lg, kLdsNoArc);
             for (int32_t v = 0; v < n; ++v)
                 for (int32_t e = g->h_ro[v]; e < g->h_ro[v + 1]; ++e)
@@ -393,7 +397,7 @@ static gr_status graph_build(gr_graph *g, int32_t n, int32_t m, const int32_t *r
     // Also on skewed ones: a hub's arcs take many passes of one group of
     // lanes, but R-MAT graphs of 1-4 K vertices still run 2.3-3.2x faster
     // than with the queued loop (scale 10 to 12: 0.08-0.14 ms against 0.26-0.32).
-    if (g->lds_fit && g->lds_w16) g->auto_loop = GR_LOOP_LDS;
+    if ((g->lds_fit || g->d_ell) && g->lds_w16) g->auto_loop = GR_LOOP_LDS;
     // Large skewed graphs: few, heavy rounds, where the host-driven loop's
     // push grid of 16 blocks per CU beats the step kernel (R-MAT 22: 3.48 ms
     // against 3.63); smaller ones keep the queued loop (no host round trip
@@ -583,7 +587,7 @@ static gr_status check_opts(const gr_graph *g, const gr_sssp_opts *o, RunCfg *rc
         if (!(x > 0.f && x <= FLT_MAX)) return fail(GR_ERR_INVALID_ARG, "delta must be a positive finite binary32");
     }
     if (rc->loop == GR_LOOP_LDS) {
-        if (!g->lds_fit)
+        if (!g->lds_fit && !g->d_ell)
             return fail(GR_ERR_INVALID_ARG, "the single-workgroup loop needs a graph that fits one workgroup's LDS "
                                             "(n = %d, m = %d do not)", g->plain.n, g->plain.m);
         if (rc->direction == GR_DIR_PULL || rc->direction == GR_DIR_ALTERNATE)
@@ -977,7 +981,7 @@ static gr_status run_lds(const gr_graph *g, int32_t src, uint32_t *dist, hipStre
                          gr_sssp_stats *stats) {
     const DevGraph &dg = g->plain;
     const int wt = rc.dg->wt == 2 ? 2 : dg.wt;
-    if (!g->lds_fit) return fail(GR_ERR_INVALID_ARG, "the graph does not fit the single-workgroup loop");
+    if (!g->lds_fit && !g->d_ell) return fail(GR_ERR_INVALID_ARG, "the graph does not fit the single-workgroup loop");
     if (wt != 2 && !(dg.wt == GR_W_U32 && g->lds_w16))
         return fail(GR_ERR_INVALID_ARG, "the single-workgroup loop packs weights in 16 bits: uint32 weights "
                                         "below 65,536 only");
@@ -1263,7 +1267,7 @@ extern "C" gr_status gr_bfs_ex(const gr_graph *g, int32_t src, void *depth_out, 
     int loop = rc.loop;
     if (loop == GR_LOOP_AUTO) {
         const bool push_only = !(rc.direction == GR_DIR_PULL || rc.direction == GR_DIR_ALTERNATE || rc.delta);
-        loop = g->lds_fit && push_only                ? GR_LOOP_LDS
+        loop = (g->lds_fit || g->d_ell) && push_only ? GR_LOOP_LDS
                : g->max_degree > kSmallMaxDegree ? GR_LOOP_HOST
                                                  : GR_LOOP_QUEUED;
     }
@@ -1561,7 +1565,15 @@ extern "C" gr_status gr_sssp_multi(const gr_graph *const *graphs, const int32_t 
     hipStream_t st = static_cast<hipStream_t>(stream);
     // every graph's default is the single-workgroup loop: one workgroup per query
     bool all_lds = k <= kLdsMaxBatch;
-    for (int32_t i = 0; i < k && all_lds; ++i) all_lds = graphs[i]->auto_loop == GR_LOOP_LDS;
+    // (one launch takes one arc layout: every graph fits the row-offset one,
+    // or all have the padded one with the same slot count)
+    bool all_csr = true, all_ell = true;
+    for (int32_t i = 0; i < k && all_lds; ++i) {
+        all_lds = graphs[i]->auto_loop == GR_LOOP_LDS;
+        all_csr = all_csr && graphs[i]->lds_fit;
+        all_ell = all_ell && graphs[i]->d_ell && graphs[i]->ell_lg == graphs[0]->ell_lg;
+    }
+    all_lds = all_lds && (all_csr || all_ell);
     if (all_lds) {
         std::vector<uint32_t *> rows((size_t)k);
         for (int32_t i = 0; i < k; ++i) rows[i] = static_cast<uint32_t *>(dist_out[i]);
@@ -2077,7 +2089,8 @@ extern "C" gr_status gr_serve_submit(gr_server *s, int32_t graph_id, int32_t src
     tk.res.t_submit_ns = t;
     // queries on graphs that run the single-workgroup loop by default are
     // run outside the executors' sessions
-    s->policy->push(SchedQuery{id, graph_id, src, dist_out, t, g->auto_loop == GR_LOOP_LDS});
+    // (those whose graph fits the row-offset layout, which any mix of them shares)
+    s->policy->push(SchedQuery{id, graph_id, src, dist_out, t, g->auto_loop == GR_LOOP_LDS && g->lds_fit});
     s->cv.notify_all();
     *ticket = id;
     return GR_OK;
@@ -2306,7 +2319,7 @@ extern "C" gr_status gr_graph_tune(gr_graph *g, const int32_t *srcs, int32_t nsr
         std::vector<int32_t> loops = coop ? std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_PERSISTENT,
                                                                  GR_LOOP_ASYNC}
                                           : std::vector<int32_t>{GR_LOOP_HOST, GR_LOOP_QUEUED, GR_LOOP_ASYNC};
-        if (g->lds_fit && g->lds_w16) loops.push_back(GR_LOOP_LDS);
+        if ((g->lds_fit || g->d_ell) && g->lds_w16) loops.push_back(GR_LOOP_LDS);
         knobs.push_back({1, loops});
     }
     knobs.push_back({2, {8, 64, 512}});

@@ -52,7 +52,8 @@ inline bool lds_ell_fits(int32_t n, int lg) {
 
 // wt: 0 uint32 weights (every weight below 2^16), 2 unit steps, for every
 // job.  jobs: host array of k jobs, 1 <= k <= kLdsMaxBatch, each graph
-// fitting (lds_fits); workgroup b copies job b's graph into its LDS, writes
+// fitting the layout the launch takes (the padded one when every job has it
+// with the same ell_lg, else lds_fits); workgroup b copies job b's graph into its LDS, writes
 // its dist row and stat[4 b .. 4 b + 3] (device memory or pinned host
 // memory: written with system-scope stores).
 hipError_t launch_lds(const LdsJob *jobs, int32_t k, int wt, int64_t max_rounds, unsigned long long *stat,

@@ -254,8 +254,8 @@ hipError_t launch_lds(const LdsJob *jobs, int32_t k, int wt, int64_t max_rounds,
     int32_t lg = 0;
     for (int32_t b = 0; b < k; ++b) {
         const LdsJob &j = jobs[b];
-        if (!lds_fits(j.n, j.m) || j.src < 0 || j.src >= j.n || !j.ro || !j.dist || (j.m > 0 && !j.adj))
-            return hipErrorInvalidValue;
+        const bool fits = lds_fits(j.n, j.m) || (j.ell && lds_ell_fits(j.n, j.ell_lg));
+        if (!fits || j.src < 0 || j.src >= j.n || !j.ro || !j.dist || (j.m > 0 && !j.adj)) return hipErrorInvalidValue;
         a.job[b] = j;
         while (lg < 4 && ((int64_t)j.n << lg) < j.m) ++lg;
     }
@@ -263,6 +263,9 @@ hipError_t launch_lds(const LdsJob *jobs, int32_t k, int wt, int64_t max_rounds,
     bool ell = true;
     for (int32_t b = 0; b < k && ell; ++b)
         ell = jobs[b].ell && jobs[b].ell_lg == jobs[0].ell_lg && lds_ell_fits(jobs[b].n, jobs[b].ell_lg);
+    // the row-offset layout needs every graph to fit it
+    for (int32_t b = 0; b < k && !ell; ++b)
+        if (!lds_fits(jobs[b].n, jobs[b].m)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)k), block(kLdsThreads);
     if (ell) {
         if (wt == 2) launch_lg<2, true>(jobs[0].ell_lg, grid, block, st, a);

@@ -119,21 +119,68 @@ def test_lds_long_path_distances():
 
 
 def test_lds_size_limit():
-    # 3 n + m + 1 words must fit 39,936: a 75 x 75 grid does, 76 x 76 does not
-    fits, over = gg.grid(75, 7, name="grid75"), gg.grid(76, 7, name="grid76")
-    check(fits, [0, fits.n - 1], bfs=False)
-    G = gr.Graph.from_csr(over)
+    # row offsets: 3 n + m + 1 words must fit 39,936 (a 75 x 75 grid does);
+    # padded arcs: 6 n words for a grid (4 slots per vertex), so 76 x 76 to
+    # 81 x 81 fit only that way (uint32 weights: the padded copy holds
+    # 16-bit weights), and 82 x 82 fits neither
+    check(gg.grid(75, 7, name="grid75"), [0, 75 * 75 - 1], bfs=False)
+    for side in (76, 81):
+        g = gg.grid(side, 7, name="grid%d" % side)
+        check(g, [0, g.n - 1, 1234])
+        G = gr.Graph.from_csr(g)
+        try:
+            d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            st = gr.gr_sssp_ex(G.handle, 5, d)
+            torch.cuda.synchronize()
+            assert st["loop"] == gr.GR_LOOP_LDS
+            np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), oracle.dijkstra(g, 5))
+        finally:
+            G.close()
+    for over in (gg.grid(82, 7, name="grid82"), gg.grid(76, 7, wtype=gg.W_F32, name="grid76f")):
+        G = gr.Graph.from_csr(over)
+        try:
+            with pytest.raises(gr.GrError) as ei:
+                run(G, over.n, 0, bfs=True)
+            assert ei.value.status == gr.GR_ERR_INVALID_ARG
+            d = torch.empty(over.n, dtype=torch.int32, device="cuda")
+            st = gr.gr_sssp_ex(G.handle, 0, d)  # AUTO takes another loop
+            torch.cuda.synchronize()
+            assert st["loop"] != gr.GR_LOOP_LDS
+            np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), oracle.dijkstra(over, 0))
+        finally:
+            G.close()
+
+
+def test_lds_padded_only_graph_in_batches():
+    # a graph that fits only the padded layout: same-graph batches use it;
+    # multi-graph launches use it when every graph has the same slot count,
+    # and fall back to the multi-query engine when the layouts differ
+    g76, g64 = gg.grid(76, 7, name="grid76"), gg.workload("grid64")[0]
+    road = gg.grid(60, 5, whi=1000, shortcuts=4, sseed=9, name="road60")  # 8 slots
+    Gs = [gr.Graph.from_csr(x) for x in (g76, g64, road)]
     try:
-        with pytest.raises(gr.GrError) as ei:
-            run(G, over.n, 0)
-        assert ei.value.status == gr.GR_ERR_INVALID_ARG
-        d = torch.empty(over.n, dtype=torch.int32, device="cuda")
-        st = gr.gr_sssp_ex(G.handle, 0, d)  # AUTO takes another loop
+        srcs = np.asarray(gg.pick_sources(g76, 61, 8), np.int32)
+        out = torch.full((8, g76.n), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+        say("lds batch grid76 k=8")
+        st = gr.gr_sssp_batch_ex(Gs[0].handle, srcs, out)
         torch.cuda.synchronize()
-        assert st["loop"] != gr.GR_LOOP_LDS
-        np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), oracle.dijkstra(over, 0))
+        rows = out.cpu().numpy().view(np.uint32)
+        for i, s in enumerate(srcs):
+            np.testing.assert_array_equal(rows[i], oracle.dijkstra(g76, int(s)))
+        assert st["replays"] == 0
+        for members, lds in (((0, 1), True), ((0, 2), False)):
+            gs = [(g76, g64, road)[i] for i in members]
+            ss = [3, 7]
+            outs = [torch.full((x.n,), 0x5A5A5A5A, dtype=torch.int32, device="cuda") for x in gs]
+            say("lds multi %s" % [x.name for x in gs])
+            st = gr.gr_sssp_multi([Gs[i].handle for i in members], ss, outs)
+            torch.cuda.synchronize()
+            for x, s, o in zip(gs, ss, outs):
+                np.testing.assert_array_equal(o.cpu().numpy().view(np.uint32), oracle.dijkstra(x, s))
+            assert (st["replays"] == 0) == lds
     finally:
-        G.close()
+        for G in Gs:
+            G.close()
 
 
 def test_lds_is_the_small_mesh_default_and_errors():
